@@ -1,0 +1,23 @@
+"""CPU oracle for the MeshSplats hot path (arXiv 2502.07754).
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product imports, links or runs this
+package; only the tests, the smoke check and the CPU-baseline leg of the
+benchmark do. It shares no code with the HIP path: the two meet only through
+the seeded inputs of `paper_2502_07754_amd.scenes`, which hold none of the
+method's arithmetic.
+
+Every function is a plain, slow float64 numpy statement of what the paper
+defines (section / equation cited in each docstring) or, where the paper is
+silent, of the reading recorded with it.
+
+Modules:
+  convert   Gaussian -> triangle fan (flat Gaussians section, Eq. 2d_scaledrot
+            and the vertex equation; opacity fall-off paragraph)
+  render    brute-force per-pixel ray/triangle intersection, full depth sort,
+            front-to-back compositing, and its adjoint (rendering section)
+  binning   float32 statement of the tile-binning formula used to check tile
+            lists and sort order bit for bit
+  sh        real spherical harmonics up to degree 3
+  finetune  loss, Adam step and pruning (fine-tuning section)
+  mlp       refiner MLP with bfloat16 rounding points
+"""

@@ -1,0 +1,148 @@
+"""Seeded synthetic inputs: Gaussian scenes and pinhole cameras.
+
+This module only draws random numbers and builds camera poses. It holds none
+of the method's arithmetic (no conversion, projection, binning or
+compositing), so both the HIP path and the CPU oracle can take their inputs
+from it.
+
+Every array is produced in float64 and rounded once to float32; callers that
+need float64 (the oracle) promote the float32 values back, so both sides see
+the same numbers.
+
+Layouts are structure-of-arrays with the component axis first:
+  mean [3][N], scale [3][N] (linear, already activated), quat [4][N] as
+  (w, x, y, z), opacity [N], rgb [3][N], sh [48][N] (basis-major,
+  channel-minor: row = 3*basis + channel).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Gaussians:
+    mean: np.ndarray      # [3][N] f32
+    scale: np.ndarray     # [3][N] f32, linear
+    quat: np.ndarray      # [4][N] f32, (w, x, y, z), unit length
+    opacity: np.ndarray   # [N] f32 in (0, 1)
+    rgb: np.ndarray       # [3][N] f32 in [0, 1]
+    sh: np.ndarray | None = None  # [48][N] f32 or None
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+
+@dataclasses.dataclass
+class Camera:
+    """OpenCV pinhole: x right, y down, z forward; pixel (i, j) centre at (i+0.5, j+0.5)."""
+    world_to_cam: np.ndarray  # [3][4] f32, rows (R | t)
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    znear: float = 0.01
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def gaussians(n: int, seed: int, scale_lo: float, scale_hi: float, flat: bool,
+              sh: bool = False) -> Gaussians:
+    """Draws n Gaussians in a fixed order from default_rng(seed).
+
+    Order: means U(-1, 1) (n,3); log-scales U(ln lo, ln hi) (n,3) -> exp, with
+    the third column set to 0 for flat Gaussians; quaternions N(0, 1) (n,4)
+    normalised, (w, x, y, z); opacity sigmoid(N(0, 1)); rgb U(0, 1) (n,3);
+    optionally SH coefficients N(0, 0.1^2) (n,16,3).
+    """
+    rng = np.random.default_rng(seed)
+    mean = rng.uniform(-1.0, 1.0, size=(n, 3))
+    logs = rng.uniform(math.log(scale_lo), math.log(scale_hi), size=(n, 3))
+    scale = np.exp(logs)
+    if flat:
+        scale[:, 2] = 0.0
+    q = rng.standard_normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = 1.0 / (1.0 + np.exp(-rng.standard_normal(size=n)))
+    rgb = rng.uniform(0.0, 1.0, size=(n, 3))
+    shc = None
+    if sh:
+        shc = rng.normal(0.0, 0.1, size=(n, 16, 3)).reshape(n, 48)
+    return Gaussians(mean=_f32(mean.T), scale=_f32(scale.T), quat=_f32(q.T),
+                     opacity=_f32(op), rgb=_f32(rgb.T),
+                     sh=None if shc is None else _f32(shc.T))
+
+
+def look_at(center, width: int, height: int, fov_y_deg: float = 60.0,
+            znear: float = 0.01) -> Camera:
+    """Camera at `center` looking at the origin with world up +y.
+
+    forward f = -c/|c|, right = normalize(f x up), down = f x right; focal
+    length from the vertical field of view; principal point at the image centre.
+    """
+    c = np.asarray(center, dtype=np.float64)
+    f = -c / np.linalg.norm(c)
+    up = np.array([0.0, 1.0, 0.0])
+    r = np.cross(f, up)
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])            # rows: camera axes in world coordinates
+    t = -R @ c
+    w2c = np.concatenate([R, t[:, None]], axis=1)
+    fy = (height / 2.0) / math.tan(math.radians(fov_y_deg) / 2.0)
+    return Camera(world_to_cam=_f32(w2c), fx=float(np.float32(fy)), fy=float(np.float32(fy)),
+                  cx=float(np.float32(width / 2.0)), cy=float(np.float32(height / 2.0)),
+                  width=int(width), height=int(height), znear=float(np.float32(znear)))
+
+
+def ring_cameras(n_views: int, width: int, height: int, radius: float = 3.0,
+                 elevation_deg: float = 0.0) -> list[Camera]:
+    """Views on a horizontal ring: c_v = r (cos e sin phi, sin e, cos e cos phi), phi = 2 pi v / V."""
+    cams = []
+    e = math.radians(elevation_deg)
+    for v in range(n_views):
+        phi = 2.0 * math.pi * v / n_views
+        c = radius * np.array([math.cos(e) * math.sin(phi), math.sin(e), math.cos(e) * math.cos(phi)])
+        cams.append(look_at(c, width, height))
+    return cams
+
+
+def upstream_grad(n_views: int, height: int, width: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """dL/dimage, N(0, 1) * scale, layout [V][4][H][W] float32."""
+    rng = np.random.default_rng(seed)
+    return _f32(rng.standard_normal(size=(n_views, 4, height, width)) * scale)
+
+
+# ---------------------------------------------------------------------------
+# The five workload shapes of the hot path (sizes as stated with the metric).
+# ---------------------------------------------------------------------------
+
+def config1(seed: int = 0):
+    """1,000 flat Gaussians, K=8, sigma=2, one 128x128 view at distance 3."""
+    g = gaussians(1000, seed, 0.01, 0.1, flat=True)
+    return g, ring_cameras(1, 128, 128), dict(K=8, sigma=2.0)
+
+
+def config2(seed: int = 0):
+    """100k 3D Gaussians (scales log-U[0.005, 0.05]), K=8, one 800x800 view."""
+    g = gaussians(100_000, seed, 0.005, 0.05, flat=False)
+    return g, ring_cameras(1, 800, 800), dict(K=8, sigma=2.0)
+
+
+def config3(seed: int = 0, n: int = 500_000, views: int = 8, width: int = 1920, height: int = 1080):
+    """500k flat Gaussians, K=16, SH degree 3, eight 1920x1080 ring views."""
+    g = gaussians(n, seed, 0.01, 0.1, flat=True, sh=True)
+    return g, ring_cameras(views, width, height), dict(K=16, sigma=2.0)
+
+
+def config5(seed: int = 0, n: int = 3_000_000, views: int = 16, width: int = 1920, height: int = 1080):
+    """3M flat Gaussians, K=8, sixteen 1920x1080 ring views."""
+    g = gaussians(n, seed, 0.01, 0.1, flat=True)
+    return g, ring_cameras(views, width, height), dict(K=8, sigma=2.0)
