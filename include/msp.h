@@ -1,0 +1,192 @@
+/*
+ * msp.h — C ABI of the MeshSplats hot path for AMD Instinct MI355X (gfx950).
+ *
+ * MeshSplats (arXiv 2502.07754) turns trained Gaussians into a soup of
+ * semi-transparent triangle fans and renders that soup by depth-ordered,
+ * front-to-back alpha compositing, forward and backward, so the faces can be
+ * fine-tuned. This library exposes exactly those steps:
+ *
+ *   msp_convert          Gaussians -> fans (flat-Gaussian transformation
+ *                        section: Eq. 2d_scaledrot, the vertex equation, the
+ *                        fan construction and the opacity fall-off paragraph)
+ *   msp_render           faces x cameras -> RGBA images (rendering section:
+ *                        MVP transform, depth-peeled layers, interpolated
+ *                        vertex attributes, blending through alpha)
+ *   msp_render_backward  dL/dimage -> dL/d(vertex position, opacity, colour)
+ *                        (fine-tuning section: the gradients its optimiser
+ *                        consumes)
+ *
+ * Conventions shared by every call
+ *   - All array arguments are DEVICE pointers owned by the caller unless a
+ *     comment says "host". Arrays are structure-of-arrays, component axis
+ *     first ([3][n] means x[0..n), y[0..n), z[0..n) back to back), float32 or
+ *     int32, and must be 4-byte aligned (256-byte alignment is recommended for
+ *     full-rate loads).
+ *   - Work is enqueued on the context's HIP stream; calls return once the work
+ *     is enqueued unless a comment says the call synchronises.
+ *   - Every call returns an msp_status (0 = success, negative = error); no
+ *     exception or abort crosses the ABI. msp_last_error() returns a
+ *     NUL-terminated message for the last failure on that context. A context
+ *     must not be used by two host threads at once.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum msp_status {
+  MSP_OK = 0,
+  MSP_EINVAL = -1,     /* an argument is out of range or a required pointer is NULL */
+  MSP_ENOMEM = -2,     /* a device allocation of library-owned scratch failed */
+  MSP_EHIP = -3,       /* a HIP runtime call failed (message names it) */
+  MSP_EOVERFLOW = -4,  /* a bounded buffer was too small and the retry failed too */
+  MSP_ESTALE = -5      /* a render state was used with faces other than the ones it was made from */
+} msp_status;
+
+typedef struct msp_ctx msp_ctx;      /* library-owned: stream binding, kernels, autotune cache */
+typedef struct msp_state msp_state;  /* library-owned: tile lists and per-pixel counts of one render */
+
+/* Gaussians (the input of the conversion). n may be 0. */
+typedef struct msp_gaussians {
+  int64_t n;
+  const float* mean;     /* [3][n] centres */
+  const float* scale;    /* [3][n] linear (already exponentiated) scales, >= 0 */
+  const float* quat;     /* [4][n] rotation as (w, x, y, z); normalised inside */
+  const float* opacity;  /* [n] opacity in [0, 1] */
+  const float* rgb;      /* [3][n] colour */
+  const float* sh;       /* [48][n] degree-3 SH coefficients (row 3*basis+channel) or NULL */
+} msp_gaussians;
+
+/* Triangle soup: per-vertex position/opacity/colour, per-face vertex ids.
+ * Vertex and face ids are int32, so n_verts and n_faces must be < 2^31. */
+typedef struct msp_faces {
+  int64_t n_verts;
+  int64_t n_faces;
+  float* pos;        /* [3][n_verts] world positions */
+  float* opacity;    /* [n_verts] */
+  float* rgb;        /* [3][n_verts] */
+  float* sh;         /* [48][n_faces] or NULL: per-face SH colour instead of rgb */
+  int32_t* idx;      /* [3][n_faces] vertex ids */
+  int32_t* gid;      /* [n_faces] id of the Gaussian a face came from (may be NULL for render) */
+} msp_faces;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward). Camera coordinates
+ * are x_c = W[0..2] . x + W[3] (row 0), etc. for the 3x4 row-major matrix W;
+ * pixel (i, j) has its centre at (i + 1/2, j + 1/2) and u = fx x_c / z_c + cx. */
+typedef struct msp_camera {
+  float world_to_cam[12];
+  float fx, fy, cx, cy;
+  float znear;           /* faces with any corner at z_c <= znear are not drawn */
+  int32_t width, height; /* all views of one render share width and height */
+} msp_camera;
+
+enum { MSP_FAN_FLAT = 0 };                       /* conversion modes */
+enum { MSP_COLOR_RGB = 0, MSP_COLOR_SH3 = 1 };   /* colour source of a render */
+
+typedef struct msp_render_opts {
+  int32_t tile_w, tile_h; /* binning tile in pixels; multiples of 8 in [8, 64]; 0 = autotuned/default */
+  int32_t kbuf;           /* depth of the per-pixel ordering buffer: 8 or 16; 0 = default */
+  int32_t color_mode;     /* MSP_COLOR_RGB or MSP_COLOR_SH3 */
+  float t_eps;            /* a pixel stops once its transmittance falls below t_eps (>= 0) */
+  float bg[3];            /* background colour */
+} msp_render_opts;
+
+/* Gradients, caller-owned, OVERWRITTEN by msp_render_backward (not accumulated).
+ * Any pointer may be NULL to skip that output. */
+typedef struct msp_face_grads {
+  float* dpos;      /* [3][n_verts] */
+  float* dopacity;  /* [n_verts] */
+  float* drgb;      /* [3][n_verts] (RGB mode) */
+  float* dsh;       /* [48][n_faces] (SH mode) */
+} msp_face_grads;
+
+typedef struct msp_render_stats {
+  int64_t n_views, width, height, tile_w, tile_h;
+  int64_t entries;          /* (face, tile) pairs over all views */
+  int64_t max_tile_entries; /* longest tile list */
+  int64_t fragments;        /* fragments composited (before early stop) over all views */
+  int64_t restarts;         /* ordering-buffer overflows resolved by re-scanning a tile list */
+} msp_render_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` bound to `hip_stream` (a hipStream_t
+ * cast to void*, or NULL for the default stream). The stream is borrowed. */
+msp_status msp_create(int device, void* hip_stream, msp_ctx** out);
+msp_status msp_destroy(msp_ctx* ctx);
+msp_status msp_set_stream(msp_ctx* ctx, void* hip_stream);
+const char* msp_last_error(const msp_ctx* ctx);
+/* Library version as major*10000 + minor*100 + patch. */
+int msp_version(void);
+
+/* ---- conversion --------------------------------------------------------- */
+
+/* Host-only sizing: n_verts = n (K + 1), n_faces = n K for MSP_FAN_FLAT.
+ * EINVAL if K is outside [3, 64], n < 0 or mode is unknown. */
+msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_t* n_faces);
+
+/* Gaussian -> fan conversion (flat-Gaussian transformation section).
+ * Per Gaussian g with unit rotation R (columns r1..r3): the two largest scales
+ * (ties to the lower index), in index order a < b, give A = sigma s_a r_a and
+ * B = sigma s_b r_b (Eq. 2d_scaledrot with scale_mul = sigma and linear scales);
+ * vertex g(K+1) is the mean, vertex g(K+1)+1+k is m + cos(t_k) A + sin(t_k) B
+ * with t_k = -pi + 2 pi k / K (the vertex equation); face gK+k is (centre,
+ * boundary k, boundary (k+1) mod K); every vertex takes the Gaussian's colour;
+ * opacity is the Gaussian's at the centre and opac_mul times it on the
+ * boundary. When g->sh is non-NULL each face gets its Gaussian's 48 SH
+ * coefficients in out->sh. `out` arrays must be sized by msp_convert_size.
+ * EINVAL: sigma not finite and > 0, opac_mul not finite, NULL arrays with n > 0,
+ * out sizes that differ from msp_convert_size, or out->sh NULL while g->sh is set. */
+msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                       int mode, msp_faces* out);
+
+/* ---- rendering ---------------------------------------------------------- */
+
+msp_status msp_state_create(msp_ctx* ctx, msp_state** out);
+msp_status msp_state_free(msp_ctx* ctx, msp_state* st);
+
+/* Renders n_views views of the face soup into img [n_views][4][H][W] (RGBA
+ * planes, float32). `cams` is HOST memory (n_views entries, copied).
+ * Per pixel: every face (all corners in front of znear) whose triangle
+ * contains the pixel centre contributes one fragment with perspective-correct
+ * barycentrics b, alpha = clamp(b . o, 0, 1) and colour b . c (RGB mode) or the
+ * face's SH colour for that view (SH mode). Fragments are composited front to
+ * back in exact (depth, face id) order: C += T a c, T *= 1 - a, stopping once
+ * T < t_eps; RGB = C + T bg and A = 1 - T. `st` keeps the tile lists and
+ * per-pixel fragment counts for msp_render_backward; the faces must stay
+ * unchanged until that call. Synchronises the stream once (to size the tile
+ * lists). EINVAL: n_views < 1, sizes outside [1, 16384], cameras with
+ * different sizes, non-finite camera values, bad tiles, or SH mode without
+ * f->sh. */
+msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                      const msp_render_opts* opts, float* img, msp_state* st);
+
+/* Adjoint of the last msp_render made with `st`. dimg is [n_views][4][H][W]
+ * (dL/dRGBA). Fragment lists are recomputed, not stored. The derivative
+ * freezes which fragments cover each pixel and their order (no edge or
+ * visibility terms) and is exact otherwise; the opacity clamp passes the
+ * gradient only where 0 < b . o < 1. Synchronises the stream once (to size the
+ * recomputed lists). ESTALE if `f` is not the soup the state was rendered with. */
+msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
+                               msp_face_grads* grads);
+
+/* Counters of the last render on `st` (synchronises). */
+msp_status msp_state_stats(msp_ctx* ctx, msp_state* st, msp_render_stats* out);
+
+/* Debug copies (synchronise). Tile lists of view `view`: offsets (HOST,
+ * n_tiles + 1 int64) and sorted keys (HOST, entries uint64; key = (bits of the
+ * face's nearest camera depth as float32) << 32 | face id). Pass keys = NULL
+ * to read only the offsets. n_tiles = ceil(W/tile_w) ceil(H/tile_h). */
+msp_status msp_debug_tiles(msp_ctx* ctx, msp_state* st, int view, int64_t* offsets, uint64_t* keys);
+/* Per-pixel count of composited fragments, HOST int32 [n_views][H][W]. */
+msp_status msp_debug_nfrag(msp_ctx* ctx, msp_state* st, int32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSP_H */

@@ -1,0 +1,228 @@
+"""MeshSplats hot path for AMD Instinct MI355X (gfx950).
+
+Thin Python layer over libmsp.so (include/msp.h): torch tensors supply device
+memory and the stream; every step of conversion, binning, sorting,
+compositing and the adjoint runs in the library's HIP kernels.
+
+    faces = convert(gaussians, K=8, sigma=2.0)
+    img, state = render(faces, cameras)
+    grads = render_backward(state, faces, dimg)
+    img = MeshRender.apply(pos, opacity, rgb, faces, cameras, options)  # autograd
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+from . import _lib
+from ._lib import MspError
+
+__all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
+           "camera_struct", "load_library"]
+
+MSP_COLOR_RGB = 0
+MSP_COLOR_SH3 = 1
+
+
+def load_library():
+    return _lib.load()
+
+
+def _dev_ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name):
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ctx(t):
+    return _lib.Context.get(t.device.index if t.device.index is not None else 0)
+
+
+def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2) -> dict:
+    """Gaussian -> triangle fans (msp_convert). `g` holds GPU float32 tensors
+    mean [3,N], scale [3,N], quat [4,N], opacity [N], rgb [3,N] and optionally sh [48,N]."""
+    import torch
+    mean = _need(g["mean"], torch.float32, "mean")
+    ctx = _ctx(mean)
+    ctx.bind_stream()
+    n = mean.shape[1]
+    nv, nf = C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.msp_convert_size(n, K, 0, C.byref(nv), C.byref(nf)), "msp_convert_size")
+    dev = mean.device
+    sh = g.get("sh")
+    out = dict(pos=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               opacity=torch.empty((nv.value,), dtype=torch.float32, device=dev),
+               rgb=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               idx=torch.empty((3, nf.value), dtype=torch.int32, device=dev),
+               gid=torch.empty((nf.value,), dtype=torch.int32, device=dev),
+               sh=None if sh is None else torch.empty((48, nf.value), dtype=torch.float32, device=dev))
+    G = _lib.Gaussians(n, _dev_ptr(mean), _dev_ptr(_need(g["scale"], torch.float32, "scale")),
+                       _dev_ptr(_need(g["quat"], torch.float32, "quat")),
+                       _dev_ptr(_need(g["opacity"], torch.float32, "opacity")),
+                       _dev_ptr(_need(g["rgb"], torch.float32, "rgb")),
+                       None if sh is None else _dev_ptr(_need(sh, torch.float32, "sh")))
+    Fc = _faces_struct(out)
+    ctx.check(ctx.lib.msp_convert(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), 0, C.byref(Fc)),
+              "msp_convert")
+    return out
+
+
+def _faces_struct(f: dict) -> _lib.Faces:
+    return _lib.Faces(f["pos"].shape[1], f["idx"].shape[1], _dev_ptr(f["pos"]), _dev_ptr(f["opacity"]),
+                      _dev_ptr(f.get("rgb")), _dev_ptr(f.get("sh")), _dev_ptr(f["idx"]), _dev_ptr(f.get("gid")))
+
+
+def camera_struct(cam) -> _lib.Camera:
+    """scenes.Camera (or any object with the same fields) -> msp_camera."""
+    import numpy as np
+    W = np.asarray(cam.world_to_cam, dtype=np.float32).reshape(12)
+    return _lib.Camera((C.c_float * 12)(*W.tolist()), cam.fx, cam.fy, cam.cx, cam.cy, cam.znear,
+                       int(cam.width), int(cam.height))
+
+
+@dataclasses.dataclass
+class RenderOptions:
+    tile_w: int = 0        # 0: the context's autotuned (or default 16) tile
+    tile_h: int = 0
+    kbuf: int = 0          # 0: default 16
+    t_eps: float = 1e-6
+    bg: tuple = (0.0, 0.0, 0.0)
+    color_mode: int = MSP_COLOR_RGB
+
+    def struct(self) -> _lib.RenderOpts:
+        return _lib.RenderOpts(self.tile_w, self.tile_h, self.kbuf, self.color_mode, self.t_eps,
+                               (C.c_float * 3)(*self.bg))
+
+
+class RenderState:
+    """Library-owned tile lists and per-pixel counts of one render."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(ctx.lib.msp_state_create(ctx.h, C.byref(h)), "msp_state_create")
+        self.h = h
+        self.n_views = self.height = self.width = 0
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.msp_state_free(self.ctx.h, self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        s = _lib.RenderStats()
+        self.ctx.check(self.ctx.lib.msp_state_stats(self.ctx.h, self.h, C.byref(s)), "msp_state_stats")
+        return {n: getattr(s, n) for n, _ in s._fields_}
+
+    def tiles(self, view: int):
+        import numpy as np
+        st = self.stats()
+        nt = -(-st["width"] // st["tile_w"]) * -(-st["height"] // st["tile_h"])
+        off = np.zeros(nt + 1, dtype=np.int64)
+        self.ctx.check(self.ctx.lib.msp_debug_tiles(self.ctx.h, self.h, view, off.ctypes.data_as(C.c_void_p), None),
+                       "msp_debug_tiles")
+        keys = np.zeros(max(1, int(off[-1])), dtype=np.uint64)
+        self.ctx.check(self.ctx.lib.msp_debug_tiles(self.ctx.h, self.h, view, off.ctypes.data_as(C.c_void_p),
+                                                    keys.ctypes.data_as(C.c_void_p)), "msp_debug_tiles")
+        return off, keys[:int(off[-1])]
+
+    def nfrag(self):
+        import numpy as np
+        out = np.zeros((self.n_views, self.height, self.width), dtype=np.int32)
+        self.ctx.check(self.ctx.lib.msp_debug_nfrag(self.ctx.h, self.h, out.ctypes.data_as(C.c_void_p)),
+                       "msp_debug_nfrag")
+        return out
+
+
+def render(faces: dict, cams, opts: RenderOptions | None = None, state: RenderState | None = None):
+    """msp_render: returns (img [V,4,H,W] float32 on the faces' device, state)."""
+    import torch
+    opts = opts or RenderOptions()
+    pos = _need(faces["pos"], torch.float32, "pos")
+    _need(faces["opacity"], torch.float32, "opacity")
+    _need(faces["idx"], torch.int32, "idx")
+    if opts.color_mode == MSP_COLOR_RGB:
+        _need(faces["rgb"], torch.float32, "rgb")
+    ctx = _ctx(pos)
+    ctx.bind_stream()
+    V = len(cams)
+    arr = (_lib.Camera * V)(*[camera_struct(c) for c in cams])
+    H, W = int(cams[0].height), int(cams[0].width)
+    img = torch.empty((V, 4, H, W), dtype=torch.float32, device=pos.device)
+    state = state or RenderState(ctx)
+    Fc = _faces_struct(faces)
+    o = opts.struct()
+    ctx.check(ctx.lib.msp_render(ctx.h, C.byref(Fc), arr, V, C.byref(o), _dev_ptr(img), state.h), "msp_render")
+    state.n_views, state.height, state.width = V, H, W
+    return img, state
+
+
+def render_backward(state: RenderState, faces: dict, dimg, need=("dpos", "dopacity", "drgb")) -> dict:
+    """msp_render_backward: gradients of the last render on `state`."""
+    import torch
+    ctx = state.ctx
+    ctx.bind_stream()
+    dimg = _need(dimg, torch.float32, "dimg")
+    nv = faces["pos"].shape[1]
+    dev = faces["pos"].device
+    out = {}
+    if "dpos" in need:
+        out["dpos"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
+    if "dopacity" in need:
+        out["dopacity"] = torch.empty((nv,), dtype=torch.float32, device=dev)
+    if "drgb" in need:
+        out["drgb"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
+    G = _lib.FaceGrads(_dev_ptr(out.get("dpos")), _dev_ptr(out.get("dopacity")), _dev_ptr(out.get("drgb")), None)
+    Fc = _faces_struct(faces)
+    ctx.check(ctx.lib.msp_render_backward(ctx.h, state.h, C.byref(Fc), _dev_ptr(dimg), C.byref(G)),
+              "msp_render_backward")
+    return out
+
+
+def _autograd():
+    import torch
+
+    class _MeshRender(torch.autograd.Function):
+        """Differentiable render of a triangle soup: forward msp_render, backward
+        msp_render_backward (fragment lists recomputed, not stored)."""
+
+        @staticmethod
+        def forward(ctx, pos, opacity, rgb, idx, cams, opts):
+            faces = dict(pos=pos.contiguous(), opacity=opacity.contiguous(), rgb=rgb.contiguous(), idx=idx)
+            img, state = render(faces, cams, opts)
+            ctx.faces = faces
+            ctx.state = state
+            return img
+
+        @staticmethod
+        def backward(ctx, gimg):
+            g = render_backward(ctx.state, ctx.faces, gimg.contiguous())
+            return g["dpos"], g["dopacity"], g["drgb"], None, None, None
+
+    return _MeshRender
+
+
+class _LazyFunction:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFunction._fn is None:
+            _LazyFunction._fn = _autograd()
+        return _LazyFunction._fn.apply(*args)
+
+
+MeshRender = _LazyFunction()

@@ -1,0 +1,119 @@
+"""ctypes binding of libmsp.so (include/msp.h). Argument marshalling only.
+
+Every computation runs in the HIP library; there is no Python or CPU fallback.
+If the library is missing or the device is not a GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsp.so")
+
+
+class MspError(RuntimeError):
+    pass
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("rgb", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Faces(C.Structure):
+    _fields_ = [("n_verts", C.c_int64), ("n_faces", C.c_int64), ("pos", C.c_void_p), ("opacity", C.c_void_p),
+                ("rgb", C.c_void_p), ("sh", C.c_void_p), ("idx", C.c_void_p), ("gid", C.c_void_p)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("world_to_cam", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("znear", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("kbuf", C.c_int32), ("color_mode", C.c_int32),
+                ("t_eps", C.c_float), ("bg", C.c_float * 3)]
+
+
+class FaceGrads(C.Structure):
+    _fields_ = [("dpos", C.c_void_p), ("dopacity", C.c_void_p), ("drgb", C.c_void_p), ("dsh", C.c_void_p)]
+
+
+class RenderStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_views", "width", "height", "tile_w", "tile_h", "entries",
+                                         "max_tile_entries", "fragments", "restarts")]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "msp_version": (C.c_int, []),
+    "msp_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "msp_destroy": (C.c_int, [C.c_void_p]),
+    "msp_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "msp_last_error": (C.c_char_p, [C.c_void_p]),
+    "msp_convert_size": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "msp_convert": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float, C.c_int,
+                              C.POINTER(Faces)]),
+    "msp_state_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "msp_state_free": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "msp_render": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),
+                             C.c_void_p, C.c_void_p]),
+    "msp_render_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Faces), C.c_void_p, C.POINTER(FaceGrads)]),
+    "msp_state_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RenderStats)]),
+    "msp_debug_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "msp_debug_nfrag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Loads libmsp.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise MspError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_07754_amd.build`")
+            lib = C.CDLL(LIB_PATH)
+            for name, (res, args) in EXPORTS.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+class Context:
+    """One msp_ctx per device; each call binds it to torch's current stream."""
+
+    _by_device: dict = {}
+
+    def __init__(self, device: int):
+        import torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        rc = self.lib.msp_create(device, C.c_void_p(stream), C.byref(h))
+        if rc != 0:
+            raise MspError(f"msp_create failed ({rc})")
+        self.h = h
+
+    @classmethod
+    def get(cls, device: int) -> "Context":
+        ctx = cls._by_device.get(device)
+        if ctx is None:
+            ctx = cls._by_device[device] = Context(device)
+        return ctx
+
+    def bind_stream(self):
+        import torch
+        self.lib.msp_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self.lib.msp_last_error(self.h)
+            raise MspError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")

@@ -1,0 +1,370 @@
+// Host side of the C ABI declared in include/msp.h: argument checking,
+// library-owned scratch, and the order of kernel launches on the caller's stream.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kVersion = 10000;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool finite_cam(const msp_camera& c) {
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(c.world_to_cam[i])) return false;
+  return std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) &&
+         std::isfinite(c.znear) && c.fx != 0.f && c.fy != 0.f;
+}
+
+template <class T>
+T* P(const DevBuf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+}  // namespace
+
+int msp_fail(msp_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int msp_ensure(msp_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return MSP_OK;
+  if (b.p) {
+    // the stream may still use the old buffer
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return msp_fail(ctx, MSP_EHIP, "hipStreamSynchronize");
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;  // headroom against small growth
+  want = (want + 255) & ~size_t(255);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return msp_fail(ctx, MSP_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.bytes = want;
+  return MSP_OK;
+}
+
+extern "C" {
+
+int msp_version(void) { return kVersion; }
+
+msp_status msp_create(int device, void* hip_stream, msp_ctx** out) {
+  if (!out) return MSP_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MSP_EINVAL;
+  DeviceGuard g(device);
+  if (!g.ok) return MSP_EHIP;
+  msp_ctx* c = new msp_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+    c->n_cu = 1;
+  *out = c;
+  return MSP_OK;
+}
+
+msp_status msp_destroy(msp_ctx* ctx) {
+  if (!ctx) return MSP_EINVAL;
+  delete ctx;
+  return MSP_OK;
+}
+
+msp_status msp_set_stream(msp_ctx* ctx, void* hip_stream) {
+  if (!ctx) return MSP_EINVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return MSP_OK;
+}
+
+const char* msp_last_error(const msp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_t* n_faces) {
+  if (n < 0 || K < 3 || K > 64 || mode != MSP_FAN_FLAT || !n_verts || !n_faces) return MSP_EINVAL;
+  *n_verts = n * (K + 1);
+  *n_faces = n * K;
+  if (*n_verts >= (int64_t(1) << 31) || *n_faces >= (int64_t(1) << 31)) return MSP_EINVAL;
+  return MSP_OK;
+}
+
+msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, int mode,
+                       msp_faces* out) {
+  if (!ctx) return MSP_EINVAL;
+  if (!g || !out) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: null argument");
+  int64_t V, F;
+  if (msp_convert_size(g->n, K, mode, &V, &F) != MSP_OK)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: n, K or mode out of range");
+  if (!std::isfinite(sigma) || !(sigma > 0.f) || !std::isfinite(opac_mul))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: sigma must be finite and > 0, opac_mul finite");
+  if (out->n_verts != V || out->n_faces != F)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: output sizes differ from msp_convert_size");
+  if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->rgb || !out->pos || !out->opacity ||
+                   !out->rgb || !out->idx))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: null array");
+  if (g->sh && !out->sh) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: g->sh set but out->sh is NULL");
+  if (g->n == 0) return MSP_OK;
+  DeviceGuard dg(ctx->device);
+  std::vector<float> cs(2 * K);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < K; ++k) {
+    const double th = -pi + 2.0 * pi * k / K;
+    cs[k] = (float)std::cos(th);
+    cs[K + k] = (float)std::sin(th);
+  }
+  MSP_HIP(ctx, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  return MSP_OK;
+}
+
+msp_status msp_state_create(msp_ctx* ctx, msp_state** out) {
+  if (!ctx || !out) return MSP_EINVAL;
+  *out = new msp_state();
+  return MSP_OK;
+}
+
+msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
+  if (!ctx || !st) return MSP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  DevBuf* bufs[] = {&st->cams, &st->recs, &st->tile_cnt, &st->tile_off, &st->cursor, &st->vis, &st->vis_cnt,
+                    &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap, &st->blk_off,
+                    &st->frag_list, &st->col, &st->dcol};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  delete[] st->h_cams;
+  delete st;
+  return MSP_OK;
+}
+
+static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
+  std::memset(&a, 0, sizeof(a));
+  a.pos = f->pos;
+  a.opacity = f->opacity;
+  a.rgb = f->rgb;
+  a.idx = f->idx;
+  a.n_verts = f->n_verts;
+  a.n_faces = f->n_faces;
+  a.cams = P<msp_camera>(st->cams);
+  a.n_views = st->n_views;
+  a.W = st->W;
+  a.H = st->H;
+  a.tile_w = st->tile_w;
+  a.tile_h = st->tile_h;
+  a.ntx = st->ntx;
+  a.nty = st->nty;
+  a.n_tiles = st->n_tiles;
+  a.recs = P<FaceRec>(st->recs);
+  a.tile_cnt = P<uint32_t>(st->tile_cnt);
+  a.tile_off = P<int64_t>(st->tile_off);
+  a.cursor = P<uint32_t>(st->cursor);
+  a.vis = P<int32_t>(st->vis);
+  a.vis_cnt = P<uint32_t>(st->vis_cnt);
+  a.keys = P<uint64_t>(st->keys);
+  a.tmp = P<uint64_t>(st->tmp);
+  a.key_cap = (int64_t)(st->keys.bytes / sizeof(uint64_t));
+  a.col = nullptr;
+  a.t_eps = st->t_eps;
+  a.bg0 = st->bg[0];
+  a.bg1 = st->bg[1];
+  a.bg2 = st->bg[2];
+  a.nfrag = P<int32_t>(st->nfrag);
+  a.counters = P<unsigned long long>(st->counters);
+}
+
+msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                      const msp_render_opts* opts, float* img, msp_state* st) {
+  if (!ctx) return MSP_EINVAL;
+  auto bad = [&](const char* m) { return (msp_status)msp_fail(ctx, MSP_EINVAL, std::string("msp_render: ") + m); };
+  if (!f || !cams || !opts || !img || !st) return bad("null argument");
+  if (n_views < 1) return bad("n_views < 1");
+  if (f->n_faces < 0 || f->n_verts < 0 || f->n_faces >= (int64_t(1) << 31) || f->n_verts >= (int64_t(1) << 31))
+    return bad("face or vertex count out of range");
+  if (f->n_faces > 0 && (!f->pos || !f->opacity || !f->idx)) return bad("null face array");
+  const int W = cams[0].width, H = cams[0].height;
+  if (W < 1 || H < 1 || W > 16384 || H > 16384) return bad("width/height outside [1, 16384]");
+  for (int v = 0; v < n_views; ++v) {
+    if (cams[v].width != W || cams[v].height != H) return bad("all views must share width and height");
+    if (!finite_cam(cams[v])) return bad("camera has non-finite values or zero focal length");
+  }
+  int tw = opts->tile_w ? opts->tile_w : (ctx->tuned_tile_w ? ctx->tuned_tile_w : 16);
+  int th = opts->tile_h ? opts->tile_h : (ctx->tuned_tile_h ? ctx->tuned_tile_h : 16);
+  if (tw < 8 || th < 8 || tw > 64 || th > 64 || tw % 8 || th % 8) return bad("tile sizes must be multiples of 8 in [8, 64]");
+  int kb = opts->kbuf ? opts->kbuf : (ctx->tuned_kbuf ? ctx->tuned_kbuf : 16);
+  if (kb != 8 && kb != 16) return bad("kbuf must be 8 or 16");
+  if (!(opts->t_eps >= 0.f) || !std::isfinite(opts->t_eps)) return bad("t_eps must be finite and >= 0");
+  if (opts->color_mode != MSP_COLOR_RGB && opts->color_mode != MSP_COLOR_SH3) return bad("unknown color_mode");
+  if (opts->color_mode == MSP_COLOR_RGB && f->n_faces > 0 && !f->rgb) return bad("RGB mode needs f->rgb");
+  if (opts->color_mode == MSP_COLOR_SH3 && f->n_faces > 0 && !f->sh) return bad("SH mode needs f->sh");
+  if (opts->color_mode == MSP_COLOR_SH3) return bad("SH colour mode is not available in this build");
+
+  DeviceGuard dg(ctx->device);
+  st->n_views = n_views;
+  st->W = W;
+  st->H = H;
+  st->tile_w = tw;
+  st->tile_h = th;
+  st->kbuf = kb;
+  st->color_mode = opts->color_mode;
+  st->ntx = (W + tw - 1) / tw;
+  st->nty = (H + th - 1) / th;
+  st->n_tiles = (int64_t)st->ntx * st->nty;
+  st->n_faces = f->n_faces;
+  st->n_verts = f->n_verts;
+  st->faces_pos = f->pos;
+  st->faces_idx = f->idx;
+  st->t_eps = opts->t_eps;
+  for (int i = 0; i < 3; ++i) st->bg[i] = opts->bg[i];
+  st->rendered = false;
+  const int64_t V = n_views, F = f->n_faces, NT = st->n_tiles * V;
+  const int64_t npix = (int64_t)W * H * V;
+
+  int rc;
+  if ((rc = msp_ensure(ctx, st->cams, sizeof(msp_camera) * V)) ||
+      (rc = msp_ensure(ctx, st->recs, sizeof(FaceRec) * V * F)) ||
+      (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
+      (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->vis, 4 * V * F)) ||
+      (rc = msp_ensure(ctx, st->vis_cnt, 4 * V)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
+      (rc = msp_ensure(ctx, st->counters, 8 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))))
+    return (msp_status)rc;
+  if (st->h_cams_cap < n_views) {
+    delete[] st->h_cams;
+    st->h_cams = new msp_camera[n_views];
+    st->h_cams_cap = n_views;
+  }
+  std::memcpy(st->h_cams, cams, sizeof(msp_camera) * n_views);
+  hipStream_t s = ctx->stream;
+  MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
+  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->tile_cnt), 0u, NT));
+  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->vis_cnt), 0u, V));
+  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
+
+  RasterArgs a;
+  fill_args(st, f, a);
+  a.img = img;
+  MSP_HIP(ctx, launch_setup(s, a));
+  MSP_HIP(ctx, launch_scan_u32(s, a.tile_cnt, a.tile_off, NT, st->scan_part.p));
+  int64_t E = 0;
+  MSP_HIP(ctx, hipMemcpyAsync(&E, a.tile_off + NT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP(ctx, hipStreamSynchronize(s));
+  if ((rc = msp_ensure(ctx, st->keys, 8 * E)) || (rc = msp_ensure(ctx, st->tmp, 8 * E))) return (msp_status)rc;
+  st->entries = E;
+  fill_args(st, f, a);
+  a.img = img;
+  MSP_HIP(ctx, launch_fill_u32(s, a.cursor, 0u, NT));
+  MSP_HIP(ctx, launch_emit(s, a));
+  MSP_HIP(ctx, launch_tile_sort(s, a));
+  MSP_HIP(ctx, launch_composite(s, a, kb, ctx->n_cu));
+  st->rendered = true;
+  return MSP_OK;
+}
+
+msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
+                               msp_face_grads* grads) {
+  if (!ctx) return MSP_EINVAL;
+  auto bad = [&](const char* m) {
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, std::string("msp_render_backward: ") + m);
+  };
+  if (!st || !f || !dimg || !grads) return bad("null argument");
+  if (!st->rendered) return bad("state has no render");
+  if (f->pos != st->faces_pos || f->idx != st->faces_idx || f->n_faces != st->n_faces || f->n_verts != st->n_verts)
+    return (msp_status)msp_fail(ctx, MSP_ESTALE, "msp_render_backward: faces differ from the rendered ones");
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = ctx->stream;
+  const int64_t Vn = f->n_verts;
+  if (grads->dpos) MSP_HIP(ctx, launch_fill_f32(s, grads->dpos, 0.f, 3 * Vn));
+  if (grads->dopacity) MSP_HIP(ctx, launch_fill_f32(s, grads->dopacity, 0.f, Vn));
+  if (grads->drgb) MSP_HIP(ctx, launch_fill_f32(s, grads->drgb, 0.f, 3 * Vn));
+  if (f->n_faces == 0) return MSP_OK;
+  const int64_t nb = (int64_t)st->n_views * ((st->W + 7) / 8) * ((st->H + 7) / 8);
+  int rc;
+  if ((rc = msp_ensure(ctx, st->blk_cap, 4 * nb)) || (rc = msp_ensure(ctx, st->blk_off, 8 * (nb + 1))) ||
+      (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(nb))))
+    return (msp_status)rc;
+  RasterArgs a;
+  fill_args(st, f, a);
+  a.blk_cap = P<uint32_t>(st->blk_cap);
+  a.blk_off = P<int64_t>(st->blk_off);
+  MSP_HIP(ctx, launch_block_max(s, a));
+  MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
+  int64_t rows = 0;
+  MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP(ctx, hipStreamSynchronize(s));
+  if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * (rows > 0 ? rows : 1)))) return (msp_status)rc;
+  a.frag_list = P<uint2>(st->frag_list);
+  a.frag_cap = rows;
+  a.dimg = dimg;
+  a.dpos = grads->dpos;
+  a.dop = grads->dopacity;
+  a.drgb = grads->drgb;
+  // reset the backward work queue (counter 3)
+  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 2));
+  MSP_HIP(ctx, launch_backward(s, a, st->kbuf, ctx->n_cu));
+  return MSP_OK;
+}
+
+msp_status msp_state_stats(msp_ctx* ctx, msp_state* st, msp_render_stats* out) {
+  if (!ctx || !st || !out) return MSP_EINVAL;
+  if (!st->rendered) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_state_stats: no render");
+  DeviceGuard dg(ctx->device);
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  unsigned long long c[8];
+  MSP_HIP(ctx, hipMemcpy(c, st->counters.p, sizeof(c), hipMemcpyDeviceToHost));
+  const int64_t NT = st->n_tiles * st->n_views;
+  std::vector<int64_t> off(NT + 1);
+  MSP_HIP(ctx, hipMemcpy(off.data(), st->tile_off.p, sizeof(int64_t) * (NT + 1), hipMemcpyDeviceToHost));
+  int64_t mx = 0;
+  for (int64_t t = 0; t < NT; ++t) mx = off[t + 1] - off[t] > mx ? off[t + 1] - off[t] : mx;
+  out->n_views = st->n_views;
+  out->width = st->W;
+  out->height = st->H;
+  out->tile_w = st->tile_w;
+  out->tile_h = st->tile_h;
+  out->entries = st->entries;
+  out->max_tile_entries = mx;
+  out->fragments = (int64_t)c[0];
+  out->restarts = (int64_t)c[1];
+  return MSP_OK;
+}
+
+msp_status msp_debug_tiles(msp_ctx* ctx, msp_state* st, int view, int64_t* offsets, uint64_t* keys) {
+  if (!ctx || !st || !offsets) return MSP_EINVAL;
+  if (!st->rendered || view < 0 || view >= st->n_views)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_debug_tiles: no render or bad view");
+  DeviceGuard dg(ctx->device);
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t nt = st->n_tiles;
+  MSP_HIP(ctx, hipMemcpy(offsets, P<int64_t>(st->tile_off) + view * nt, sizeof(int64_t) * (nt + 1),
+                         hipMemcpyDeviceToHost));
+  const int64_t b = offsets[0];
+  for (int64_t t = 0; t <= nt; ++t) offsets[t] -= b;
+  if (keys && offsets[nt] > 0)
+    MSP_HIP(ctx, hipMemcpy(keys, P<uint64_t>(st->keys) + b, sizeof(uint64_t) * offsets[nt], hipMemcpyDeviceToHost));
+  return MSP_OK;
+}
+
+msp_status msp_debug_nfrag(msp_ctx* ctx, msp_state* st, int32_t* out) {
+  if (!ctx || !st || !out) return MSP_EINVAL;
+  if (!st->rendered) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_debug_nfrag: no render");
+  DeviceGuard dg(ctx->device);
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  MSP_HIP(ctx, hipMemcpy(out, st->nfrag.p, sizeof(int32_t) * st->n_views * st->W * st->H, hipMemcpyDeviceToHost));
+  return MSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP translation units of libmsp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "msp.h"
+
+#define MSP_WAVE 64
+
+// Face record written by the setup pass, one per (view, face): the clamped
+// pixel footprint [px0, px1] x [py0, py1] packed as 16-bit pairs, and the bits
+// of the nearest camera depth. A culled face has px0 > px1.
+struct FaceRec {
+  uint32_t xr;     // px0 | px1 << 16
+  uint32_t yr;     // py0 | py1 << 16
+  uint32_t zbits;  // float bits of min corner z_c
+  uint32_t ntiles; // number of tiles the footprint touches
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct msp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  std::string err;
+  // autotuned tile choice per (n_faces bucket, width, height, n_views), filled by msp_autotune
+  int tuned_tile_w = 0, tuned_tile_h = 0, tuned_kbuf = 0;
+};
+
+struct msp_state {
+  // geometry of the last render
+  int n_views = 0, W = 0, H = 0, tile_w = 0, tile_h = 0, ntx = 0, nty = 0, kbuf = 0, color_mode = 0;
+  int64_t n_tiles = 0;       // per view
+  int64_t n_faces = 0, n_verts = 0;
+  const void* faces_pos = nullptr;
+  const void* faces_idx = nullptr;
+  float t_eps = 0.f, bg[3] = {0, 0, 0};
+  int64_t entries = 0;
+  int64_t max_tile = 0;
+  bool rendered = false;
+  msp_camera* h_cams = nullptr;  // host copy
+  int h_cams_cap = 0;
+
+  DevBuf cams, recs, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
+      scan_part, blk_cap, blk_off, frag_list, col, dcol;
+};
+
+// ---- error helpers (host) ----
+int msp_fail(msp_ctx* ctx, int code, const std::string& msg);
+#define MSP_HIP(ctx, call)                                                            \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return (msp_status)msp_fail((ctx), MSP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int msp_ensure(msp_ctx* ctx, DevBuf& b, size_t bytes);
+
+// ---- launchers implemented in the kernel translation units ----
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n);
+hipError_t launch_fill_f32(hipStream_t s, float* p, float v, int64_t n);
+
+hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                               const float* cos_sin, msp_faces* out);
+
+// exclusive scan of n uint32 values into n+1 int64 offsets (last = total); scratch sized by scan_scratch_bytes
+size_t scan_scratch_bytes(int64_t n);
+hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, int64_t* out, int64_t n, void* scratch);
+
+struct RasterArgs {
+  const float* pos;
+  const float* opacity;
+  const float* rgb;
+  const int32_t* idx;
+  int64_t n_verts, n_faces;
+  const msp_camera* cams;  // device [n_views]
+  int n_views, W, H, tile_w, tile_h, ntx, nty;
+  int64_t n_tiles;         // per view
+  FaceRec* recs;           // [V][F]
+  uint32_t* tile_cnt;      // [V * n_tiles]
+  int64_t* tile_off;       // [V * n_tiles + 1]
+  uint32_t* cursor;        // [V * n_tiles]
+  int32_t* vis;            // [V][F]
+  uint32_t* vis_cnt;       // [V]
+  uint64_t* keys;          // [entries]
+  uint64_t* tmp;           // [entries]
+  int64_t key_cap;
+  const float* col;        // SH mode: [V][3][F] per-view face colour, else nullptr
+  float t_eps;
+  float bg0, bg1, bg2;
+  float* img;              // [V][4][H][W]
+  int32_t* nfrag;          // [V][H][W]
+  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd queue
+  // backward
+  const float* dimg;
+  const int64_t* blk_off;  // [n_blocks + 1] in units of 64-slot rows
+  uint2* frag_list;        // recomputed fragment lists
+  int64_t frag_cap;
+  uint32_t* blk_cap;       // [n_blocks]
+  float* dpos;
+  float* dop;
+  float* drgb;
+  float* dcol;             // SH mode: [V][3][F]
+};
+
+hipError_t launch_setup(hipStream_t s, const RasterArgs& a);
+hipError_t launch_emit(hipStream_t s, const RasterArgs& a);
+hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a);
+hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
+hipError_t launch_block_max(hipStream_t s, const RasterArgs& a);
+hipError_t launch_backward(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);

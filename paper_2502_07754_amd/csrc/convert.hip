@@ -1,0 +1,144 @@
+// Gaussian -> triangle-fan conversion (flat-Gaussian transformation section of
+// the paper: Eq. 2d_scaledrot for the two scaled axes, the vertex equation for
+// the boundary points, the fan construction, and the opacity paragraph for the
+// centre/boundary opacities). Streaming and HBM-bound: one thread per output
+// vertex and one per output face, structure-of-arrays writes, coalesced.
+#include "common.h"
+
+namespace {
+
+constexpr int kMaxK = 64;
+
+struct CosSin {
+  float c[kMaxK];
+  float s[kMaxK];
+};
+
+// Columns of the rotation of a (w, x, y, z) quaternion, normalised in float32.
+__device__ inline void rot_column(float w, float x, float y, float z, int col, float& r0, float& r1,
+                                  float& r2) {
+  const float n = sqrtf(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  if (col == 0) {
+    r0 = 1.f - 2.f * (y * y + z * z); r1 = 2.f * (x * y + w * z); r2 = 2.f * (x * z - w * y);
+  } else if (col == 1) {
+    r0 = 2.f * (x * y - w * z); r1 = 1.f - 2.f * (x * x + z * z); r2 = 2.f * (y * z + w * x);
+  } else {
+    r0 = 2.f * (x * z + w * y); r1 = 2.f * (y * z - w * x); r2 = 1.f - 2.f * (x * x + y * y);
+  }
+}
+
+// The fan spans the two largest scales (ties to the lower index), in index order.
+__device__ inline void pick_axes(float s0, float s1, float s2, int& a, int& b) {
+  int drop;
+  if (s2 <= s0 && s2 <= s1) drop = 2;
+  else if (s1 <= s0) drop = 1;
+  else drop = 0;
+  a = drop == 0 ? 1 : 0;
+  b = drop == 2 ? 1 : 2;
+}
+
+__global__ void k_convert_vertices(const float* __restrict__ mean, const float* __restrict__ scale,
+                                   const float* __restrict__ quat, const float* __restrict__ opacity,
+                                   const float* __restrict__ rgb, int64_t n, int K, float sigma,
+                                   float opac_mul, CosSin cs, float* __restrict__ pos,
+                                   float* __restrict__ vop, float* __restrict__ vrgb) {
+  const int64_t V = n * (K + 1);
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int64_t g = v / (K + 1);
+  const int j = (int)(v - g * (K + 1));
+  const float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
+  float px = mx, py = my, pz = mz;
+  const float o = opacity[g];
+  if (j > 0) {
+    const float s[3] = {scale[g], scale[n + g], scale[2 * n + g]};
+    int a, b;
+    pick_axes(s[0], s[1], s[2], a, b);
+    const float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
+    float ra0, ra1, ra2, rb0, rb1, rb2;
+    rot_column(qw, qx, qy, qz, a, ra0, ra1, ra2);
+    rot_column(qw, qx, qy, qz, b, rb0, rb1, rb2);
+    const float la = sigma * s[a], lb = sigma * s[b];
+    const float c = cs.c[j - 1], sn = cs.s[j - 1];
+    px = mx + c * (la * ra0) + sn * (lb * rb0);
+    py = my + c * (la * ra1) + sn * (lb * rb1);
+    pz = mz + c * (la * ra2) + sn * (lb * rb2);
+  }
+  pos[v] = px;
+  pos[V + v] = py;
+  pos[2 * V + v] = pz;
+  vop[v] = j == 0 ? o : opac_mul * o;
+  vrgb[v] = rgb[g];
+  vrgb[V + v] = rgb[n + g];
+  vrgb[2 * V + v] = rgb[2 * n + g];
+}
+
+__global__ void k_convert_faces(int64_t n, int K, const float* __restrict__ sh, int32_t* __restrict__ idx,
+                                int32_t* __restrict__ gid, float* __restrict__ fsh) {
+  const int64_t F = n * K;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int64_t g = f / K;
+  const int k = (int)(f - g * K);
+  const int32_t c = (int32_t)(g * (K + 1));
+  idx[f] = c;
+  idx[F + f] = c + 1 + k;
+  idx[2 * F + f] = c + 1 + (k + 1) % K;
+  if (gid) gid[f] = (int32_t)g;
+  if (sh && fsh) {
+#pragma unroll 4
+    for (int r = 0; r < 48; ++r) fsh[r * F + f] = sh[r * n + g];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(hipStream_t s, float* p, float v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                               const float* cos_sin, msp_faces* out) {
+  if (g->n == 0) return hipSuccess;
+  CosSin cs;
+  for (int k = 0; k < kMaxK; ++k) {
+    cs.c[k] = k < K ? cos_sin[k] : 0.f;
+    cs.s[k] = k < K ? cos_sin[K + k] : 0.f;
+  }
+  const int64_t V = g->n * (K + 1), F = g->n * K;
+  hipLaunchKernelGGL(k_convert_vertices, dim3(grid_for(V, 256)), dim3(256), 0, s, g->mean, g->scale, g->quat,
+                     g->opacity, g->rgb, g->n, K, sigma, opac_mul, cs, out->pos, out->opacity, out->rgb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_convert_faces, dim3(grid_for(F, 256)), dim3(256), 0, s, g->n, K, g->sh, out->idx, out->gid,
+                     out->sh);
+  return hipGetLastError();
+}

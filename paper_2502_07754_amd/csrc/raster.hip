@@ -1,0 +1,773 @@
+// Tile-binned, exactly depth-ordered rendering of a triangle soup, forward and
+// adjoint (rendering section of the paper: MVP transform, layers peeled in
+// depth order, interpolated vertex attributes, front-to-back blending through
+// alpha; the adjoint feeds the fine-tuning section's optimiser).
+//
+// Pipeline per render (all views in one launch per stage):
+//   setup      per (view, face): fixed-order float32 projection, near cull,
+//              pixel footprint with a 2^-8 px margin, nearest depth; tile
+//              counts; visible faces compacted with a wavefront ballot.
+//   scan       tile counts -> tile-list offsets (scan.hip).
+//   emit       per visible face: its key (bits(zmin) << 32 | face id) into
+//              every tile it touches.
+//   tile_sort  each tile list sorted ascending in LDS (bitonic; lists longer
+//              than the LDS tile are chunk-sorted then merged in place).
+//   composite  persistent: each wavefront pulls (view, 8x8 pixel block) work
+//              items; the block's tile list is staged 64 entries at a time in
+//              a per-wave LDS slab (ballot-compacted to the faces whose
+//              footprint meets the block) and streamed in nearest-depth
+//              order. Each lane keeps a register buffer of up to KB fragments
+//              sorted by (depth, face id); a fragment is composited once the
+//              next entry's nearest depth exceeds its depth, because no later
+//              face can then come in front of it. If the buffer overflows, the
+//              largest keys are dropped and remembered, everything smaller
+//              is still composited in exact order, and the lane re-scans the
+//              list for the keys after the last one it composited. The
+//              result is the exact (depth, face id) order at any depth
+//              complexity.
+//   backward   recomputes each pixel's ordered list with the same code into a
+//              per-block [k][64] slab, then walks it back to front:
+//              S_{i} = a_i c_i + (1 - a_i) S_{i+1}, P_i = (1 - a_i) P_{i+1}
+//              give d alpha and d colour without dividing by (1 - a), and
+//              the ray/triangle Jacobian gives d position.
+#include "common.h"
+
+namespace {
+
+constexpr float kMargin = 0.00390625f;  // 2^-8 pixel
+constexpr int kRec = 28;                // floats per staged face record
+constexpr int kWavesPerWG = 4;
+
+enum : int { DONE = 0, ACTIVE = 1, RESTART = 2 };
+
+struct Proj {
+  float xc, yc, zc, u, v;
+};
+
+// Camera coordinates and pixel coordinates, one IEEE float32 operation at a
+// time in a fixed order (no contraction), so binning is reproducible bit for bit.
+__device__ __forceinline__ Proj project(const msp_camera& c, float x, float y, float z) {
+#pragma clang fp contract(off)
+  Proj p;
+  const float* W = c.world_to_cam;
+  p.xc = ((W[0] * x + W[1] * y) + W[2] * z) + W[3];
+  p.yc = ((W[4] * x + W[5] * y) + W[6] * z) + W[7];
+  p.zc = ((W[8] * x + W[9] * y) + W[10] * z) + W[11];
+  p.u = c.fx * (p.xc / p.zc) + c.cx;
+  p.v = c.fy * (p.yc / p.zc) + c.cy;
+  return p;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// setup: footprint, nearest depth, tile counts, ballot compaction of visible faces
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
+  const int view = blockIdx.y;
+  const int64_t F = a.n_faces, V = a.n_verts;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  const msp_camera c = a.cams[view];
+  bool ok = false;
+  if (f < F) {
+    FaceRec r{1u, 0u, 0u, 0u};
+    const int32_t i0 = a.idx[f], i1 = a.idx[F + f], i2 = a.idx[2 * F + f];
+    if ((uint64_t)i0 < (uint64_t)V && (uint64_t)i1 < (uint64_t)V && (uint64_t)i2 < (uint64_t)V) {
+      const Proj p0 = project(c, a.pos[i0], a.pos[V + i0], a.pos[2 * V + i0]);
+      const Proj p1 = project(c, a.pos[i1], a.pos[V + i1], a.pos[2 * V + i1]);
+      const Proj p2 = project(c, a.pos[i2], a.pos[V + i2], a.pos[2 * V + i2]);
+      const bool vis = p0.zc > c.znear && p1.zc > c.znear && p2.zc > c.znear;
+      const bool fin = isfinite(p0.u) && isfinite(p1.u) && isfinite(p2.u) && isfinite(p0.v) &&
+                       isfinite(p1.v) && isfinite(p2.v);
+      if (vis && fin) {
+#pragma clang fp contract(off)
+        const float umin = fminf(fminf(p0.u, p1.u), p2.u), umax = fmaxf(fmaxf(p0.u, p1.u), p2.u);
+        const float vmin = fminf(fminf(p0.v, p1.v), p2.v), vmax = fmaxf(fmaxf(p0.v, p1.v), p2.v);
+        float fx0 = ceilf((umin - 0.5f) - kMargin), fx1 = floorf((umax - 0.5f) + kMargin);
+        float fy0 = ceilf((vmin - 0.5f) - kMargin), fy1 = floorf((vmax - 0.5f) + kMargin);
+        fx0 = fmaxf(fx0, 0.f);
+        fy0 = fmaxf(fy0, 0.f);
+        fx1 = fminf(fx1, (float)(a.W - 1));
+        fy1 = fminf(fy1, (float)(a.H - 1));
+        if (fx0 <= fx1 && fy0 <= fy1) {
+          const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
+          const float zmin = fminf(fminf(p0.zc, p1.zc), p2.zc);
+          const int tx0 = px0 / a.tile_w, tx1 = px1 / a.tile_w, ty0 = py0 / a.tile_h, ty1 = py1 / a.tile_h;
+          r.xr = (uint32_t)px0 | ((uint32_t)px1 << 16);
+          r.yr = (uint32_t)py0 | ((uint32_t)py1 << 16);
+          r.zbits = __float_as_uint(zmin);
+          r.ntiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          ok = true;
+          uint32_t* cnt = a.tile_cnt + (int64_t)view * a.n_tiles;
+          for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&cnt[ty * a.ntx + tx], 1u);
+        }
+      }
+    }
+    a.recs[(int64_t)view * F + f] = r;
+  }
+  // wavefront ballot compaction of the visible faces of this view
+  const uint64_t m = __ballot(ok);
+  uint32_t base = 0;
+  if (lane == 0 && m) base = atomicAdd(&a.vis_cnt[view], (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (ok) a.vis[(int64_t)view * F + base + __popcll(m & lanemask_lt(lane))] = (int32_t)f;
+}
+
+// ---------------------------------------------------------------------------
+// emit: scatter keys into the tile segments
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
+  const int view = blockIdx.y;
+  const int64_t F = a.n_faces;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.vis_cnt[view]) return;
+  const int32_t f = a.vis[(int64_t)view * F + i];
+  const FaceRec r = a.recs[(int64_t)view * F + f];
+  const int px0 = r.xr & 0xffff, px1 = r.xr >> 16, py0 = r.yr & 0xffff, py1 = r.yr >> 16;
+  const int tx0 = px0 / a.tile_w, tx1 = px1 / a.tile_w, ty0 = py0 / a.tile_h, ty1 = py1 / a.tile_h;
+  const uint64_t key = ((uint64_t)r.zbits << 32) | (uint32_t)f;
+  const int64_t tb = (int64_t)view * a.n_tiles;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int64_t t = tb + ty * a.ntx + tx;
+      const uint32_t slot = atomicAdd(&a.cursor[t], 1u);
+      const int64_t p = a.tile_off[t] + slot;
+      if (p < a.tile_off[t + 1] && p < a.key_cap) a.keys[p] = key;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile_sort: per-tile ascending sort of 64-bit keys
+// ---------------------------------------------------------------------------
+__device__ void bitonic_lds(uint64_t* s, int P) {
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = s[i], y = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            s[i] = y;
+            s[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ inline int next_pow2(int n) {
+  int p = 2;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Sorts keys[0, n) (n <= CAP) through LDS.
+template <int CAP>
+__device__ void sort_chunk(uint64_t* keys, int n, uint64_t* s) {
+  const int P = next_pow2(n);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < n ? keys[i] : ~0ull;
+  __syncthreads();
+  bitonic_lds(s, P);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = s[i];
+  __syncthreads();
+}
+
+// Cooperative merge of two sorted runs A[0, na) and B[0, nb) into out (merge path).
+__device__ void merge_runs(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out) {
+  const int64_t total = na + nb;
+  const int64_t per = (total + blockDim.x - 1) / blockDim.x;
+  int64_t d0 = (int64_t)threadIdx.x * per;
+  if (d0 > total) d0 = total;
+  int64_t d1 = d0 + per;
+  if (d1 > total) d1 = total;
+  if (d0 >= d1) return;
+  int64_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d0 - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  int64_t i = lo, j = d0 - lo;
+  for (int64_t d = d0; d < d1; ++d) {
+    if (j >= nb || (i < na && A[i] <= B[j])) out[d] = A[i++];
+    else out[d] = B[j++];
+  }
+}
+
+template <int CAP, bool BIG>
+__global__ __launch_bounds__(256) void k_tile_sort(RasterArgs a, int64_t n_seg) {
+  __shared__ uint64_t s[CAP];
+  const int64_t seg = blockIdx.x;
+  if (seg >= n_seg) return;
+  const int64_t beg = a.tile_off[seg];
+  const int64_t n = a.tile_off[seg + 1] - beg;
+  if (n <= 1) return;
+  if (!BIG) {
+    if (n > CAP) return;
+    sort_chunk<CAP>(a.keys + beg, (int)n, s);
+    return;
+  }
+  if (n <= 1024) return;  // handled by the small-list kernel
+  uint64_t* src = a.keys + beg;
+  uint64_t* dst = a.tmp + beg;
+  for (int64_t c0 = 0; c0 < n; c0 += CAP) {
+    const int64_t m = n - c0 < CAP ? n - c0 : CAP;
+    sort_chunk<CAP>(src + c0, (int)m, s);
+  }
+  for (int64_t w = CAP; w < n; w <<= 1) {
+    for (int64_t s0 = 0; s0 < n; s0 += 2 * w) {
+      const int64_t na = (n - s0 < w) ? n - s0 : w;
+      const int64_t rest = n - s0 - na;
+      const int64_t nb = rest < w ? rest : w;
+      merge_runs(src + s0, na, src + s0 + na, nb, dst + s0);
+    }
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a.keys + beg) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a.keys[beg + i] = src[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// composite forward / backward
+// ---------------------------------------------------------------------------
+
+// Staged face record (floats): 0 zmin | 1..3 edge 0 (e0, ex, ey) | 4..6 edge 1 |
+// 7..9 edge 2 | 10..12 1/z of the corners | 13..15 corner opacities | 16 face id bits |
+// 17..25 corner colours (r,g,b per corner) or the face colour in 17..19 | 26, 27 pad.
+// Edge k is the one opposite corner k, oriented so that inside is >= 0 and
+// evaluated relative to the centre of the block's first pixel.
+__device__ __forceinline__ bool build_record(const RasterArgs& a, const msp_camera& c, int view, int32_t f,
+                                             float rx, float ry, float* R) {
+#pragma clang fp contract(off)
+  const int64_t F = a.n_faces, V = a.n_verts;
+  const int32_t id[3] = {a.idx[f], a.idx[F + f], a.idx[2 * F + f]};
+  float u[3], v[3], z[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const Proj p = project(c, a.pos[id[k]], a.pos[V + id[k]], a.pos[2 * V + id[k]]);
+    u[k] = p.u;
+    v[k] = p.v;
+    z[k] = p.zc;
+  }
+  const float area2 = (u[1] - u[0]) * (v[2] - v[0]) - (v[1] - v[0]) * (u[2] - u[0]);
+  if (!(area2 != 0.f) || !isfinite(area2)) return false;
+  const float sg = area2 > 0.f ? 1.f : -1.f;
+  R[0] = fminf(fminf(z[0], z[1]), z[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ia = (k + 1) % 3, ib = (k + 2) % 3;
+    const float du = u[ib] - u[ia], dv = v[ib] - v[ia];
+    R[1 + 3 * k] = sg * (du * (ry - v[ia]) - dv * (rx - u[ia]));
+    R[2 + 3 * k] = -sg * dv;
+    R[3 + 3 * k] = sg * du;
+    R[10 + k] = 1.f / z[k];
+    R[13 + k] = a.opacity[id[k]];
+  }
+  R[16] = __uint_as_float((uint32_t)f);
+  if (a.col) {
+    const int64_t cb = (int64_t)view * 3 * F;
+    R[17] = a.col[cb + f];
+    R[18] = a.col[cb + F + f];
+    R[19] = a.col[cb + 2 * F + f];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R[17 + 3 * k] = a.rgb[id[k]];
+      R[18 + 3 * k] = a.rgb[V + id[k]];
+      R[19 + 3 * k] = a.rgb[2 * V + id[k]];
+    }
+  }
+  return true;
+}
+
+// Coverage and perspective-correct barycentrics of the pixel at block offset (dx, dy).
+__device__ __forceinline__ bool pixel_eval(const float* R, float dx, float dy, float& z, float& b0, float& b1,
+                                           float& b2) {
+#pragma clang fp contract(off)
+  const float E0 = fmaf(R[3], dy, fmaf(R[2], dx, R[1]));
+  const float E1 = fmaf(R[6], dy, fmaf(R[5], dx, R[4]));
+  const float E2 = fmaf(R[9], dy, fmaf(R[8], dx, R[7]));
+  if (E0 < 0.f || E1 < 0.f || E2 < 0.f) return false;
+  const float w0 = E0 * R[10], w1 = E1 * R[11], w2 = E2 * R[12];
+  const float s = (w0 + w1) + w2;
+  if (!(s > 0.f)) return false;
+  const float inv = 1.f / s;
+  b0 = w0 * inv;
+  b1 = w1 * inv;
+  b2 = w2 * inv;
+  z = fmaxf(((E0 + E1) + E2) * inv, R[0]);
+  return true;
+}
+
+__device__ __forceinline__ void frag_attr(const float* R, bool sh, float b0, float b1, float b2, float& raw,
+                                          float& al, float& cr, float& cg, float& cb) {
+#pragma clang fp contract(off)
+  raw = (b0 * R[13] + b1 * R[14]) + b2 * R[15];
+  al = fminf(fmaxf(raw, 0.f), 1.f);
+  if (sh) {
+    cr = R[17];
+    cg = R[18];
+    cb = R[19];
+  } else {
+    cr = (b0 * R[17] + b1 * R[20]) + b2 * R[23];
+    cg = (b0 * R[18] + b1 * R[21]) + b2 * R[24];
+    cb = (b0 * R[19] + b1 * R[22]) + b2 * R[25];
+  }
+}
+
+__device__ __forceinline__ uint64_t mkkey(float z, uint32_t f) {
+  return ((uint64_t)__float_as_uint(z) << 32) | f;
+}
+
+struct Item {
+  int view, bx0, by0;
+  int64_t seg;   // tile segment index
+  int64_t blk;   // global 8x8 block index
+};
+
+__device__ __forceinline__ bool decode_item(const RasterArgs& a, uint32_t item, Item& it) {
+  const int bpx = a.tile_w / 8, bpy = a.tile_h / 8;
+  const int64_t per_view = a.n_tiles * bpx * bpy;
+  it.view = (int)(item / per_view);
+  const int64_t r = item - (int64_t)it.view * per_view;
+  const int64_t tile = r / (bpx * bpy);
+  const int sb = (int)(r - tile * (bpx * bpy));
+  const int tx = (int)(tile % a.ntx), ty = (int)(tile / a.ntx);
+  it.bx0 = tx * a.tile_w + (sb % bpx) * 8;
+  it.by0 = ty * a.tile_h + (sb / bpx) * 8;
+  it.seg = (int64_t)it.view * a.n_tiles + tile;
+  const int nbx = (a.W + 7) / 8, nby = (a.H + 7) / 8;
+  it.blk = ((int64_t)it.view * nby + it.by0 / 8) * nbx + it.bx0 / 8;
+  return it.bx0 < a.W && it.by0 < a.H;
+}
+
+template <int KB>
+struct KBuf {
+  float z[KB];
+  uint32_t f[KB];
+  float al[KB], cr[KB], cg[KB], cb[KB];
+};
+
+// Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1 also
+// records each composited fragment (face id, transmittance before it) into the
+// block's list slab.
+template <int KB, int MODE>
+__device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, int lane, float& T, float& Cr,
+                            float& Cg, float& Cb, int& nf, uint32_t& restarts, uint2* list, int64_t list_rows) {
+  const msp_camera c = a.cams[it.view];
+  const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
+  const bool valid = px < a.W && py < a.H;
+  const int64_t beg = a.tile_off[it.seg];
+  const int64_t n = a.tile_off[it.seg + 1] - beg;
+  const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
+  const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
+  const bool sh = a.col != nullptr;
+  const float eps = a.t_eps;
+
+  KBuf<KB> kb;
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    kb.z[i] = __uint_as_float(0x7f800000u);
+    kb.f[i] = 0xffffffffu;
+    kb.al[i] = kb.cr[i] = kb.cg[i] = kb.cb[i] = 0.f;
+  }
+  T = 1.f;
+  Cr = Cg = Cb = 0.f;
+  nf = 0;
+  uint64_t lo = 0, drop = ~0ull, last = 0;
+  int state = valid ? ACTIVE : DONE;
+
+  auto pop_front = [&]() {
+    if (MODE == 1) {
+      if (nf < list_rows) list[(int64_t)nf * MSP_WAVE + lane] = make_uint2(kb.f[0], __float_as_uint(T));
+    }
+    const float w = T * kb.al[0];
+    Cr = fmaf(w, kb.cr[0], Cr);
+    Cg = fmaf(w, kb.cg[0], Cg);
+    Cb = fmaf(w, kb.cb[0], Cb);
+    T = T * (1.f - kb.al[0]);
+    last = mkkey(kb.z[0], kb.f[0]);
+    ++nf;
+#pragma unroll
+    for (int i = 0; i < KB - 1; ++i) {
+      kb.z[i] = kb.z[i + 1];
+      kb.f[i] = kb.f[i + 1];
+      kb.al[i] = kb.al[i + 1];
+      kb.cr[i] = kb.cr[i + 1];
+      kb.cg[i] = kb.cg[i + 1];
+      kb.cb[i] = kb.cb[i + 1];
+    }
+    kb.z[KB - 1] = __uint_as_float(0x7f800000u);
+    kb.f[KB - 1] = 0xffffffffu;
+  };
+  // composite every buffered fragment (all keys below the drop threshold are final)
+  auto flush_all = [&]() {
+    while (kb.f[0] != 0xffffffffu && T >= eps) pop_front();
+    // fragments left after the early stop are discarded
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      kb.z[i] = __uint_as_float(0x7f800000u);
+      kb.f[i] = 0xffffffffu;
+    }
+  };
+
+  while (__any(state != DONE)) {
+    if (state == RESTART) {
+      state = ACTIVE;
+      lo = last;
+      drop = ~0ull;
+      ++restarts;
+    }
+    for (int64_t base = 0; base < n; base += MSP_WAVE) {
+      if (!__any(state == ACTIVE)) break;
+      // ---- stage the next 64 entries, compacted to faces meeting this block ----
+      bool keep = false;
+      float R[kRec];
+      const int64_t e = base + lane;
+      if (e < n) {
+        const uint64_t key = a.keys[beg + e];
+        const int32_t f = (int32_t)(uint32_t)key;
+        if ((uint64_t)(uint32_t)f < (uint64_t)a.n_faces) {
+          const FaceRec r = a.recs[(int64_t)it.view * a.n_faces + f];
+          const int px0 = r.xr & 0xffff, px1 = r.xr >> 16, py0 = r.yr & 0xffff, py1 = r.yr >> 16;
+          keep = px0 <= px1 && px0 <= it.bx0 + 7 && px1 >= it.bx0 && py0 <= it.by0 + 7 && py1 >= it.by0;
+          if (keep) keep = build_record(a, c, it.view, f, rx, ry, R);
+        }
+      }
+      const uint64_t m = __ballot(keep);
+      const int cnt = __popcll(m);
+      if (keep) {
+        float4* dst = reinterpret_cast<float4*>(slab + __popcll(m & lanemask_lt(lane)) * kRec);
+#pragma unroll
+        for (int q = 0; q < kRec / 4; ++q) dst[q] = make_float4(R[4 * q], R[4 * q + 1], R[4 * q + 2], R[4 * q + 3]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // ---- stream the staged faces in nearest-depth order ----
+      for (int j = 0; j < cnt; ++j) {
+        const float* S = slab + j * kRec;
+        if (state == ACTIVE) {
+          const float W = S[0];
+          if (W > __uint_as_float((uint32_t)(drop >> 32))) {
+            // everything below the drop threshold has been seen: finish it, then re-scan
+            flush_all();
+            state = RESTART;
+          } else {
+            while (kb.z[0] < W && T >= eps) pop_front();
+            if (T < eps) {
+              state = DONE;
+            } else {
+              float z, b0, b1, b2;
+              if (pixel_eval(S, dx, dy, z, b0, b1, b2)) {
+                const uint32_t fid = __float_as_uint(S[16]);
+                const uint64_t nk = mkkey(z, fid);
+                if (nk > lo && nk < drop) {
+                  float raw, al, cr, cg, cb;
+                  frag_attr(S, sh, b0, b1, b2, raw, al, cr, cg, cb);
+                  const uint64_t lastk = mkkey(kb.z[KB - 1], kb.f[KB - 1]);
+                  if (kb.f[KB - 1] != 0xffffffffu) {
+                    // full: the largest of buffer + new is dropped
+                    drop = nk < lastk ? lastk : nk;
+                  }
+                  if (!(kb.f[KB - 1] != 0xffffffffu && nk > lastk)) {
+                    bool cpos[KB];
+#pragma unroll
+                    for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(kb.z[i], kb.f[i]);
+#pragma unroll
+                    for (int i = KB - 1; i >= 1; --i) {
+                      const bool sh_up = cpos[i - 1];
+                      const bool put = !sh_up && cpos[i];
+                      kb.z[i] = sh_up ? kb.z[i - 1] : (put ? z : kb.z[i]);
+                      kb.f[i] = sh_up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
+                      kb.al[i] = sh_up ? kb.al[i - 1] : (put ? al : kb.al[i]);
+                      kb.cr[i] = sh_up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
+                      kb.cg[i] = sh_up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
+                      kb.cb[i] = sh_up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
+                    }
+                    if (cpos[0]) {
+                      kb.z[0] = z;
+                      kb.f[0] = fid;
+                      kb.al[0] = al;
+                      kb.cr[0] = cr;
+                      kb.cg[0] = cg;
+                      kb.cb[0] = cb;
+                    }
+                  }
+                }
+              }
+            }
+          }
+        }
+        if (!__any(state == ACTIVE)) break;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (state == ACTIVE) {
+      flush_all();
+      state = (T < eps || drop == ~0ull) ? DONE : RESTART;
+    } else if (state == RESTART && T < eps) {
+      state = DONE;
+    }
+  }
+}
+
+struct BlockOut {
+  int dummy;
+};
+
+template <int KB>
+__global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_items) {
+  __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
+  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  float* slab = slabs[threadIdx.x / MSP_WAVE];
+  uint64_t frags = 0;
+  uint32_t restarts = 0;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[2], 1ull);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    Item it;
+    if (!decode_item(a, item, it)) continue;
+    float T, Cr, Cg, Cb;
+    int nf;
+    trace_block<KB, 0>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, nullptr, 0);
+    const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
+    if (px < a.W && py < a.H) {
+      const int64_t plane = (int64_t)a.H * a.W;
+      const int64_t o = (int64_t)it.view * 4 * plane + (int64_t)py * a.W + px;
+      a.img[o] = Cr + T * a.bg0;
+      a.img[o + plane] = Cg + T * a.bg1;
+      a.img[o + 2 * plane] = Cb + T * a.bg2;
+      a.img[o + 3 * plane] = 1.f - T;
+      a.nfrag[(int64_t)it.view * plane + (int64_t)py * a.W + px] = nf;
+      frags += (uint64_t)nf;
+    }
+  }
+  // one atomic per wave for the counters
+  for (int d = 32; d >= 1; d >>= 1) frags += __shfl_xor(frags, d);
+  if (lane == 0) {
+    atomicAdd(&a.counters[0], (unsigned long long)frags);
+    if (restarts) atomicAdd(&a.counters[1], (unsigned long long)restarts);
+  }
+}
+
+// per 8x8 block: the longest fragment list of its pixels (rows of the backward slab)
+__global__ void k_block_max(RasterArgs a, int64_t n_blocks) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_blocks) return;
+  const int nbx = (a.W + 7) / 8, nby = (a.H + 7) / 8;
+  const int64_t view = b / ((int64_t)nbx * nby);
+  const int64_t r = b - view * nbx * nby;
+  const int by0 = (int)(r / nbx) * 8, bx0 = (int)(r % nbx) * 8;
+  int mx = 0;
+  const int64_t plane = (int64_t)a.H * a.W;
+  for (int y = by0; y < by0 + 8 && y < a.H; ++y)
+    for (int x = bx0; x < bx0 + 8 && x < a.W; ++x) {
+      const int v = a.nfrag[view * plane + (int64_t)y * a.W + x];
+      mx = v > mx ? v : mx;
+    }
+  a.blk_cap[b] = (uint32_t)mx;
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void k_backward(RasterArgs a, uint32_t n_items) {
+  __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
+  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  float* slab = slabs[threadIdx.x / MSP_WAVE];
+  uint32_t restarts = 0;
+  const bool sh = a.col != nullptr;
+  const int64_t F = a.n_faces, V = a.n_verts;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[3], 1ull);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    Item it;
+    if (!decode_item(a, item, it)) continue;
+    const int64_t row0 = a.blk_off[it.blk];
+    const int64_t rows = a.blk_off[it.blk + 1] - row0;
+    uint2* list = a.frag_list + row0 * MSP_WAVE;
+    float T, Cr, Cg, Cb;
+    int nf;
+    trace_block<KB, 1>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, list, rows);
+    const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
+    if (!(px < a.W && py < a.H)) continue;
+    const msp_camera c = a.cams[it.view];
+    const int64_t plane = (int64_t)a.H * a.W;
+    const int64_t o = (int64_t)it.view * 4 * plane + (int64_t)py * a.W + px;
+    const float gr = a.dimg[o], gg = a.dimg[o + plane], gb = a.dimg[o + 2 * plane], gA = a.dimg[o + 3 * plane];
+    const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
+    const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
+    // pixel ray direction in camera space (z = 1)
+    const float d0 = ((float)px + 0.5f - c.cx) / c.fx, d1 = ((float)py + 0.5f - c.cy) / c.fy, d2 = 1.f;
+    const float* Wc = c.world_to_cam;
+    float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, P = 1.f;
+    const int nrows = nf < rows ? nf : (int)rows;
+    for (int k = nrows - 1; k >= 0; --k) {
+      const uint2 e = list[(int64_t)k * MSP_WAVE + lane];
+      const int32_t f = (int32_t)e.x;
+      const float Ti = __uint_as_float(e.y);
+      if ((uint64_t)e.x >= (uint64_t)F) continue;
+      float R[kRec];
+      if (!build_record(a, c, it.view, f, rx, ry, R)) continue;
+      float z, b0, b1, b2;
+      if (!pixel_eval(R, dx, dy, z, b0, b1, b2)) continue;
+      float raw, al, cr, cg, cb;
+      frag_attr(R, sh, b0, b1, b2, raw, al, cr, cg, cb);
+      const float wgt = Ti * al;
+      const float dcr = gr * wgt, dcg = gg * wgt, dcb = gb * wgt;
+      const float dal = Ti * (gr * (cr - Sr) + gg * (cg - Sg) + gb * (cb - Sb)) + gA * Ti * P;
+      Sr = al * cr + (1.f - al) * Sr;
+      Sg = al * cg + (1.f - al) * Sg;
+      Sb = al * cb + (1.f - al) * Sb;
+      P = (1.f - al) * P;
+      const float dalr = (raw > 0.f && raw < 1.f) ? dal : 0.f;
+      const int32_t id[3] = {a.idx[f], a.idx[F + f], a.idx[2 * F + f]};
+      const float bb[3] = {b0, b1, b2};
+      float dLdb[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        dLdb[q] = R[13 + q] * dalr;
+        if (!sh) dLdb[q] += R[17 + 3 * q] * dcr + R[18 + 3 * q] * dcg + R[19 + 3 * q] * dcb;
+      }
+      if (a.dop) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) atomicAdd(&a.dop[id[q]], bb[q] * dalr);
+      }
+      if (sh) {
+        if (a.dcol) {
+          const int64_t cbase = (int64_t)it.view * 3 * F;
+          atomicAdd(&a.dcol[cbase + f], dcr);
+          atomicAdd(&a.dcol[cbase + F + f], dcg);
+          atomicAdd(&a.dcol[cbase + 2 * F + f], dcb);
+        }
+      } else if (a.drgb) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          atomicAdd(&a.drgb[id[q]], bb[q] * dcr);
+          atomicAdd(&a.drgb[V + id[q]], bb[q] * dcg);
+          atomicAdd(&a.drgb[2 * V + id[q]], bb[q] * dcb);
+        }
+      }
+      if (a.dpos) {
+        // camera-space corners
+        float X[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const Proj p = project(c, a.pos[id[q]], a.pos[V + id[q]], a.pos[2 * V + id[q]]);
+          X[q][0] = p.xc;
+          X[q][1] = p.yc;
+          X[q][2] = p.zc;
+        }
+        const float e1[3] = {X[1][0] - X[0][0], X[1][1] - X[0][1], X[1][2] - X[0][2]};
+        const float e2[3] = {X[2][0] - X[0][0], X[2][1] - X[0][1], X[2][2] - X[0][2]};
+        // det = -d . (e1 x e2)
+        const float n0 = e1[1] * e2[2] - e1[2] * e2[1];
+        const float n1 = e1[2] * e2[0] - e1[0] * e2[2];
+        const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
+        const float det = -(d0 * n0 + d1 * n1 + d2 * n2);
+        if (det != 0.f && isfinite(det)) {
+          const float gu = dLdb[1] - dLdb[0], gv = dLdb[2] - dLdb[0];
+          // d x e2 and e1 x d
+          const float a0 = d1 * e2[2] - d2 * e2[1], a1 = d2 * e2[0] - d0 * e2[2], a2 = d0 * e2[1] - d1 * e2[0];
+          const float c0 = e1[1] * d2 - e1[2] * d1, c1 = e1[2] * d0 - e1[0] * d2, c2 = e1[0] * d1 - e1[1] * d0;
+          const float id_ = 1.f / det;
+          const float w0 = (gu * a0 + gv * c0) * id_, w1 = (gu * a1 + gv * c1) * id_, w2 = (gu * a2 + gv * c2) * id_;
+          // world gradient of corner q: R^T (-b_q w)
+          const float g0 = Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2;
+          const float g1 = Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2;
+          const float g2 = Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            atomicAdd(&a.dpos[id[q]], -bb[q] * g0);
+            atomicAdd(&a.dpos[V + id[q]], -bb[q] * g1);
+            atomicAdd(&a.dpos[2 * V + id[q]], -bb[q] * g2);
+          }
+        }
+      }
+    }
+  }
+}
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+template <class K>
+int persistent_grid(K kernel, int n_cu, uint32_t n_items) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t g = (int64_t)n_cu * per_cu;
+  const int64_t need = ((int64_t)n_items + kWavesPerWG - 1) / kWavesPerWG;
+  if (g > need) g = need;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_setup(hipStream_t s, const RasterArgs& a) {
+  if (a.n_faces == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_setup, dim3(grid_for(a.n_faces, 256), a.n_views), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(hipStream_t s, const RasterArgs& a) {
+  if (a.n_faces == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(a.n_faces, 256), a.n_views), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a) {
+  const int64_t n_seg = a.n_tiles * a.n_views;
+  hipLaunchKernelGGL((k_tile_sort<1024, false>), dim3((unsigned)n_seg), dim3(256), 0, s, a, n_seg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_tile_sort<8192, true>), dim3((unsigned)n_seg), dim3(256), 0, s, a, n_seg);
+  return hipGetLastError();
+}
+
+static uint32_t n_items_of(const RasterArgs& a) {
+  return (uint32_t)(a.n_tiles * (a.tile_w / 8) * (a.tile_h / 8) * a.n_views);
+}
+
+hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
+  const uint32_t n_items = n_items_of(a);
+  if (kbuf == 8) {
+    const int g = persistent_grid(k_composite<8>, n_cu, n_items);
+    hipLaunchKernelGGL(k_composite<8>, dim3(g), dim3(256), 0, s, a, n_items);
+  } else {
+    const int g = persistent_grid(k_composite<16>, n_cu, n_items);
+    hipLaunchKernelGGL(k_composite<16>, dim3(g), dim3(256), 0, s, a, n_items);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_max(hipStream_t s, const RasterArgs& a) {
+  const int64_t nb = (int64_t)a.n_views * ((a.W + 7) / 8) * ((a.H + 7) / 8);
+  hipLaunchKernelGGL(k_block_max, dim3(grid_for(nb, 256)), dim3(256), 0, s, a, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
+  const uint32_t n_items = n_items_of(a);
+  if (kbuf == 8) {
+    const int g = persistent_grid(k_backward<8>, n_cu, n_items);
+    hipLaunchKernelGGL(k_backward<8>, dim3(g), dim3(256), 0, s, a, n_items);
+  } else {
+    const int g = persistent_grid(k_backward<16>, n_cu, n_items);
+    hipLaunchKernelGGL(k_backward<16>, dim3(g), dim3(256), 0, s, a, n_items);
+  }
+  return hipGetLastError();
+}
