@@ -114,6 +114,7 @@ class RenderState:
         ctx.check(ctx.lib.msp_state_create(ctx.h, C.byref(h)), "msp_state_create")
         self.h = h
         self.n_views = self.height = self.width = 0
+        self.color_mode = MSP_COLOR_RGB
 
     def __del__(self):
         try:
@@ -157,6 +158,8 @@ def render(faces: dict, cams, opts: RenderOptions | None = None, state: RenderSt
     _need(faces["idx"], torch.int32, "idx")
     if opts.color_mode == MSP_COLOR_RGB:
         _need(faces["rgb"], torch.float32, "rgb")
+    else:
+        _need(faces.get("sh"), torch.float32, "sh")
     ctx = _ctx(pos)
     ctx.bind_stream()
     V = len(cams)
@@ -168,11 +171,13 @@ def render(faces: dict, cams, opts: RenderOptions | None = None, state: RenderSt
     o = opts.struct()
     ctx.check(ctx.lib.msp_render(ctx.h, C.byref(Fc), arr, V, C.byref(o), _dev_ptr(img), state.h), "msp_render")
     state.n_views, state.height, state.width = V, H, W
+    state.color_mode = opts.color_mode
     return img, state
 
 
-def render_backward(state: RenderState, faces: dict, dimg, need=("dpos", "dopacity", "drgb")) -> dict:
-    """msp_render_backward: gradients of the last render on `state`."""
+def render_backward(state: RenderState, faces: dict, dimg, need=("dpos", "dopacity", "drgb", "dsh")) -> dict:
+    """msp_render_backward: gradients of the last render on `state` (drgb in RGB
+    mode, dsh in SH mode)."""
     import torch
     ctx = state.ctx
     ctx.bind_stream()
@@ -184,9 +189,13 @@ def render_backward(state: RenderState, faces: dict, dimg, need=("dpos", "dopaci
         out["dpos"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
     if "dopacity" in need:
         out["dopacity"] = torch.empty((nv,), dtype=torch.float32, device=dev)
-    if "drgb" in need:
+    sh_mode = getattr(state, "color_mode", MSP_COLOR_RGB) == MSP_COLOR_SH3
+    if "drgb" in need and not sh_mode:
         out["drgb"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
-    G = _lib.FaceGrads(_dev_ptr(out.get("dpos")), _dev_ptr(out.get("dopacity")), _dev_ptr(out.get("drgb")), None)
+    if "dsh" in need and sh_mode:
+        out["dsh"] = torch.empty((48, faces["idx"].shape[1]), dtype=torch.float32, device=dev)
+    G = _lib.FaceGrads(_dev_ptr(out.get("dpos")), _dev_ptr(out.get("dopacity")), _dev_ptr(out.get("drgb")),
+                       _dev_ptr(out.get("dsh")))
     Fc = _faces_struct(faces)
     ctx.check(ctx.lib.msp_render_backward(ctx.h, state.h, C.byref(Fc), _dev_ptr(dimg), C.byref(G)),
               "msp_render_backward")

@@ -211,7 +211,7 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   if (opts->color_mode != MSP_COLOR_RGB && opts->color_mode != MSP_COLOR_SH3) return bad("unknown color_mode");
   if (opts->color_mode == MSP_COLOR_RGB && f->n_faces > 0 && !f->rgb) return bad("RGB mode needs f->rgb");
   if (opts->color_mode == MSP_COLOR_SH3 && f->n_faces > 0 && !f->sh) return bad("SH mode needs f->sh");
-  if (opts->color_mode == MSP_COLOR_SH3) return bad("SH colour mode is not available in this build");
+  if (opts->color_mode == MSP_COLOR_SH3 && n_views > sh_max_views()) return bad("SH mode supports at most 64 views");
 
   DeviceGuard dg(ctx->device);
   st->n_views = n_views;
@@ -254,6 +254,10 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->vis_cnt), 0u, V));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
 
+  if (opts->color_mode == MSP_COLOR_SH3) {
+    if ((rc = msp_ensure(ctx, st->col, sizeof(float) * 3 * V * F))) return (msp_status)rc;
+    MSP_HIP(ctx, launch_sh_eval(s, f, st->h_cams, n_views, P<float>(st->col)));
+  }
   RasterArgs a;
   fill_args(st, f, a);
   a.img = img;
@@ -266,6 +270,7 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   st->entries = E;
   fill_args(st, f, a);
   a.img = img;
+  if (opts->color_mode == MSP_COLOR_SH3) a.col = P<float>(st->col);
   MSP_HIP(ctx, launch_fill_u32(s, a.cursor, 0u, NT));
   MSP_HIP(ctx, launch_emit(s, a));
   MSP_HIP(ctx, launch_tile_sort(s, a));
@@ -290,7 +295,10 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
   if (grads->dpos) MSP_HIP(ctx, launch_fill_f32(s, grads->dpos, 0.f, 3 * Vn));
   if (grads->dopacity) MSP_HIP(ctx, launch_fill_f32(s, grads->dopacity, 0.f, Vn));
   if (grads->drgb) MSP_HIP(ctx, launch_fill_f32(s, grads->drgb, 0.f, 3 * Vn));
+  const bool shm = st->color_mode == MSP_COLOR_SH3;
+  if (shm && grads->dsh) MSP_HIP(ctx, launch_fill_f32(s, grads->dsh, 0.f, 48 * f->n_faces));
   if (f->n_faces == 0) return MSP_OK;
+  if (shm && !f->sh) return bad("SH render state needs f->sh");
   const int64_t nb = (int64_t)st->n_views * ((st->W + 7) / 8) * ((st->H + 7) / 8);
   int rc;
   if ((rc = msp_ensure(ctx, st->blk_cap, 4 * nb)) || (rc = msp_ensure(ctx, st->blk_off, 8 * (nb + 1))) ||
@@ -311,10 +319,19 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
   a.dimg = dimg;
   a.dpos = grads->dpos;
   a.dop = grads->dopacity;
-  a.drgb = grads->drgb;
+  a.drgb = shm ? nullptr : grads->drgb;
+  if (shm) {
+    const int64_t nc = 3 * (int64_t)st->n_views * f->n_faces;
+    if ((rc = msp_ensure(ctx, st->dcol, sizeof(float) * nc))) return (msp_status)rc;
+    MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
+    a.col = P<float>(st->col);
+    a.dcol = P<float>(st->dcol);
+  }
   // reset the backward work queue (counter 3)
   MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 2));
   MSP_HIP(ctx, launch_backward(s, a, st->kbuf, ctx->n_cu));
+  if (shm && grads->dsh)
+    MSP_HIP(ctx, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
   return MSP_OK;
 }
 

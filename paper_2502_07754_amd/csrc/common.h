@@ -111,6 +111,11 @@ struct RasterArgs {
   float* dcol;             // SH mode: [V][3][F]
 };
 
+int sh_max_views();
+hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float* col);
+hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, const float* dcol,
+                         float* dsh, float* dpos);
+
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a);
 hipError_t launch_emit(hipStream_t s, const RasterArgs& a);
 hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a);

@@ -297,3 +297,60 @@ def test_render_rejects_bad_arguments(gpu):
     bad = scenes.ring_cameras(1, 16, 32)
     with pytest.raises(gpu.MspError):
         gpu.render(f, [cams[0], bad[0]], gpu.RenderOptions())
+
+
+# ---------------------------------------------------------------------------
+# spherical-harmonics colour (per face, per view)
+# ---------------------------------------------------------------------------
+def _sh_scene(n=400, K=16, seed=12):
+    g = scenes.gaussians(n, seed, 0.02, 0.15, flat=True, sh=True)
+    f = faces_f32(oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, 2.0, sh=g.sh))
+    return f
+
+
+def test_sh_images_multiview(gpu):
+    from oracle import sh as osh
+    f = _sh_scene()
+    cams = scenes.ring_cameras(3, 56, 40)
+    _say("sh images")
+    img, st = gpu.render(to_gpu(f), cams, gpu.RenderOptions(t_eps=0.0, color_mode=1, bg=(0.05, 0.1, 0.0)))
+    img = img.cpu().numpy().astype(np.float64)
+    f64 = faces_f64(f)
+    for v, cam in enumerate(cams):
+        col, _ = osh.face_colours(f64["sh"], f64["pos"], f64["idx"], cam)
+        px = [(i, j) for j in range(40) for i in range(56)]
+        unexplained, nflag, covered, worst = _check_image(img[v], f, cam, px, bg=(0.05, 0.1, 0.0), view_col=col)
+        _say("view", v, "worst", worst, "flagged", nflag)
+        assert not unexplained, unexplained[:10]
+        assert nflag <= MAX_FLAGGED * covered
+
+
+def test_sh_backward_multiview(gpu):
+    import torch
+    from oracle import sh as osh
+    f = _sh_scene(n=150, K=16, seed=13)
+    cams = scenes.ring_cameras(2, 40, 32)
+    fg = to_gpu(f)
+    _say("sh backward")
+    img, st = gpu.render(fg, cams, gpu.RenderOptions(t_eps=0.0, color_mode=1))
+    dimg = scenes.upstream_grad(2, 32, 40, seed=5)
+    f64 = faces_f64(f)
+    px = [(i, j) for j in range(32) for i in range(40)]
+    gi = img.cpu().numpy().astype(np.float64)
+    ref = dict(dpos=np.zeros_like(f64["pos"]), dop=np.zeros_like(f64["opacity"]), dsh=np.zeros_like(f64["sh"]))
+    for v, cam in enumerate(cams):
+        col, _ = osh.face_colours(f64["sh"], f64["pos"], f64["idx"], cam)
+        rimg = orr.render_pixels(f64, cam, px, view_col=col)
+        got = np.stack([gi[v][:, j, i] for i, j in px])
+        for n in np.flatnonzero(np.max(np.abs(got - rimg), axis=1) > IMG_TOL):
+            i, j = px[n]
+            dimg[v, :, j, i] = 0.0
+        r = orr.render_backward_pixels(f64, cam, px, [dimg[v, :, j, i] for i, j in px], view_col=col)
+        dsh, dpos_dir = osh.face_colours_backward(f64["sh"], f64["pos"], f64["idx"], cam, r["dcol"])
+        ref["dpos"] += r["dpos"] + dpos_dir
+        ref["dop"] += r["dop"]
+        ref["dsh"] += dsh
+    gr = gpu.render_backward(st, fg, torch.from_numpy(dimg).cuda())
+    for k, rk in (("dpos", "dpos"), ("dopacity", "dop"), ("dsh", "dsh")):
+        ok, ex = grad_close(gr[k].cpu().numpy(), ref[rk])
+        assert ok, (k, ex)
