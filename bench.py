@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the MeshSplats hot path on one MI355X.
+
+Workload (the batched-render configuration): 500,000 flat Gaussians (means
+U[-1,1]^3, two scales log-U[0.01, 0.1], third 0, uniform rotations, opacity
+sigmoid(N(0,1)), colours from degree-3 SH with coefficients N(0, 0.1^2)),
+converted to K = 16 fans at sigma = 2 (8,000,000 triangles), rendered from
+eight 1920x1080 views on a ring of radius 3, forward and backward with a fixed
+upstream gradient dL/dimage = 1e-3 N(0, 1) (seed 3).
+
+One step = SH colour for all views + setup/bin/sort/composite of all views +
+recomputed-list adjoint + SH adjoint, i.e. one msp_render and one
+msp_render_backward. Conversion runs once before timing. Inputs are resident
+in HBM before the timed region starts.
+
+Prints one JSON line on stdout; a per-stage breakdown goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, cams, K, sigma, seconds: float):
+    """The float64 oracle (brute force over every face per pixel) on a few
+    pixels of view 0 of the same workload, forward and backward; extrapolated
+    to Mpix/s. Single process."""
+    import numpy as np
+
+    from oracle import convert as oc
+    from oracle import render as orr
+    from oracle import sh as osh
+    from paper_2502_07754_amd import scenes
+
+    f = oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, sh=g.sh)
+    f = {k: (v.astype(np.float32).astype(np.float64) if v.dtype == np.float64 else v) for k, v in f.items()}
+    cam = cams[0]
+    col, _ = osh.face_colours(f["sh"], f["pos"], f["idx"], cam)
+    geom = orr.face_geometry(f["pos"], f["idx"], cam)
+    rng = np.random.default_rng(7)
+    dimg = scenes.upstream_grad(1, cam.height, cam.width, 3, 1e-3)
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        i = int(rng.integers(cam.width // 4, 3 * cam.width // 4))
+        j = int(rng.integers(cam.height // 4, 3 * cam.height // 4))
+        fr = orr.pixel_fragments(f, cam, i, j, geom)
+        a, _, c = orr.fragment_attributes(f, fr, col)
+        orr.composite(a, c, (0.0, 0.0, 0.0))
+        r = orr.pixel_backward(f, cam, i, j, dimg[0, :, j, i], fr, view_col=col, geom=geom)
+        osh.face_colours_backward(f["sh"][:, r["fid"]], f["pos"], f["idx"][:, r["fid"]], cam, r["dcol"].T)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or done >= 64:
+            break
+    return dict(value=done / el / 1e6, unit="Mpix/s", cores=1, kind="oracle",
+                sample=f"{done} pixels of view 0 (central half), forward + backward, brute force over all "
+                       f"{f['idx'].shape[1]} faces per pixel, float64, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=500_000, help="Gaussians")
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--kbuf", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_07754_amd as msp
+    from paper_2502_07754_amd import _lib, scenes
+
+    W, H = 1920, 1080
+    g, cams, p = scenes.config3(n=args.n, views=args.views, width=W, height=H)
+    K, sigma = p["K"], p["sigma"]
+    dev = torch.device("cuda:0")
+    gg = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
+          dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=g.sh).items()}
+    ctx = _lib.Context.get(0)
+    ctx.timing(True)
+    faces = msp.convert(gg, K, sigma)
+    dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
+    opts = msp.RenderOptions(tile_w=args.tile, tile_h=args.tile, kbuf=args.kbuf, t_eps=1e-6, color_mode=1)
+    state = msp.RenderState(ctx)
+
+    def step():
+        img, _ = msp.render(faces, cams, opts, state=state)
+        grads = msp.render_backward(state, faces, dimg)
+        return img, grads
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.read_timing()  # discard warm-up stage times
+    log(f"warm-up done ({args.warmup} steps)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.read_timing()
+    st = state.stats()
+    dt = (t1 - t0) / args.steps
+    pix = args.views * W * H
+    value = pix / dt / 1e6
+    for name, (ms, calls) in sorted(stages.items(), key=lambda kv: -kv[1][0]):
+        if calls:
+            log(f"  {name:10s} {ms / calls:9.3f} ms/launch x {calls // args.steps}/step")
+    log(f"stats: {st}")
+
+    # dominant kernel and its algorithmic work
+    dom = max((k for k in stages if stages[k][1]), key=lambda k: stages[k][0])
+    dom_ms = stages[dom][0] / max(1, stages[dom][1])
+    frags = st["fragments"]
+    entries = st["entries"]
+    if dom in ("composite", "bwd_lists"):
+        # per composited fragment: barycentrics, alpha, colour, blend (~40 flop);
+        # per (tile entry, pixel) coverage test (~12 flop) is counted via entries x tile pixels
+        flop = 40.0 * frags + 12.0 * entries * 64
+        roof = dict(bound="alu", achieved=flop / (dom_ms * 1e-3) / 1e12, peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", traffic=None)
+    elif dom == "bwd_grads":
+        flop = 160.0 * frags
+        roof = dict(bound="alu", achieved=flop / (dom_ms * 1e-3) / 1e12, peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", traffic=None)
+    else:
+        nbytes = {"sort": 16.0 * entries, "emit": 8.0 * entries + 64.0 * faces["idx"].shape[1] * args.views,
+                  "setup": (12 + 36 + 48) * faces["idx"].shape[1] * args.views,
+                  "sh_eval": (192 + 36 + 16 * args.views) * faces["idx"].shape[1],
+                  "sh_bwd": (192 * 2 + 36 + 12 * args.views) * faces["idx"].shape[1]}.get(dom, 0.0)
+        roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                    traffic=None)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["ms_per_launch"] = dom_ms
+
+    out = {
+        "metric": "Mpix/s fwd+bwd at 1080p, 500k Gaussians K=16; fine-tune s to target MSE",
+        "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.n} flat Gaussians, K={K}, sigma={sigma}, SH degree 3, {args.views} views "
+                               f"{W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
+                   "faces": int(faces["idx"].shape[1]), "tile": args.tile, "kbuf": args.kbuf,
+                   "entries_per_step": entries, "fragments_per_step": frags,
+                   "fragments_per_s": frags / dt},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample ...")
+        out["cpu_baseline"] = cpu_baseline(g, cams, K, sigma, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,21 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
 msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
                                msp_face_grads* grads);
 
+/* ---- per-stage timing ------------------------------------------------- */
+
+/* Number of timed stages. Index: 0 convert, 1 SH colour, 2 setup (projection,
+ * footprints, tile counts, face records), 3 tile-offset scan, 4 emit, 5 tile
+ * sort, 6 composite, 7 per-block list sizing, 8 backward list recompute,
+ * 9 backward gradients, 10 SH adjoint, 11 other. */
+#define MSP_N_STAGES 12
+
+/* When on, every kernel stage is bracketed by a pair of HIP events recorded on
+ * the context stream (adds two event records per stage; off by default). */
+msp_status msp_timing_enable(msp_ctx* ctx, int on);
+/* Synchronises, then returns the summed milliseconds and call counts per stage
+ * since the last read (HOST arrays of n_stages entries), and resets them. */
+msp_status msp_timing_read(msp_ctx* ctx, double* ms, int64_t* calls, int n_stages);
+
 /* Counters of the last render on `st` (synchronises). */
 msp_status msp_state_stats(msp_ctx* ctx, msp_state* st, msp_render_stats* out);
 

@@ -64,7 +64,12 @@ EXPORTS = {
     "msp_state_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RenderStats)]),
     "msp_debug_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "msp_debug_nfrag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "msp_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "msp_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }
+
+STAGES = ["convert", "sh_eval", "setup", "scan", "emit", "sort", "composite", "block_max", "bwd_lists",
+          "bwd_grads", "sh_bwd", "other"]
 
 _lib = None
 _lock = threading.Lock()
@@ -112,6 +117,17 @@ class Context:
     def bind_stream(self):
         import torch
         self.lib.msp_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def timing(self, on: bool):
+        self.check(self.lib.msp_timing_enable(self.h, 1 if on else 0), "msp_timing_enable")
+
+    def read_timing(self) -> dict:
+        import numpy as np
+        ms = np.zeros(len(STAGES), dtype=np.float64)
+        calls = np.zeros(len(STAGES), dtype=np.int64)
+        self.check(self.lib.msp_timing_read(self.h, ms.ctypes.data_as(C.c_void_p), calls.ctypes.data_as(C.c_void_p),
+                                            len(STAGES)), "msp_timing_read")
+        return {n: (float(ms[i]), int(calls[i])) for i, n in enumerate(STAGES)}
 
     def check(self, rc: int, what: str):
         if rc != 0:

@@ -35,7 +35,50 @@ T* P(const DevBuf& b) {
   return reinterpret_cast<T*>(b.p);
 }
 
+#define MSP_TIMED(ctx, stage, call) \
+  do {                                \
+    timer_begin((ctx), (stage));      \
+    MSP_HIP((ctx), call);             \
+    timer_end((ctx), (stage));        \
+  } while (0)
+
 }  // namespace
+
+struct StageTimer {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> done;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[ST_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+void timer_begin(msp_ctx* ctx, int stage) {
+  StageTimer* t = ctx->timer;
+  if (!t || !t->on) return;
+  hipEvent_t e = t->get();
+  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->open[stage] = e;
+}
+
+void timer_end(msp_ctx* ctx, int stage) {
+  StageTimer* t = ctx->timer;
+  if (!t || !t->on || !t->open[stage]) return;
+  hipEvent_t e = t->get();
+  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->done.push_back({stage, t->open[stage], e});
+  t->open[stage] = nullptr;
+}
 
 int msp_fail(msp_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -84,7 +127,44 @@ msp_status msp_create(int device, void* hip_stream, msp_ctx** out) {
 
 msp_status msp_destroy(msp_ctx* ctx) {
   if (!ctx) return MSP_EINVAL;
+  if (ctx->timer) {
+    for (auto& r : ctx->timer->done) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->timer->pool) (void)hipEventDestroy(e);
+    delete ctx->timer;
+  }
   delete ctx;
+  return MSP_OK;
+}
+
+msp_status msp_timing_enable(msp_ctx* ctx, int on) {
+  if (!ctx) return MSP_EINVAL;
+  if (!ctx->timer) ctx->timer = new StageTimer();
+  ctx->timer->on = on != 0;
+  return MSP_OK;
+}
+
+msp_status msp_timing_read(msp_ctx* ctx, double* ms, int64_t* calls, int n_stages) {
+  if (!ctx || !ms || !calls || n_stages < 1) return MSP_EINVAL;
+  for (int i = 0; i < n_stages; ++i) {
+    ms[i] = 0.0;
+    calls[i] = 0;
+  }
+  if (!ctx->timer) return MSP_OK;
+  DeviceGuard dg(ctx->device);
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& r : ctx->timer->done) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.stage < n_stages) {
+      ms[r.stage] += t;
+      calls[r.stage] += 1;
+    }
+    ctx->timer->pool.push_back(r.a);
+    ctx->timer->pool.push_back(r.b);
+  }
+  ctx->timer->done.clear();
   return MSP_OK;
 }
 
@@ -128,7 +208,7 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
     cs[k] = (float)std::cos(th);
     cs[K + k] = (float)std::sin(th);
   }
-  MSP_HIP(ctx, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
   return MSP_OK;
 }
 
@@ -142,9 +222,9 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
   if (!ctx || !st) return MSP_EINVAL;
   DeviceGuard dg(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&st->cams, &st->recs, &st->tile_cnt, &st->tile_off, &st->cursor, &st->vis, &st->vis_cnt,
-                    &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap, &st->blk_off,
-                    &st->frag_list, &st->col, &st->dcol};
+  DevBuf* bufs[] = {&st->cams, &st->geo, &st->attr, &st->tile_cnt, &st->tile_off, &st->cursor, &st->vis,
+                    &st->vis_cnt, &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap,
+                    &st->blk_off, &st->frag_list, &st->col4, &st->dcol};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   delete[] st->h_cams;
@@ -169,7 +249,8 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.ntx = st->ntx;
   a.nty = st->nty;
   a.n_tiles = st->n_tiles;
-  a.recs = P<FaceRec>(st->recs);
+  a.geo = P<float4>(st->geo);
+  a.attr = P<float4>(st->attr);
   a.tile_cnt = P<uint32_t>(st->tile_cnt);
   a.tile_off = P<int64_t>(st->tile_off);
   a.cursor = P<uint32_t>(st->cursor);
@@ -178,7 +259,7 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.keys = P<uint64_t>(st->keys);
   a.tmp = P<uint64_t>(st->tmp);
   a.key_cap = (int64_t)(st->keys.bytes / sizeof(uint64_t));
-  a.col = nullptr;
+  a.col4 = st->color_mode == MSP_COLOR_SH3 ? P<float4>(st->col4) : nullptr;
   a.t_eps = st->t_eps;
   a.bg0 = st->bg[0];
   a.bg1 = st->bg[1];
@@ -236,7 +317,7 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
 
   int rc;
   if ((rc = msp_ensure(ctx, st->cams, sizeof(msp_camera) * V)) ||
-      (rc = msp_ensure(ctx, st->recs, sizeof(FaceRec) * V * F)) ||
+      (rc = msp_ensure(ctx, st->geo, 48 * V * F)) || (rc = msp_ensure(ctx, st->attr, 64 * F)) ||
       (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
       (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->vis, 4 * V * F)) ||
       (rc = msp_ensure(ctx, st->vis_cnt, 4 * V)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
@@ -255,14 +336,14 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
 
   if (opts->color_mode == MSP_COLOR_SH3) {
-    if ((rc = msp_ensure(ctx, st->col, sizeof(float) * 3 * V * F))) return (msp_status)rc;
-    MSP_HIP(ctx, launch_sh_eval(s, f, st->h_cams, n_views, P<float>(st->col)));
+    if ((rc = msp_ensure(ctx, st->col4, 16 * V * F))) return (msp_status)rc;
+    MSP_TIMED(ctx, ST_SH_EVAL, launch_sh_eval(s, f, st->h_cams, n_views, P<float4>(st->col4)));
   }
   RasterArgs a;
   fill_args(st, f, a);
   a.img = img;
-  MSP_HIP(ctx, launch_setup(s, a));
-  MSP_HIP(ctx, launch_scan_u32(s, a.tile_cnt, a.tile_off, NT, st->scan_part.p));
+  MSP_TIMED(ctx, ST_SETUP, launch_setup(s, a));
+  MSP_TIMED(ctx, ST_SCAN, launch_scan_u32(s, a.tile_cnt, a.tile_off, NT, st->scan_part.p));
   int64_t E = 0;
   MSP_HIP(ctx, hipMemcpyAsync(&E, a.tile_off + NT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MSP_HIP(ctx, hipStreamSynchronize(s));
@@ -270,11 +351,10 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   st->entries = E;
   fill_args(st, f, a);
   a.img = img;
-  if (opts->color_mode == MSP_COLOR_SH3) a.col = P<float>(st->col);
   MSP_HIP(ctx, launch_fill_u32(s, a.cursor, 0u, NT));
-  MSP_HIP(ctx, launch_emit(s, a));
-  MSP_HIP(ctx, launch_tile_sort(s, a));
-  MSP_HIP(ctx, launch_composite(s, a, kb, ctx->n_cu));
+  MSP_TIMED(ctx, ST_EMIT, launch_emit(s, a));
+  MSP_TIMED(ctx, ST_SORT, launch_tile_sort(s, a));
+  MSP_TIMED(ctx, ST_COMPOSITE, launch_composite(s, a, kb, ctx->n_cu));
   st->rendered = true;
   return MSP_OK;
 }
@@ -308,7 +388,7 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
   fill_args(st, f, a);
   a.blk_cap = P<uint32_t>(st->blk_cap);
   a.blk_off = P<int64_t>(st->blk_off);
-  MSP_HIP(ctx, launch_block_max(s, a));
+  MSP_TIMED(ctx, ST_BLOCK_MAX, launch_block_max(s, a));
   MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
   int64_t rows = 0;
   MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -324,14 +404,14 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
     const int64_t nc = 3 * (int64_t)st->n_views * f->n_faces;
     if ((rc = msp_ensure(ctx, st->dcol, sizeof(float) * nc))) return (msp_status)rc;
     MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
-    a.col = P<float>(st->col);
     a.dcol = P<float>(st->dcol);
   }
-  // reset the backward work queue (counter 3)
-  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 2));
-  MSP_HIP(ctx, launch_backward(s, a, st->kbuf, ctx->n_cu));
+  // reset the backward work queues (counters 3 and 4)
+  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 4));
+  MSP_TIMED(ctx, ST_BWD_LISTS, launch_bwd_lists(s, a, st->kbuf, ctx->n_cu));
+  MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
   if (shm && grads->dsh)
-    MSP_HIP(ctx, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
+    MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
   return MSP_OK;
 }
 

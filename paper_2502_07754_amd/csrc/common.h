@@ -10,23 +10,16 @@
 
 #define MSP_WAVE 64
 
-// Face record written by the setup pass, one per (view, face): the clamped
-// pixel footprint [px0, px1] x [py0, py1] packed as 16-bit pairs, and the bits
-// of the nearest camera depth. A culled face has px0 > px1.
-struct FaceRec {
-  uint32_t xr;     // px0 | px1 << 16
-  uint32_t yr;     // py0 | py1 << 16
-  uint32_t zbits;  // float bits of min corner z_c
-  uint32_t ntiles; // number of tiles the footprint touches
-};
-
 // Grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
 
+struct StageTimer;
+
 struct msp_ctx {
+  StageTimer* timer = nullptr;
   int device = 0;
   hipStream_t stream = nullptr;
   int n_cu = 0;
@@ -49,8 +42,8 @@ struct msp_state {
   msp_camera* h_cams = nullptr;  // host copy
   int h_cams_cap = 0;
 
-  DevBuf cams, recs, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
-      scan_part, blk_cap, blk_off, frag_list, col, dcol;
+  DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
+      scan_part, blk_cap, blk_off, frag_list, col4, dcol;
 };
 
 // ---- error helpers (host) ----
@@ -84,7 +77,8 @@ struct RasterArgs {
   const msp_camera* cams;  // device [n_views]
   int n_views, W, H, tile_w, tile_h, ntx, nty;
   int64_t n_tiles;         // per view
-  FaceRec* recs;           // [V][F]
+  float4* geo;             // [V][F][3] per-view geometry records (setup)
+  float4* attr;            // [F][4] corner opacities, colours and vertex ids
   uint32_t* tile_cnt;      // [V * n_tiles]
   int64_t* tile_off;       // [V * n_tiles + 1]
   uint32_t* cursor;        // [V * n_tiles]
@@ -93,12 +87,12 @@ struct RasterArgs {
   uint64_t* keys;          // [entries]
   uint64_t* tmp;           // [entries]
   int64_t key_cap;
-  const float* col;        // SH mode: [V][3][F] per-view face colour, else nullptr
+  const float4* col4;      // SH mode: [V][F] per-view face colour (r, g, b, 0), else nullptr
   float t_eps;
   float bg0, bg1, bg2;
   float* img;              // [V][4][H][W]
   int32_t* nfrag;          // [V][H][W]
-  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd queue
+  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd list queue, [4] bwd grad queue
   // backward
   const float* dimg;
   const int64_t* blk_off;  // [n_blocks + 1] in units of 64-slot rows
@@ -112,7 +106,7 @@ struct RasterArgs {
 };
 
 int sh_max_views();
-hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float* col);
+hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float4* col4);
 hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, const float* dcol,
                          float* dsh, float* dpos);
 
@@ -121,4 +115,13 @@ hipError_t launch_emit(hipStream_t s, const RasterArgs& a);
 hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a);
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
 hipError_t launch_block_max(hipStream_t s, const RasterArgs& a);
-hipError_t launch_backward(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
+hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
+hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu);
+
+// ---- per-stage timing with HIP events on the context stream ----
+enum MspStage {
+  ST_CONVERT = 0, ST_SH_EVAL, ST_SETUP, ST_SCAN, ST_EMIT, ST_SORT, ST_COMPOSITE, ST_BLOCK_MAX, ST_BWD_LISTS,
+  ST_BWD_GRADS, ST_SH_BWD, ST_OTHER, ST_COUNT
+};
+void timer_begin(msp_ctx* ctx, int stage);
+void timer_end(msp_ctx* ctx, int stage);

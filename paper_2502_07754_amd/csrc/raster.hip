@@ -5,31 +5,37 @@
 //
 // Pipeline per render (all views in one launch per stage):
 //   setup      per (view, face): fixed-order float32 projection, near cull,
-//              pixel footprint with a 2^-8 px margin, nearest depth; tile
-//              counts; visible faces compacted with a wavefront ballot.
+//              pixel footprint with a 2^-8 px margin, nearest depth; writes a
+//              48-byte geometry record; per-tile counts with wavefront-
+//              aggregated atomics; visible faces compacted with a ballot.
+//   attr       per face: corner opacities, colours and vertex ids packed in a
+//              64-byte record (view independent).
 //   scan       tile counts -> tile-list offsets (scan.hip).
 //   emit       per visible face: its key (bits(zmin) << 32 | face id) into
-//              every tile it touches.
+//              every tile it touches (wavefront-aggregated slot reservation).
 //   tile_sort  each tile list sorted ascending in LDS (bitonic; lists longer
 //              than the LDS tile are chunk-sorted then merged in place).
 //   composite  persistent: each wavefront pulls (view, 8x8 pixel block) work
 //              items; the block's tile list is staged 64 entries at a time in
 //              a per-wave LDS slab (ballot-compacted to the faces whose
-//              footprint meets the block) and streamed in nearest-depth
-//              order. Each lane keeps a register buffer of up to KB fragments
-//              sorted by (depth, face id); a fragment is composited once the
-//              next entry's nearest depth exceeds its depth, because no later
-//              face can then come in front of it. If the buffer overflows, the
-//              largest keys are dropped and remembered, everything smaller
-//              is still composited in exact order, and the lane re-scans the
-//              list for the keys after the last one it composited. The
-//              result is the exact (depth, face id) order at any depth
-//              complexity.
-//   backward   recomputes each pixel's ordered list with the same code into a
-//              per-block [k][64] slab, then walks it back to front:
-//              S_{i} = a_i c_i + (1 - a_i) S_{i+1}, P_i = (1 - a_i) P_{i+1}
-//              give d alpha and d colour without dividing by (1 - a), and
-//              the ray/triangle Jacobian gives d position.
+//              footprint meets the block; the next chunk's records are
+//              fetched while the current one is processed) and streamed in
+//              nearest-depth order. Each lane keeps a register buffer of up
+//              to KB fragments sorted by (depth, face id); a fragment is
+//              composited once the next entry's nearest depth exceeds its
+//              depth, because no later face can then come in front of it. If
+//              the buffer overflows, the largest keys are dropped and
+//              remembered, everything smaller is still composited in exact
+//              order, and the lane re-scans the list for the keys after the
+//              last one it composited: exact (depth, face id) order at any
+//              depth complexity.
+//   backward   pass 1 recomputes each pixel's ordered list with the same code
+//              into a per-block [k][64] slab (face id, transmittance);
+//              pass 2 walks it back to front with S_i = a_i c_i +
+//              (1 - a_i) S_{i+1} and P_i = (1 - a_i) P_{i+1} (no division by
+//              1 - a), takes d position through the ray/triangle Jacobian,
+//              and sums per-face gradients in a per-wave LDS hash table
+//              before one set of global atomics per (block, face).
 #include "common.h"
 
 namespace {
@@ -37,6 +43,8 @@ namespace {
 constexpr float kMargin = 0.00390625f;  // 2^-8 pixel
 constexpr int kRec = 28;                // floats per staged face record
 constexpr int kWavesPerWG = 4;
+constexpr int kHashSlots = 128;         // per-wave gradient table
+constexpr uint32_t kEmpty = 0xffffffffu;
 
 enum : int { DONE = 0, ACTIVE = 1, RESTART = 2 };
 
@@ -62,18 +70,48 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (MSP_WAVE - 1); }
+
+// Adds `inc` to counter[t] for every active lane, one atomic per distinct t in
+// the wavefront; returns each lane's old-value-plus-rank (a unique slot).
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* counter, int64_t t, bool active, bool want_slot) {
+  const int lane = lane_id();
+  uint64_t pending = __ballot(active);
+  uint32_t slot = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int64_t t0 = __shfl(t, leader);
+    const uint64_t m = __ballot(active && t == t0);
+    uint32_t base = 0;
+    if (lane == leader) {
+      if (want_slot) base = atomicAdd(&counter[t0], (uint32_t)__popcll(m));
+      else atomicAdd(&counter[t0], (uint32_t)__popcll(m));
+    }
+    if (want_slot) {
+      base = __shfl(base, leader);
+      if (active && t == t0) slot = base + (uint32_t)__popcll(m & lanemask_lt(lane));
+    }
+    pending &= ~m;
+  }
+  return slot;
+}
+
 // ---------------------------------------------------------------------------
-// setup: footprint, nearest depth, tile counts, ballot compaction of visible faces
+// setup
 // ---------------------------------------------------------------------------
+// geometry record (3 float4): (u0, v0, u1, v1) (u2, v2, z0, z1) (z2, xr, yr, zbits)
+// with xr = px0 | px1 << 16, yr = py0 | py1 << 16; a culled face has px0 > px1.
 __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
   const int view = blockIdx.y;
   const int64_t F = a.n_faces, V = a.n_verts;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  const int lane = lane_id();
   const msp_camera c = a.cams[view];
   bool ok = false;
+  int tx0 = 0, ty0 = 0, tw = 0, nt = 0;
   if (f < F) {
-    FaceRec r{1u, 0u, 0u, 0u};
+    float4 g0 = make_float4(0, 0, 0, 0), g1 = g0;
+    float4 g2 = make_float4(0.f, __uint_as_float(1u), __uint_as_float(0u), 0.f);
     const int32_t i0 = a.idx[f], i1 = a.idx[F + f], i2 = a.idx[2 * F + f];
     if ((uint64_t)i0 < (uint64_t)V && (uint64_t)i1 < (uint64_t)V && (uint64_t)i2 < (uint64_t)V) {
       const Proj p0 = project(c, a.pos[i0], a.pos[V + i0], a.pos[2 * V + i0]);
@@ -95,19 +133,31 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
         if (fx0 <= fx1 && fy0 <= fy1) {
           const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
           const float zmin = fminf(fminf(p0.zc, p1.zc), p2.zc);
-          const int tx0 = px0 / a.tile_w, tx1 = px1 / a.tile_w, ty0 = py0 / a.tile_h, ty1 = py1 / a.tile_h;
-          r.xr = (uint32_t)px0 | ((uint32_t)px1 << 16);
-          r.yr = (uint32_t)py0 | ((uint32_t)py1 << 16);
-          r.zbits = __float_as_uint(zmin);
-          r.ntiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          tx0 = px0 / a.tile_w;
+          ty0 = py0 / a.tile_h;
+          tw = px1 / a.tile_w - tx0 + 1;
+          nt = tw * (py1 / a.tile_h - ty0 + 1);
           ok = true;
-          uint32_t* cnt = a.tile_cnt + (int64_t)view * a.n_tiles;
-          for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&cnt[ty * a.ntx + tx], 1u);
+          g0 = make_float4(p0.u, p0.v, p1.u, p1.v);
+          g1 = make_float4(p2.u, p2.v, p0.zc, p1.zc);
+          g2 = make_float4(p2.zc, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
+                           __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)), __uint_as_float(__float_as_uint(zmin)));
         }
       }
     }
-    a.recs[(int64_t)view * F + f] = r;
+    float4* geo = a.geo + ((int64_t)view * F + f) * 3;
+    geo[0] = g0;
+    geo[1] = g1;
+    geo[2] = g2;
+  }
+  // per-tile counts, one atomic per distinct tile per wavefront step
+  int maxnt = nt;
+  for (int d = 32; d >= 1; d >>= 1) maxnt = max(maxnt, __shfl_xor(maxnt, d));
+  uint32_t* cnt = a.tile_cnt + (int64_t)view * a.n_tiles;
+  for (int j = 0; j < maxnt; ++j) {
+    const bool act = j < nt;
+    const int64_t t = act ? (int64_t)(ty0 + j / tw) * a.ntx + tx0 + j % tw : -1;
+    wave_aggregated_add(cnt, t, act, false);
   }
   // wavefront ballot compaction of the visible faces of this view
   const uint64_t m = __ballot(ok);
@@ -117,6 +167,28 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
   if (ok) a.vis[(int64_t)view * F + base + __popcll(m & lanemask_lt(lane))] = (int32_t)f;
 }
 
+// attribute record (4 float4): (o0, o1, o2, id0) (r0, g0, b0, id1) (r1, g1, b1, id2) (r2, g2, b2, 0)
+__global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
+  const int64_t F = a.n_faces, V = a.n_verts;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  int32_t id[3] = {a.idx[f], a.idx[F + f], a.idx[2 * F + f]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if ((uint64_t)id[k] >= (uint64_t)V) id[k] = 0;  // such faces are culled in setup and never drawn
+  float4* r = a.attr + f * 4;
+  r[0] = make_float4(a.opacity[id[0]], a.opacity[id[1]], a.opacity[id[2]], __int_as_float(id[0]));
+  if (a.rgb) {
+    r[1] = make_float4(a.rgb[id[0]], a.rgb[V + id[0]], a.rgb[2 * V + id[0]], __int_as_float(id[1]));
+    r[2] = make_float4(a.rgb[id[1]], a.rgb[V + id[1]], a.rgb[2 * V + id[1]], __int_as_float(id[2]));
+    r[3] = make_float4(a.rgb[id[2]], a.rgb[V + id[2]], a.rgb[2 * V + id[2]], 0.f);
+  } else {
+    r[1] = make_float4(0.f, 0.f, 0.f, __int_as_float(id[1]));
+    r[2] = make_float4(0.f, 0.f, 0.f, __int_as_float(id[2]));
+    r[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // emit: scatter keys into the tile segments
 // ---------------------------------------------------------------------------
@@ -124,20 +196,33 @@ __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
   const int view = blockIdx.y;
   const int64_t F = a.n_faces;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)a.vis_cnt[view]) return;
-  const int32_t f = a.vis[(int64_t)view * F + i];
-  const FaceRec r = a.recs[(int64_t)view * F + f];
-  const int px0 = r.xr & 0xffff, px1 = r.xr >> 16, py0 = r.yr & 0xffff, py1 = r.yr >> 16;
-  const int tx0 = px0 / a.tile_w, tx1 = px1 / a.tile_w, ty0 = py0 / a.tile_h, ty1 = py1 / a.tile_h;
-  const uint64_t key = ((uint64_t)r.zbits << 32) | (uint32_t)f;
+  const int64_t nvis = (int64_t)a.vis_cnt[view];
+  if ((int64_t)blockIdx.x * blockDim.x >= nvis) return;  // whole block idle (uniform)
+  int tx0 = 0, ty0 = 0, tw = 1, nt = 0;
+  uint64_t key = 0;
+  if (i < nvis) {
+    const int32_t f = a.vis[(int64_t)view * F + i];
+    const float4 g2 = a.geo[((int64_t)view * F + f) * 3 + 2];
+    const uint32_t xr = __float_as_uint(g2.y), yr = __float_as_uint(g2.z);
+    const int px0 = xr & 0xffff, px1 = xr >> 16, py0 = yr & 0xffff, py1 = yr >> 16;
+    tx0 = px0 / a.tile_w;
+    ty0 = py0 / a.tile_h;
+    tw = px1 / a.tile_w - tx0 + 1;
+    nt = tw * (py1 / a.tile_h - ty0 + 1);
+    key = ((uint64_t)__float_as_uint(g2.w) << 32) | (uint32_t)f;
+  }
+  int maxnt = nt;
+  for (int d = 32; d >= 1; d >>= 1) maxnt = max(maxnt, __shfl_xor(maxnt, d));
   const int64_t tb = (int64_t)view * a.n_tiles;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const int64_t t = tb + ty * a.ntx + tx;
-      const uint32_t slot = atomicAdd(&a.cursor[t], 1u);
+  for (int j = 0; j < maxnt; ++j) {
+    const bool act = j < nt;
+    const int64_t t = act ? tb + (int64_t)(ty0 + j / tw) * a.ntx + tx0 + j % tw : -1;
+    const uint32_t slot = wave_aggregated_add(a.cursor, t, act, true);
+    if (act) {
       const int64_t p = a.tile_off[t] + slot;
       if (p < a.tile_off[t + 1] && p < a.key_cap) a.keys[p] = key;
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -167,7 +252,6 @@ __device__ inline int next_pow2(int n) {
   return p;
 }
 
-// Sorts keys[0, n) (n <= CAP) through LDS.
 template <int CAP>
 __device__ void sort_chunk(uint64_t* keys, int n, uint64_t* s) {
   const int P = next_pow2(n);
@@ -178,7 +262,6 @@ __device__ void sort_chunk(uint64_t* keys, int n, uint64_t* s) {
   __syncthreads();
 }
 
-// Cooperative merge of two sorted runs A[0, na) and B[0, nb) into out (merge path).
 __device__ void merge_runs(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out) {
   const int64_t total = na + nb;
   const int64_t per = (total + blockDim.x - 1) / blockDim.x;
@@ -246,23 +329,34 @@ __global__ __launch_bounds__(256) void k_tile_sort(RasterArgs a, int64_t n_seg) 
 // 17..25 corner colours (r,g,b per corner) or the face colour in 17..19 | 26, 27 pad.
 // Edge k is the one opposite corner k, oriented so that inside is >= 0 and
 // evaluated relative to the centre of the block's first pixel.
-__device__ __forceinline__ bool build_record(const RasterArgs& a, const msp_camera& c, int view, int32_t f,
-                                             float rx, float ry, float* R) {
+struct Fetched {
+  float4 g0, g1, g2, a0, a1, a2, a3;
+};
+
+__device__ __forceinline__ Fetched fetch_face(const RasterArgs& a, int view, int32_t f) {
+  Fetched q;
+  const float4* g = a.geo + ((int64_t)view * a.n_faces + f) * 3;
+  q.g0 = g[0];
+  q.g1 = g[1];
+  q.g2 = g[2];
+  const float4* r = a.attr + (int64_t)f * 4;
+  q.a0 = r[0];
+  const bool sh = a.col4 != nullptr;
+  q.a1 = sh ? a.col4[(int64_t)view * a.n_faces + f] : r[1];
+  q.a2 = sh ? make_float4(0.f, 0.f, 0.f, 0.f) : r[2];
+  q.a3 = sh ? make_float4(0.f, 0.f, 0.f, 0.f) : r[3];
+  return q;
+}
+
+__device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float rx, float ry, float* R) {
 #pragma clang fp contract(off)
-  const int64_t F = a.n_faces, V = a.n_verts;
-  const int32_t id[3] = {a.idx[f], a.idx[F + f], a.idx[2 * F + f]};
-  float u[3], v[3], z[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const Proj p = project(c, a.pos[id[k]], a.pos[V + id[k]], a.pos[2 * V + id[k]]);
-    u[k] = p.u;
-    v[k] = p.v;
-    z[k] = p.zc;
-  }
+  const float u[3] = {q.g0.x, q.g0.z, q.g1.x};
+  const float v[3] = {q.g0.y, q.g0.w, q.g1.y};
+  const float z[3] = {q.g1.z, q.g1.w, q.g2.x};
   const float area2 = (u[1] - u[0]) * (v[2] - v[0]) - (v[1] - v[0]) * (u[2] - u[0]);
   if (!(area2 != 0.f) || !isfinite(area2)) return false;
   const float sg = area2 > 0.f ? 1.f : -1.f;
-  R[0] = fminf(fminf(z[0], z[1]), z[2]);
+  R[0] = q.g2.w;  // nearest depth (same bits as the sort key)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int ia = (k + 1) % 3, ib = (k + 2) % 3;
@@ -271,22 +365,16 @@ __device__ __forceinline__ bool build_record(const RasterArgs& a, const msp_came
     R[2 + 3 * k] = -sg * dv;
     R[3 + 3 * k] = sg * du;
     R[10 + k] = 1.f / z[k];
-    R[13 + k] = a.opacity[id[k]];
   }
-  R[16] = __uint_as_float((uint32_t)f);
-  if (a.col) {
-    const int64_t cb = (int64_t)view * 3 * F;
-    R[17] = a.col[cb + f];
-    R[18] = a.col[cb + F + f];
-    R[19] = a.col[cb + 2 * F + f];
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      R[17 + 3 * k] = a.rgb[id[k]];
-      R[18 + 3 * k] = a.rgb[V + id[k]];
-      R[19 + 3 * k] = a.rgb[2 * V + id[k]];
-    }
-  }
+  R[13] = q.a0.x;
+  R[14] = q.a0.y;
+  R[15] = q.a0.z;
+  R[16] = __uint_as_float(f);
+  R[17] = q.a1.x; R[18] = q.a1.y; R[19] = q.a1.z;
+  R[20] = q.a2.x; R[21] = q.a2.y; R[22] = q.a2.z;
+  R[23] = q.a3.x; R[24] = q.a3.y; R[25] = q.a3.z;
+  R[26] = 0.f;
+  R[27] = 0.f;
   return true;
 }
 
@@ -331,8 +419,8 @@ __device__ __forceinline__ uint64_t mkkey(float z, uint32_t f) {
 
 struct Item {
   int view, bx0, by0;
-  int64_t seg;   // tile segment index
-  int64_t blk;   // global 8x8 block index
+  int64_t seg;  // tile segment index
+  int64_t blk;  // global 8x8 block index
 };
 
 __device__ __forceinline__ bool decode_item(const RasterArgs& a, uint32_t item, Item& it) {
@@ -358,27 +446,43 @@ struct KBuf {
   float al[KB], cr[KB], cg[KB], cb[KB];
 };
 
+// Loads entry `e` of the tile list (key, records), used one chunk ahead of its use.
+struct Prefetch {
+  uint64_t key;
+  bool ok;
+  Fetched q;
+};
+
+__device__ __forceinline__ Prefetch prefetch_entry(const RasterArgs& a, const Item& it, int64_t beg, int64_t n,
+                                                   int64_t e) {
+  Prefetch p;
+  p.key = e < n ? a.keys[beg + e] : ~0ull;
+  const uint32_t f = (uint32_t)p.key;
+  p.ok = e < n && (uint64_t)f < (uint64_t)a.n_faces;
+  p.q = fetch_face(a, it.view, p.ok ? (int32_t)f : 0);
+  return p;
+}
+
 // Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1 also
 // records each composited fragment (face id, transmittance before it) into the
 // block's list slab.
 template <int KB, int MODE>
 __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, int lane, float& T, float& Cr,
                             float& Cg, float& Cb, int& nf, uint32_t& restarts, uint2* list, int64_t list_rows) {
-  const msp_camera c = a.cams[it.view];
   const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
   const bool valid = px < a.W && py < a.H;
   const int64_t beg = a.tile_off[it.seg];
   const int64_t n = a.tile_off[it.seg + 1] - beg;
   const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
   const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
-  const bool sh = a.col != nullptr;
+  const bool sh = a.col4 != nullptr;
   const float eps = a.t_eps;
 
   KBuf<KB> kb;
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     kb.z[i] = __uint_as_float(0x7f800000u);
-    kb.f[i] = 0xffffffffu;
+    kb.f[i] = kEmpty;
     kb.al[i] = kb.cr[i] = kb.cg[i] = kb.cb[i] = 0.f;
   }
   T = 1.f;
@@ -408,16 +512,15 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       kb.cb[i] = kb.cb[i + 1];
     }
     kb.z[KB - 1] = __uint_as_float(0x7f800000u);
-    kb.f[KB - 1] = 0xffffffffu;
+    kb.f[KB - 1] = kEmpty;
   };
   // composite every buffered fragment (all keys below the drop threshold are final)
   auto flush_all = [&]() {
-    while (kb.f[0] != 0xffffffffu && T >= eps) pop_front();
-    // fragments left after the early stop are discarded
+    while (kb.f[0] != kEmpty && T >= eps) pop_front();
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
       kb.z[i] = __uint_as_float(0x7f800000u);
-      kb.f[i] = 0xffffffffu;
+      kb.f[i] = kEmpty;
     }
   };
 
@@ -428,21 +531,17 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       drop = ~0ull;
       ++restarts;
     }
+    Prefetch pf = prefetch_entry(a, it, beg, n, lane);
     for (int64_t base = 0; base < n; base += MSP_WAVE) {
       if (!__any(state == ACTIVE)) break;
-      // ---- stage the next 64 entries, compacted to faces meeting this block ----
+      // ---- stage this chunk (ballot-compacted to faces meeting the block) ----
       bool keep = false;
       float R[kRec];
-      const int64_t e = base + lane;
-      if (e < n) {
-        const uint64_t key = a.keys[beg + e];
-        const int32_t f = (int32_t)(uint32_t)key;
-        if ((uint64_t)(uint32_t)f < (uint64_t)a.n_faces) {
-          const FaceRec r = a.recs[(int64_t)it.view * a.n_faces + f];
-          const int px0 = r.xr & 0xffff, px1 = r.xr >> 16, py0 = r.yr & 0xffff, py1 = r.yr >> 16;
-          keep = px0 <= px1 && px0 <= it.bx0 + 7 && px1 >= it.bx0 && py0 <= it.by0 + 7 && py1 >= it.by0;
-          if (keep) keep = build_record(a, c, it.view, f, rx, ry, R);
-        }
+      if (pf.ok) {
+        const uint32_t xr = __float_as_uint(pf.q.g2.y), yr = __float_as_uint(pf.q.g2.z);
+        const int px0 = xr & 0xffff, px1 = xr >> 16, py0 = yr & 0xffff, py1 = yr >> 16;
+        keep = px0 <= px1 && px0 <= it.bx0 + 7 && px1 >= it.bx0 && py0 <= it.by0 + 7 && py1 >= it.by0;
+        if (keep) keep = build_record(pf.q, (uint32_t)pf.key, rx, ry, R);
       }
       const uint64_t m = __ballot(keep);
       const int cnt = __popcll(m);
@@ -453,6 +552,8 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // ---- fetch the next chunk while this one is processed ----
+      pf = prefetch_entry(a, it, beg, n, base + MSP_WAVE + lane);
       // ---- stream the staged faces in nearest-depth order ----
       for (int j = 0; j < cnt; ++j) {
         const float* S = slab + j * kRec;
@@ -474,25 +575,23 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
                 if (nk > lo && nk < drop) {
                   float raw, al, cr, cg, cb;
                   frag_attr(S, sh, b0, b1, b2, raw, al, cr, cg, cb);
+                  const bool full = kb.f[KB - 1] != kEmpty;
                   const uint64_t lastk = mkkey(kb.z[KB - 1], kb.f[KB - 1]);
-                  if (kb.f[KB - 1] != 0xffffffffu) {
-                    // full: the largest of buffer + new is dropped
-                    drop = nk < lastk ? lastk : nk;
-                  }
-                  if (!(kb.f[KB - 1] != 0xffffffffu && nk > lastk)) {
+                  if (full) drop = nk < lastk ? lastk : nk;  // the largest of buffer + new is dropped
+                  if (!(full && nk > lastk)) {
                     bool cpos[KB];
 #pragma unroll
                     for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(kb.z[i], kb.f[i]);
 #pragma unroll
                     for (int i = KB - 1; i >= 1; --i) {
-                      const bool sh_up = cpos[i - 1];
-                      const bool put = !sh_up && cpos[i];
-                      kb.z[i] = sh_up ? kb.z[i - 1] : (put ? z : kb.z[i]);
-                      kb.f[i] = sh_up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
-                      kb.al[i] = sh_up ? kb.al[i - 1] : (put ? al : kb.al[i]);
-                      kb.cr[i] = sh_up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
-                      kb.cg[i] = sh_up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
-                      kb.cb[i] = sh_up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
+                      const bool up = cpos[i - 1];
+                      const bool put = !up && cpos[i];
+                      kb.z[i] = up ? kb.z[i - 1] : (put ? z : kb.z[i]);
+                      kb.f[i] = up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
+                      kb.al[i] = up ? kb.al[i - 1] : (put ? al : kb.al[i]);
+                      kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
+                      kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
+                      kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
                     }
                     if (cpos[0]) {
                       kb.z[0] = z;
@@ -521,14 +620,10 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
   }
 }
 
-struct BlockOut {
-  int dummy;
-};
-
 template <int KB>
 __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_items) {
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
-  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint64_t frags = 0;
   uint32_t restarts = 0;
@@ -554,7 +649,6 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
       frags += (uint64_t)nf;
     }
   }
-  // one atomic per wave for the counters
   for (int d = 32; d >= 1; d >>= 1) frags += __shfl_xor(frags, d);
   if (lane == 0) {
     atomicAdd(&a.counters[0], (unsigned long long)frags);
@@ -580,14 +674,13 @@ __global__ void k_block_max(RasterArgs a, int64_t n_blocks) {
   a.blk_cap[b] = (uint32_t)mx;
 }
 
+// backward pass 1: recompute the ordered fragment lists
 template <int KB>
-__global__ __launch_bounds__(256) void k_backward(RasterArgs a, uint32_t n_items) {
+__global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_items) {
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
-  const int lane = threadIdx.x & (MSP_WAVE - 1);
+  const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint32_t restarts = 0;
-  const bool sh = a.col != nullptr;
-  const int64_t F = a.n_faces, V = a.n_verts;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[3], 1ull);
@@ -597,106 +690,227 @@ __global__ __launch_bounds__(256) void k_backward(RasterArgs a, uint32_t n_items
     if (!decode_item(a, item, it)) continue;
     const int64_t row0 = a.blk_off[it.blk];
     const int64_t rows = a.blk_off[it.blk + 1] - row0;
-    uint2* list = a.frag_list + row0 * MSP_WAVE;
     float T, Cr, Cg, Cb;
     int nf;
-    trace_block<KB, 1>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, list, rows);
+    trace_block<KB, 1>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, a.frag_list + row0 * MSP_WAVE, rows);
+  }
+}
+
+// backward pass 2: back-to-front walk with per-wave LDS reduction of the face gradients.
+// Table values per face: RGB mode: dop[3] | drgb[3 corners][3] | dpos_cam[3 corners][3]
+//                        SH mode:  dop[3] | dcol[3]            | dpos_cam[3 corners][3]
+template <bool SH>
+struct GradLayout {
+  static constexpr int NV = SH ? 15 : 21;
+  static constexpr int COL = 3;
+  static constexpr int POS = SH ? 6 : 12;
+};
+
+template <bool SH>
+__device__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float* vals, int lane) {
+  using L = GradLayout<SH>;
+  const float* Wc = a.cams[view].world_to_cam;
+  const int64_t F = a.n_faces, V = a.n_verts;
+  for (int s = lane; s < kHashSlots; s += MSP_WAVE) {
+    const uint32_t f = keys[s];
+    if (f == kEmpty) continue;
+    const float4* r = a.attr + (int64_t)f * 4;
+    const int32_t id[3] = {__float_as_int(r[0].w), __float_as_int(r[1].w), __float_as_int(r[2].w)};
+    float v[L::NV];
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) {
+      v[q] = vals[q * kHashSlots + s];
+      vals[q * kHashSlots + s] = 0.f;
+    }
+    keys[s] = kEmpty;
+    if (a.dop) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) atomicAdd(&a.dop[id[k]], v[k]);
+    }
+    if (SH) {
+      if (a.dcol) {
+        const int64_t cb = (int64_t)view * 3 * F;
+        atomicAdd(&a.dcol[cb + f], v[3]);
+        atomicAdd(&a.dcol[cb + F + f], v[4]);
+        atomicAdd(&a.dcol[cb + 2 * F + f], v[5]);
+      }
+    } else if (a.drgb) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomicAdd(&a.drgb[id[k]], v[L::COL + 3 * k]);
+        atomicAdd(&a.drgb[V + id[k]], v[L::COL + 3 * k + 1]);
+        atomicAdd(&a.drgb[2 * V + id[k]], v[L::COL + 3 * k + 2]);
+      }
+    }
+    if (a.dpos) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float w0 = v[L::POS + 3 * k], w1 = v[L::POS + 3 * k + 1], w2 = v[L::POS + 3 * k + 2];
+        // camera -> world: R^T g
+        atomicAdd(&a.dpos[id[k]], Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2);
+        atomicAdd(&a.dpos[V + id[k]], Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2);
+        atomicAdd(&a.dpos[2 * V + id[k]], Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t f) {
+  uint32_t h = (f * 0x9E3779B1u) >> 25;  // 7 bits
+  for (int p = 0; p < 32; ++p) {
+    const uint32_t s = (h + p) & (kHashSlots - 1);
+    const uint32_t k = keys[s];
+    if (k == f) return (int)s;
+    if (k == kEmpty) {
+      const uint32_t prev = atomicCAS(&keys[s], kEmpty, f);
+      if (prev == kEmpty || prev == f) return (int)s;
+    }
+  }
+  return -1;
+}
+
+template <bool SH>
+__global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_items) {
+  using L = GradLayout<SH>;
+  __shared__ uint32_t hkeys[kWavesPerWG][kHashSlots];
+  __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];
+  const int lane = lane_id();
+  const int wid = threadIdx.x / MSP_WAVE;
+  uint32_t* keys = hkeys[wid];
+  float* vals = hvals[wid];
+  for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
+  for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[4], 1ull);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    Item it;
+    if (!decode_item(a, item, it)) continue;
+    const int64_t row0 = a.blk_off[it.blk];
+    const int64_t rows = a.blk_off[it.blk + 1] - row0;
+    const uint2* list = a.frag_list + row0 * MSP_WAVE;
     const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
-    if (!(px < a.W && py < a.H)) continue;
+    const bool valid = px < a.W && py < a.H;
     const msp_camera c = a.cams[it.view];
     const int64_t plane = (int64_t)a.H * a.W;
-    const int64_t o = (int64_t)it.view * 4 * plane + (int64_t)py * a.W + px;
-    const float gr = a.dimg[o], gg = a.dimg[o + plane], gb = a.dimg[o + 2 * plane], gA = a.dimg[o + 3 * plane];
+    int nf = 0;
+    float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
+    if (valid) {
+      nf = a.nfrag[(int64_t)it.view * plane + (int64_t)py * a.W + px];
+      if (nf > rows) nf = (int)rows;
+      const int64_t o = (int64_t)it.view * 4 * plane + (int64_t)py * a.W + px;
+      gr = a.dimg[o];
+      gg = a.dimg[o + plane];
+      gb = a.dimg[o + 2 * plane];
+      gA = a.dimg[o + 3 * plane];
+    }
     const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
     const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
-    // pixel ray direction in camera space (z = 1)
-    const float d0 = ((float)px + 0.5f - c.cx) / c.fx, d1 = ((float)py + 0.5f - c.cy) / c.fy, d2 = 1.f;
-    const float* Wc = c.world_to_cam;
+    const float d0 = ((float)px + 0.5f - c.cx) / c.fx, d1 = ((float)py + 0.5f - c.cy) / c.fy;
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, P = 1.f;
-    const int nrows = nf < rows ? nf : (int)rows;
-    for (int k = nrows - 1; k >= 0; --k) {
-      const uint2 e = list[(int64_t)k * MSP_WAVE + lane];
-      const int32_t f = (int32_t)e.x;
-      const float Ti = __uint_as_float(e.y);
-      if ((uint64_t)e.x >= (uint64_t)F) continue;
-      float R[kRec];
-      if (!build_record(a, c, it.view, f, rx, ry, R)) continue;
-      float z, b0, b1, b2;
-      if (!pixel_eval(R, dx, dy, z, b0, b1, b2)) continue;
-      float raw, al, cr, cg, cb;
-      frag_attr(R, sh, b0, b1, b2, raw, al, cr, cg, cb);
-      const float wgt = Ti * al;
-      const float dcr = gr * wgt, dcg = gg * wgt, dcb = gb * wgt;
-      const float dal = Ti * (gr * (cr - Sr) + gg * (cg - Sg) + gb * (cb - Sb)) + gA * Ti * P;
-      Sr = al * cr + (1.f - al) * Sr;
-      Sg = al * cg + (1.f - al) * Sg;
-      Sb = al * cb + (1.f - al) * Sb;
-      P = (1.f - al) * P;
-      const float dalr = (raw > 0.f && raw < 1.f) ? dal : 0.f;
-      const int32_t id[3] = {a.idx[f], a.idx[F + f], a.idx[2 * F + f]};
-      const float bb[3] = {b0, b1, b2};
-      float dLdb[3];
+    int maxn = nf;
+    for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d));
+    for (int k = maxn - 1; k >= 0; --k) {
+      bool act = k < nf;
+      float val[L::NV];
+      uint32_t f = kEmpty;
+      if (act) {
+        const uint2 e = list[(int64_t)k * MSP_WAVE + lane];
+        f = e.x;
+        const float Ti = __uint_as_float(e.y);
+        act = (uint64_t)f < (uint64_t)a.n_faces;
+        float R[kRec];
+        float z, b0, b1, b2;
+        const Fetched q = fetch_face(a, it.view, act ? (int32_t)f : 0);
+        if (act) act = build_record(q, f, rx, ry, R) && pixel_eval(R, dx, dy, z, b0, b1, b2);
+        if (act) {
+          float raw, al, cr, cg, cb;
+          frag_attr(R, SH, b0, b1, b2, raw, al, cr, cg, cb);
+          const float wgt = Ti * al;
+          const float dcr = gr * wgt, dcg = gg * wgt, dcb = gb * wgt;
+          const float dal = Ti * (gr * (cr - Sr) + gg * (cg - Sg) + gb * (cb - Sb)) + gA * Ti * P;
+          Sr = al * cr + (1.f - al) * Sr;
+          Sg = al * cg + (1.f - al) * Sg;
+          Sb = al * cb + (1.f - al) * Sb;
+          P = (1.f - al) * P;
+          const float dalr = (raw > 0.f && raw < 1.f) ? dal : 0.f;
+          const float bb[3] = {b0, b1, b2};
+          float dLdb[3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        dLdb[q] = R[13 + q] * dalr;
-        if (!sh) dLdb[q] += R[17 + 3 * q] * dcr + R[18 + 3 * q] * dcg + R[19 + 3 * q] * dcb;
-      }
-      if (a.dop) {
+          for (int qq = 0; qq < 3; ++qq) {
+            dLdb[qq] = R[13 + qq] * dalr;
+            if (!SH) dLdb[qq] += R[17 + 3 * qq] * dcr + R[18 + 3 * qq] * dcg + R[19 + 3 * qq] * dcb;
+            val[qq] = bb[qq] * dalr;
+          }
+          if (SH) {
+            val[3] = dcr;
+            val[4] = dcg;
+            val[5] = dcb;
+          } else {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) atomicAdd(&a.dop[id[q]], bb[q] * dalr);
-      }
-      if (sh) {
-        if (a.dcol) {
-          const int64_t cbase = (int64_t)it.view * 3 * F;
-          atomicAdd(&a.dcol[cbase + f], dcr);
-          atomicAdd(&a.dcol[cbase + F + f], dcg);
-          atomicAdd(&a.dcol[cbase + 2 * F + f], dcb);
-        }
-      } else if (a.drgb) {
+            for (int qq = 0; qq < 3; ++qq) {
+              val[L::COL + 3 * qq] = bb[qq] * dcr;
+              val[L::COL + 3 * qq + 1] = bb[qq] * dcg;
+              val[L::COL + 3 * qq + 2] = bb[qq] * dcb;
+            }
+          }
+          // camera-space corners, from pixel coordinates and depths
+          const float u[3] = {q.g0.x, q.g0.z, q.g1.x}, v[3] = {q.g0.y, q.g0.w, q.g1.y};
+          const float zz[3] = {q.g1.z, q.g1.w, q.g2.x};
+          float X[3][3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          atomicAdd(&a.drgb[id[q]], bb[q] * dcr);
-          atomicAdd(&a.drgb[V + id[q]], bb[q] * dcg);
-          atomicAdd(&a.drgb[2 * V + id[q]], bb[q] * dcb);
-        }
-      }
-      if (a.dpos) {
-        // camera-space corners
-        float X[3][3];
+          for (int qq = 0; qq < 3; ++qq) {
+            X[qq][0] = (u[qq] - c.cx) / c.fx * zz[qq];
+            X[qq][1] = (v[qq] - c.cy) / c.fy * zz[qq];
+            X[qq][2] = zz[qq];
+          }
+          const float e1[3] = {X[1][0] - X[0][0], X[1][1] - X[0][1], X[1][2] - X[0][2]};
+          const float e2[3] = {X[2][0] - X[0][0], X[2][1] - X[0][1], X[2][2] - X[0][2]};
+          const float n0 = e1[1] * e2[2] - e1[2] * e2[1];
+          const float n1 = e1[2] * e2[0] - e1[0] * e2[2];
+          const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
+          const float det = -(d0 * n0 + d1 * n1 + n2);
+          float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+          if (det != 0.f && isfinite(det)) {
+            const float gu = dLdb[1] - dLdb[0], gv = dLdb[2] - dLdb[0];
+            // (d x e2) and (e1 x d), d = (d0, d1, 1)
+            const float a0 = d1 * e2[2] - e2[1], a1 = e2[0] - d0 * e2[2], a2 = d0 * e2[1] - d1 * e2[0];
+            const float c0 = e1[1] - e1[2] * d1, c1 = e1[2] * d0 - e1[0], c2 = e1[0] * d1 - e1[1] * d0;
+            const float idt = 1.f / det;
+            w0 = (gu * a0 + gv * c0) * idt;
+            w1 = (gu * a1 + gv * c1) * idt;
+            w2 = (gu * a2 + gv * c2) * idt;
+          }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const Proj p = project(c, a.pos[id[q]], a.pos[V + id[q]], a.pos[2 * V + id[q]]);
-          X[q][0] = p.xc;
-          X[q][1] = p.yc;
-          X[q][2] = p.zc;
-        }
-        const float e1[3] = {X[1][0] - X[0][0], X[1][1] - X[0][1], X[1][2] - X[0][2]};
-        const float e2[3] = {X[2][0] - X[0][0], X[2][1] - X[0][1], X[2][2] - X[0][2]};
-        // det = -d . (e1 x e2)
-        const float n0 = e1[1] * e2[2] - e1[2] * e2[1];
-        const float n1 = e1[2] * e2[0] - e1[0] * e2[2];
-        const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
-        const float det = -(d0 * n0 + d1 * n1 + d2 * n2);
-        if (det != 0.f && isfinite(det)) {
-          const float gu = dLdb[1] - dLdb[0], gv = dLdb[2] - dLdb[0];
-          // d x e2 and e1 x d
-          const float a0 = d1 * e2[2] - d2 * e2[1], a1 = d2 * e2[0] - d0 * e2[2], a2 = d0 * e2[1] - d1 * e2[0];
-          const float c0 = e1[1] * d2 - e1[2] * d1, c1 = e1[2] * d0 - e1[0] * d2, c2 = e1[0] * d1 - e1[1] * d0;
-          const float id_ = 1.f / det;
-          const float w0 = (gu * a0 + gv * c0) * id_, w1 = (gu * a1 + gv * c1) * id_, w2 = (gu * a2 + gv * c2) * id_;
-          // world gradient of corner q: R^T (-b_q w)
-          const float g0 = Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2;
-          const float g1 = Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2;
-          const float g2 = Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2;
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            atomicAdd(&a.dpos[id[q]], -bb[q] * g0);
-            atomicAdd(&a.dpos[V + id[q]], -bb[q] * g1);
-            atomicAdd(&a.dpos[2 * V + id[q]], -bb[q] * g2);
+          for (int qq = 0; qq < 3; ++qq) {
+            val[L::POS + 3 * qq] = -bb[qq] * w0;
+            val[L::POS + 3 * qq + 1] = -bb[qq] * w1;
+            val[L::POS + 3 * qq + 2] = -bb[qq] * w2;
           }
         }
       }
+      // accumulate into the wave's table; flush it when a face finds no slot
+      bool need = act;
+      while (__any(need)) {
+        if (need) {
+          const int s = hash_slot(keys, f);
+          if (s >= 0) {
+#pragma unroll
+            for (int qq = 0; qq < L::NV; ++qq) atomicAdd(&vals[qq * kHashSlots + s], val[qq]);
+            need = false;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        if (__any(need)) flush_table<SH>(a, it.view, keys, vals, lane);
+      }
     }
+    flush_table<SH>(a, it.view, keys, vals, lane);
   }
 }
 
@@ -715,11 +929,18 @@ int persistent_grid(K kernel, int n_cu, uint32_t n_items) {
   return (int)(g < 1 ? 1 : g);
 }
 
+uint32_t n_items_of(const RasterArgs& a) {
+  return (uint32_t)(a.n_tiles * (a.tile_w / 8) * (a.tile_h / 8) * a.n_views);
+}
+
 }  // namespace
 
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a) {
   if (a.n_faces == 0) return hipSuccess;
   hipLaunchKernelGGL(k_setup, dim3(grid_for(a.n_faces, 256), a.n_views), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_face_attr, dim3(grid_for(a.n_faces, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -736,10 +957,6 @@ hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_tile_sort<8192, true>), dim3((unsigned)n_seg), dim3(256), 0, s, a, n_seg);
   return hipGetLastError();
-}
-
-static uint32_t n_items_of(const RasterArgs& a) {
-  return (uint32_t)(a.n_tiles * (a.tile_w / 8) * (a.tile_h / 8) * a.n_views);
 }
 
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
@@ -760,14 +977,26 @@ hipError_t launch_block_max(hipStream_t s, const RasterArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_backward(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
+hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
   const uint32_t n_items = n_items_of(a);
   if (kbuf == 8) {
-    const int g = persistent_grid(k_backward<8>, n_cu, n_items);
-    hipLaunchKernelGGL(k_backward<8>, dim3(g), dim3(256), 0, s, a, n_items);
+    const int g = persistent_grid(k_bwd_lists<8>, n_cu, n_items);
+    hipLaunchKernelGGL(k_bwd_lists<8>, dim3(g), dim3(256), 0, s, a, n_items);
   } else {
-    const int g = persistent_grid(k_backward<16>, n_cu, n_items);
-    hipLaunchKernelGGL(k_backward<16>, dim3(g), dim3(256), 0, s, a, n_items);
+    const int g = persistent_grid(k_bwd_lists<16>, n_cu, n_items);
+    hipLaunchKernelGGL(k_bwd_lists<16>, dim3(g), dim3(256), 0, s, a, n_items);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu) {
+  const uint32_t n_items = n_items_of(a);
+  if (a.col4) {
+    const int g = persistent_grid(k_bwd_grads<true>, n_cu, n_items);
+    hipLaunchKernelGGL(k_bwd_grads<true>, dim3(g), dim3(256), 0, s, a, n_items);
+  } else {
+    const int g = persistent_grid(k_bwd_grads<false>, n_cu, n_items);
+    hipLaunchKernelGGL(k_bwd_grads<false>, dim3(g), dim3(256), 0, s, a, n_items);
   }
   return hipGetLastError();
 }

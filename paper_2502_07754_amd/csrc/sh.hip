@@ -52,7 +52,7 @@ __device__ __forceinline__ void face_dir(const float* __restrict__ pos, int64_t 
 
 __global__ __launch_bounds__(256) void k_sh_eval(const float* __restrict__ sh, const float* __restrict__ pos,
                                                  int64_t V, const int32_t* __restrict__ idx, int64_t F, int n_views,
-                                                 ShArgs t, float* __restrict__ col) {
+                                                 ShArgs t, float4* __restrict__ col4) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   float k[48];
@@ -73,10 +73,7 @@ __global__ __launch_bounds__(256) void k_sh_eval(const float* __restrict__ sh, c
       cg = fmaf(k[3 * b + 1], Y, cg);
       cb = fmaf(k[3 * b + 2], Y, cb);
     }
-    const int64_t o = (int64_t)v * 3 * F + f;
-    col[o] = fmaxf(cr, 0.f);
-    col[o + F] = fmaxf(cg, 0.f);
-    col[o + 2 * F] = fmaxf(cb, 0.f);
+    col4[(int64_t)v * F + f] = make_float4(fmaxf(cr, 0.f), fmaxf(cg, 0.f), fmaxf(cb, 0.f), 0.f);
   }
 }
 
@@ -203,12 +200,12 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n
 
 int sh_max_views() { return kMaxViews; }
 
-hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float* col) {
+hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float4* col4) {
   if (f->n_faces == 0) return hipSuccess;
   ShArgs t;
   if (!make_table(h_cams, n_views, t)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sh_eval, dim3(grid_for(f->n_faces)), dim3(256), 0, s, f->sh, f->pos, f->n_verts, f->idx,
-                     f->n_faces, n_views, t, col);
+                     f->n_faces, n_views, t, col4);
   return hipGetLastError();
 }
 
