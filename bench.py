@@ -79,8 +79,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=500_000, help="Gaussians")
     ap.add_argument("--views", type=int, default=8)
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--kbuf", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="0: autotuned")
+    ap.add_argument("--kbuf", type=int, default=0, help="0: autotuned")
+    ap.add_argument("--no-graph", action="store_true", help="eager calls instead of the captured step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -106,12 +107,25 @@ def main():
     faces = msp.convert(gg, K, sigma)
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     opts = msp.RenderOptions(tile_w=args.tile, tile_h=args.tile, kbuf=args.kbuf, t_eps=1e-6, color_mode=1)
+    if args.tile == 0 or args.kbuf == 0:
+        t0 = time.perf_counter()
+        tuned = msp.autotune(faces, cams, opts, dimg)
+        log(f"autotuned tile {tuned.tile_w}x{tuned.tile_h}, kbuf {tuned.kbuf} in {time.perf_counter() - t0:.1f} s")
+        opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=args.tile or tuned.tile_h,
+                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=1)
     state = msp.RenderState(ctx)
+    if args.no_graph:
+        def step():
+            img, _ = msp.render(faces, cams, opts, state=state)
+            grads = msp.render_backward(state, faces, dimg)
+            return img, grads
+    else:
+        gstep = msp.GraphStep(faces, cams, opts)
+        gstep.dimg.copy_(dimg)
+        state = gstep.state
 
-    def step():
-        img, _ = msp.render(faces, cams, opts, state=state)
-        grads = msp.render_backward(state, faces, dimg)
-        return img, grads
+        def step():
+            return gstep()
 
     for _ in range(args.warmup):
         step()
@@ -125,6 +139,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = ctx.read_timing()
+    if not args.no_graph:
+        # stage times of the graph replays are not event-bracketed: take them from one eager step
+        img, st_ = msp.render(faces, cams, opts)
+        msp.render_backward(st_, faces, dimg)
+        torch.cuda.synchronize()
+        stages = ctx.read_timing()
+        stages = {k: (v[0] * args.steps, v[1] * args.steps) for k, v in stages.items()}
+        log(f"graph: {gstep.info()}")
     st = state.stats()
     dt = (t1 - t0) / args.steps
     pix = args.views * W * H
@@ -167,7 +189,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.n} flat Gaussians, K={K}, sigma={sigma}, SH degree 3, {args.views} views "
                                f"{W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
-                   "faces": int(faces["idx"].shape[1]), "tile": args.tile, "kbuf": args.kbuf,
+                   "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
+                   "hip_graph": not args.no_graph,
                    "entries_per_step": entries, "fragments_per_step": frags,
                    "fragments_per_s": frags / dt},
         "roofline": roof,

@@ -174,6 +174,32 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
 msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
                                msp_face_grads* grads);
 
+/* ---- captured steps and tuning ------------------------------------------ */
+
+/* One forward + backward step (msp_render then msp_render_backward with the
+ * same arguments) replayed as a captured HIP graph. The first call, and any
+ * call whose faces, cameras, options or buffers differ from the captured ones,
+ * runs the step uncaptured (which sizes the tile lists and fragment lists),
+ * then captures it with 1.5x those capacities. Later calls replay the graph
+ * and synchronise once to read an overflow flag; if the scene grew past a
+ * capacity, the step is re-run uncaptured and captured again, so the result is
+ * always complete. Results are as with msp_render / msp_render_backward. */
+msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                          const msp_render_opts* opts, float* img, const float* dimg, msp_face_grads* grads,
+                          msp_state* st);
+/* Graph counters of a state: captures made, replays completed, replays that overflowed. */
+msp_status msp_graph_info(msp_ctx* ctx, msp_state* st, int64_t* captures, int64_t* replays, int64_t* overflows);
+
+/* Times one render (and one backward when dimg is not NULL) for each candidate
+ * tile size (8x8, 16x16, 32x16, 32x32) and ordering-buffer depth (8, 16),
+ * keeping the other fields of `base`; writes the fastest options to `out` and
+ * makes them the context's defaults for tile_w = tile_h = kbuf = 0. img and
+ * grads are scratch outputs sized as for msp_render / msp_render_backward.
+ * Synchronises. */
+msp_status msp_autotune(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                        const msp_render_opts* base, float* img, const float* dimg, msp_face_grads* grads,
+                        msp_render_opts* out);
+
 /* ---- per-stage timing ------------------------------------------------- */
 
 /* Number of timed stages. Index: 0 convert, 1 SH colour, 2 setup (projection,

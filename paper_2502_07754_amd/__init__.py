@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import MspError
 
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
-           "camera_struct", "load_library"]
+           "camera_struct", "load_library", "GraphStep", "autotune"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -200,6 +200,88 @@ def render_backward(state: RenderState, faces: dict, dimg, need=("dpos", "dopaci
     ctx.check(ctx.lib.msp_render_backward(ctx.h, state.h, C.byref(Fc), _dev_ptr(dimg), C.byref(G)),
               "msp_render_backward")
     return out
+
+
+def _grads_for(state, faces, sh_mode, need=("dpos", "dopacity", "drgb", "dsh")) -> dict:
+    import torch
+    nv = faces["pos"].shape[1]
+    dev = faces["pos"].device
+    out = {}
+    if "dpos" in need:
+        out["dpos"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
+    if "dopacity" in need:
+        out["dopacity"] = torch.empty((nv,), dtype=torch.float32, device=dev)
+    if "drgb" in need and not sh_mode:
+        out["drgb"] = torch.empty((3, nv), dtype=torch.float32, device=dev)
+    if "dsh" in need and sh_mode:
+        out["dsh"] = torch.empty((48, faces["idx"].shape[1]), dtype=torch.float32, device=dev)
+    return out
+
+
+class GraphStep:
+    """A forward + backward step replayed as a captured HIP graph (msp_step_graph).
+
+    The image and gradient buffers are owned by this object and reused by every
+    call (the graph is bound to their addresses)."""
+
+    def __init__(self, faces: dict, cams, opts: "RenderOptions", dimg_shape=None):
+        import torch
+        pos = _need(faces["pos"], torch.float32, "pos")
+        self.ctx = _ctx(pos)
+        self.faces = faces
+        self.cams = cams
+        self.opts = opts
+        V, H, W = len(cams), int(cams[0].height), int(cams[0].width)
+        self.img = torch.empty((V, 4, H, W), dtype=torch.float32, device=pos.device)
+        self.dimg = torch.zeros((V, 4, H, W), dtype=torch.float32, device=pos.device)
+        self.state = RenderState(self.ctx)
+        self.state.n_views, self.state.height, self.state.width = V, H, W
+        self.state.color_mode = opts.color_mode
+        self.grads = _grads_for(self.state, faces, opts.color_mode == MSP_COLOR_SH3)
+        self._arr = (_lib.Camera * V)(*[camera_struct(c) for c in cams])
+        self._F = _faces_struct(faces)
+        self._G = _lib.FaceGrads(_dev_ptr(self.grads.get("dpos")), _dev_ptr(self.grads.get("dopacity")),
+                                 _dev_ptr(self.grads.get("drgb")), _dev_ptr(self.grads.get("dsh")))
+        self._o = opts.struct()
+
+    def __call__(self, dimg=None):
+        """Runs one step; `dimg` (if given) is copied into the bound upstream-gradient buffer first."""
+        if dimg is not None:
+            self.dimg.copy_(dimg)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_step_graph(self.ctx.h, C.byref(self._F), self._arr, len(self.cams),
+                                                   C.byref(self._o), _dev_ptr(self.img), _dev_ptr(self.dimg),
+                                                   C.byref(self._G), self.state.h), "msp_step_graph")
+        return self.img, self.grads
+
+    def info(self) -> dict:
+        c, r, o = C.c_int64(), C.c_int64(), C.c_int64()
+        self.ctx.check(self.ctx.lib.msp_graph_info(self.ctx.h, self.state.h, C.byref(c), C.byref(r), C.byref(o)),
+                       "msp_graph_info")
+        return dict(captures=c.value, replays=r.value, overflows=o.value)
+
+
+def autotune(faces: dict, cams, base: "RenderOptions", dimg=None) -> "RenderOptions":
+    """msp_autotune: the fastest tile size / buffer depth for this scene and view set."""
+    import torch
+    pos = _need(faces["pos"], torch.float32, "pos")
+    ctx = _ctx(pos)
+    ctx.bind_stream()
+    V, H, W = len(cams), int(cams[0].height), int(cams[0].width)
+    img = torch.empty((V, 4, H, W), dtype=torch.float32, device=pos.device)
+    sh_mode = base.color_mode == MSP_COLOR_SH3
+    grads = _grads_for(None, faces, sh_mode) if dimg is not None else {}
+    G = _lib.FaceGrads(_dev_ptr(grads.get("dpos")), _dev_ptr(grads.get("dopacity")), _dev_ptr(grads.get("drgb")),
+                       _dev_ptr(grads.get("dsh")))
+    arr = (_lib.Camera * V)(*[camera_struct(c) for c in cams])
+    out = _lib.RenderOpts()
+    Fc = _faces_struct(faces)
+    b = base.struct()
+    ctx.check(ctx.lib.msp_autotune(ctx.h, C.byref(Fc), arr, V, C.byref(b), _dev_ptr(img),
+                                   None if dimg is None else _dev_ptr(_need(dimg, torch.float32, "dimg")),
+                                   C.byref(G), C.byref(out)), "msp_autotune")
+    return RenderOptions(tile_w=out.tile_w, tile_h=out.tile_h, kbuf=out.kbuf, t_eps=out.t_eps,
+                         bg=tuple(out.bg), color_mode=out.color_mode)
 
 
 def _autograd():

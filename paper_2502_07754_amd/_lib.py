@@ -64,6 +64,12 @@ EXPORTS = {
     "msp_state_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RenderStats)]),
     "msp_debug_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "msp_debug_nfrag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "msp_step_graph": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),
+                                 C.c_void_p, C.c_void_p, C.POINTER(FaceGrads), C.c_void_p]),
+    "msp_graph_info": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64)]),
+    "msp_autotune": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),
+                               C.c_void_p, C.c_void_p, C.POINTER(FaceGrads), C.POINTER(RenderOpts)]),
     "msp_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "msp_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }

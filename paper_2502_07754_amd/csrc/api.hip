@@ -67,14 +67,14 @@ struct StageTimer {
 
 void timer_begin(msp_ctx* ctx, int stage) {
   StageTimer* t = ctx->timer;
-  if (!t || !t->on) return;
+  if (!t || !t->on || ctx->capturing) return;
   hipEvent_t e = t->get();
   if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->open[stage] = e;
 }
 
 void timer_end(msp_ctx* ctx, int stage) {
   StageTimer* t = ctx->timer;
-  if (!t || !t->on || !t->open[stage]) return;
+  if (!t || !t->on || ctx->capturing || !t->open[stage]) return;
   hipEvent_t e = t->get();
   if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->done.push_back({stage, t->open[stage], e});
   t->open[stage] = nullptr;
@@ -212,9 +212,18 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
   return MSP_OK;
 }
 
+static void free_graph(msp_state* st);
+
 msp_status msp_state_create(msp_ctx* ctx, msp_state** out) {
   if (!ctx || !out) return MSP_EINVAL;
-  *out = new msp_state();
+  DeviceGuard dg(ctx->device);
+  msp_state* st = new msp_state();
+  if (hipHostMalloc((void**)&st->h_flag, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    delete st;
+    return (msp_status)msp_fail(ctx, MSP_ENOMEM, "hipHostMalloc of the overflow flag failed");
+  }
+  *st->h_flag = 0;
+  *out = st;
   return MSP_OK;
 }
 
@@ -227,6 +236,8 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
                     &st->blk_off, &st->frag_list, &st->col4, &st->dcol};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  free_graph(st);
+  if (st->h_flag) (void)hipHostFree(st->h_flag);
   delete[] st->h_cams;
   delete st;
   return MSP_OK;
@@ -266,10 +277,29 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.bg2 = st->bg[2];
   a.nfrag = P<int32_t>(st->nfrag);
   a.counters = P<unsigned long long>(st->counters);
+  a.ovf = reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5);
 }
+
+static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                              const msp_render_opts* opts, float* img, msp_state* st, bool graph);
+static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
+                                msp_face_grads* grads, bool graph);
 
 msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
                       const msp_render_opts* opts, float* img, msp_state* st) {
+  return render_impl(ctx, f, cams, n_views, opts, img, st, false);
+}
+
+msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
+                               msp_face_grads* grads) {
+  return backward_impl(ctx, st, f, dimg, grads, false);
+}
+
+// In graph mode nothing may synchronise or allocate: buffer capacities come from
+// an earlier uncaptured run, and a guard kernel raises the overflow flag (which
+// makes every later kernel of the step return at once) when a capacity is short.
+static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                              const msp_render_opts* opts, float* img, msp_state* st, bool graph) {
   if (!ctx) return MSP_EINVAL;
   auto bad = [&](const char* m) { return (msp_status)msp_fail(ctx, MSP_EINVAL, std::string("msp_render: ") + m); };
   if (!f || !cams || !opts || !img || !st) return bad("null argument");
@@ -330,7 +360,7 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   }
   std::memcpy(st->h_cams, cams, sizeof(msp_camera) * n_views);
   hipStream_t s = ctx->stream;
-  MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
+  if (!graph) MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->tile_cnt), 0u, NT));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->vis_cnt), 0u, V));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
@@ -344,11 +374,15 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   a.img = img;
   MSP_TIMED(ctx, ST_SETUP, launch_setup(s, a));
   MSP_TIMED(ctx, ST_SCAN, launch_scan_u32(s, a.tile_cnt, a.tile_off, NT, st->scan_part.p));
-  int64_t E = 0;
-  MSP_HIP(ctx, hipMemcpyAsync(&E, a.tile_off + NT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  MSP_HIP(ctx, hipStreamSynchronize(s));
-  if ((rc = msp_ensure(ctx, st->keys, 8 * E)) || (rc = msp_ensure(ctx, st->tmp, 8 * E))) return (msp_status)rc;
-  st->entries = E;
+  if (graph) {
+    MSP_HIP(ctx, launch_cap_guard(s, a.tile_off + NT, (int64_t)(st->keys.bytes / 8), a.ovf, 1u));
+  } else {
+    int64_t E = 0;
+    MSP_HIP(ctx, hipMemcpyAsync(&E, a.tile_off + NT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP(ctx, hipStreamSynchronize(s));
+    if ((rc = msp_ensure(ctx, st->keys, 8 * E)) || (rc = msp_ensure(ctx, st->tmp, 8 * E))) return (msp_status)rc;
+    st->entries = E;
+  }
   fill_args(st, f, a);
   a.img = img;
   MSP_HIP(ctx, launch_fill_u32(s, a.cursor, 0u, NT));
@@ -359,8 +393,8 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
   return MSP_OK;
 }
 
-msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
-                               msp_face_grads* grads) {
+static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
+                                msp_face_grads* grads, bool graph) {
   if (!ctx) return MSP_EINVAL;
   auto bad = [&](const char* m) {
     return (msp_status)msp_fail(ctx, MSP_EINVAL, std::string("msp_render_backward: ") + m);
@@ -390,12 +424,18 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
   a.blk_off = P<int64_t>(st->blk_off);
   MSP_TIMED(ctx, ST_BLOCK_MAX, launch_block_max(s, a));
   MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
-  int64_t rows = 0;
-  MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  MSP_HIP(ctx, hipStreamSynchronize(s));
-  if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * (rows > 0 ? rows : 1)))) return (msp_status)rc;
+  if (graph) {
+    MSP_HIP(ctx, launch_cap_guard(s, P<int64_t>(st->blk_off) + nb, (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE)),
+                                  a.ovf, 2u));
+  } else {
+    int64_t rows = 0;
+    MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP(ctx, hipStreamSynchronize(s));
+    if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * (rows > 0 ? rows : 1)))) return (msp_status)rc;
+    st->rows = rows;
+  }
   a.frag_list = P<uint2>(st->frag_list);
-  a.frag_cap = rows;
+  a.frag_cap = (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE));
   a.dimg = dimg;
   a.dpos = grads->dpos;
   a.dop = grads->dopacity;
@@ -412,6 +452,161 @@ msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, 
   MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
   if (shm && grads->dsh)
     MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
+  return MSP_OK;
+}
+
+static bool same_key(const std::vector<unsigned char>& k, const std::vector<unsigned char>& m) { return k == m; }
+
+}  // extern "C"
+
+template <class T>
+static void put(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+extern "C" {
+
+static void free_graph(msp_state* st) {
+  if (st->graph_exec) (void)hipGraphExecDestroy(st->graph_exec);
+  if (st->graph) (void)hipGraphDestroy(st->graph);
+  st->graph_exec = nullptr;
+  st->graph = nullptr;
+  st->graph_key.clear();
+}
+
+static msp_status capture_step(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                               const msp_render_opts* opts, float* img, const float* dimg, msp_face_grads* grads,
+                               msp_state* st) {
+  hipStream_t s = ctx->stream;
+  free_graph(st);
+  // capacities with headroom over the uncaptured run that just sized them
+  int rc;
+  const int64_t ecap = st->entries + st->entries / 2 + 1024;
+  const int64_t rcap = st->rows + st->rows / 2 + 64;
+  if ((rc = msp_ensure(ctx, st->keys, 8 * ecap)) || (rc = msp_ensure(ctx, st->tmp, 8 * ecap)) ||
+      (rc = msp_ensure(ctx, st->frag_list, 8 * MSP_WAVE * rcap)))
+    return (msp_status)rc;
+  MSP_HIP(ctx, hipStreamSynchronize(s));
+  MSP_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  ctx->capturing = true;
+  msp_status r1 = render_impl(ctx, f, cams, n_views, opts, img, st, true);
+  msp_status r2 = r1 == MSP_OK ? backward_impl(ctx, st, f, dimg, grads, true) : r1;
+  ctx->capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (r1 != MSP_OK || r2 != MSP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r1 != MSP_OK ? r1 : r2;
+  }
+  if (e != hipSuccess) return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  st->graph = g;
+  e = hipGraphInstantiate(&st->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    free_graph(st);
+    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return MSP_OK;
+}
+
+msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                          const msp_render_opts* opts, float* img, const float* dimg, msp_face_grads* grads,
+                          msp_state* st) {
+  if (!ctx) return MSP_EINVAL;
+  if (!f || !cams || !opts || !img || !dimg || !grads || !st || n_views < 1)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_step_graph: null argument or n_views < 1");
+  DeviceGuard dg(ctx->device);
+  std::vector<unsigned char> key;
+  put(key, *f);
+  put(key, *opts);
+  put(key, *grads);
+  put(key, img);
+  put(key, dimg);
+  put(key, n_views);
+  for (int v = 0; v < n_views; ++v) put(key, cams[v]);
+  hipStream_t s = ctx->stream;
+  if (st->graph_exec && same_key(st->graph_key, key) && st->graph_stream == s) {
+    MSP_HIP(ctx, hipGraphLaunch(st->graph_exec, s));
+    uint32_t ovf = 0;
+    MSP_HIP(ctx, hipMemcpyAsync(st->h_flag, P<unsigned long long>(st->counters) + 5, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    MSP_HIP(ctx, hipStreamSynchronize(s));
+    ovf = *st->h_flag;
+    if (ovf == 0) {
+      ++st->graph_replays;
+      return MSP_OK;
+    }
+    ++st->graph_overflows;  // a capacity was short: run uncaptured and capture again
+  }
+  msp_status r = render_impl(ctx, f, cams, n_views, opts, img, st, false);
+  if (r != MSP_OK) return r;
+  r = backward_impl(ctx, st, f, dimg, grads, false);
+  if (r != MSP_OK) return r;
+  r = capture_step(ctx, f, cams, n_views, opts, img, dimg, grads, st);
+  if (r != MSP_OK) return r;
+  st->graph_key = key;
+  st->graph_stream = s;
+  ++st->graph_captures;
+  return MSP_OK;
+}
+
+msp_status msp_autotune(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
+                        const msp_render_opts* base, float* img, const float* dimg, msp_face_grads* grads,
+                        msp_render_opts* out) {
+  if (!ctx) return MSP_EINVAL;
+  if (!f || !cams || !base || !img || !out || n_views < 1 || (dimg && !grads))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_autotune: null argument or n_views < 1");
+  DeviceGuard dg(ctx->device);
+  static const int cand[][3] = {{8, 8, 16}, {16, 16, 16}, {32, 16, 16}, {32, 32, 16}, {16, 16, 8}, {32, 16, 8}};
+  msp_state* st = nullptr;
+  msp_status r = msp_state_create(ctx, &st);
+  if (r != MSP_OK) return r;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    msp_state_free(ctx, st);
+    return (msp_status)msp_fail(ctx, MSP_EHIP, "msp_autotune: hipEventCreate");
+  }
+  float best = 1e30f;
+  msp_render_opts best_o = *base;
+  const bool timer_on = ctx->timer && ctx->timer->on;
+  if (timer_on) ctx->timer->on = false;
+  for (const auto& c : cand) {
+    msp_render_opts o = *base;
+    o.tile_w = c[0];
+    o.tile_h = c[1];
+    o.kbuf = c[2];
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && r == MSP_OK; ++rep) {  // rep 0 warms up and sizes the scratch
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) r = MSP_EHIP;
+      if (r == MSP_OK) r = render_impl(ctx, f, cams, n_views, &o, img, st, false);
+      if (r == MSP_OK && dimg) r = backward_impl(ctx, st, f, dimg, grads, false);
+      if (r == MSP_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) r = MSP_EHIP;
+      if (r == MSP_OK && hipEventSynchronize(e1) != hipSuccess) r = MSP_EHIP;
+      if (r == MSP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) r = MSP_EHIP;
+    }
+    if (r != MSP_OK) break;
+    if (ms < best) {
+      best = ms;
+      best_o = o;
+    }
+  }
+  if (timer_on) ctx->timer->on = true;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  msp_state_free(ctx, st);
+  if (r != MSP_OK) return r;
+  *out = best_o;
+  ctx->tuned_tile_w = best_o.tile_w;
+  ctx->tuned_tile_h = best_o.tile_h;
+  ctx->tuned_kbuf = best_o.kbuf;
+  return MSP_OK;
+}
+
+msp_status msp_graph_info(msp_ctx* ctx, msp_state* st, int64_t* captures, int64_t* replays, int64_t* overflows) {
+  if (!ctx || !st || !captures || !replays || !overflows) return MSP_EINVAL;
+  *captures = st->graph_captures;
+  *replays = st->graph_replays;
+  *overflows = st->graph_overflows;
   return MSP_OK;
 }
 

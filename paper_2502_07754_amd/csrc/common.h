@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "msp.h"
 
@@ -26,6 +27,7 @@ struct msp_ctx {
   std::string err;
   // autotuned tile choice per (n_faces bucket, width, height, n_views), filled by msp_autotune
   int tuned_tile_w = 0, tuned_tile_h = 0, tuned_kbuf = 0;
+  bool capturing = false;
 };
 
 struct msp_state {
@@ -41,6 +43,14 @@ struct msp_state {
   bool rendered = false;
   msp_camera* h_cams = nullptr;  // host copy
   int h_cams_cap = 0;
+  int64_t rows = 0;              // backward list rows of the last uncaptured run
+  // captured fwd+bwd step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t graph_stream = nullptr;
+  std::vector<unsigned char> graph_key;
+  uint32_t* h_flag = nullptr;    // pinned host copy of the overflow flag
+  int64_t graph_captures = 0, graph_replays = 0, graph_overflows = 0;
 
   DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
       scan_part, blk_cap, blk_off, frag_list, col4, dcol;
@@ -93,6 +103,7 @@ struct RasterArgs {
   float* img;              // [V][4][H][W]
   int32_t* nfrag;          // [V][H][W]
   unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd list queue, [4] bwd grad queue
+  uint32_t* ovf;           // overflow flag (low word of counters[5]); set: kernels of the step return at once
   // backward
   const float* dimg;
   const int64_t* blk_off;  // [n_blocks + 1] in units of 64-slot rows
@@ -111,6 +122,7 @@ hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_
                          float* dsh, float* dpos);
 
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a);
+hipError_t launch_cap_guard(hipStream_t s, const int64_t* total, int64_t cap, uint32_t* flag, uint32_t bit);
 hipError_t launch_emit(hipStream_t s, const RasterArgs& a);
 hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a);
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);

@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
 // emit: scatter keys into the tile segments
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
+  if (*a.ovf) return;
   const int view = blockIdx.y;
   const int64_t F = a.n_faces;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -287,7 +288,7 @@ template <int CAP, bool BIG>
 __global__ __launch_bounds__(256) void k_tile_sort(RasterArgs a, int64_t n_seg) {
   __shared__ uint64_t s[CAP];
   const int64_t seg = blockIdx.x;
-  if (seg >= n_seg) return;
+  if (seg >= n_seg || *a.ovf) return;
   const int64_t beg = a.tile_off[seg];
   const int64_t n = a.tile_off[seg + 1] - beg;
   if (n <= 1) return;
@@ -531,10 +532,16 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       drop = ~0ull;
       ++restarts;
     }
-    Prefetch pf = prefetch_entry(a, it, beg, n, lane);
+    uint64_t next_key = lane < n ? a.keys[beg + lane] : ~0ull;
     for (int64_t base = 0; base < n; base += MSP_WAVE) {
       if (!__any(state == ACTIVE)) break;
       // ---- stage this chunk (ballot-compacted to faces meeting the block) ----
+      Prefetch pf;
+      pf.key = next_key;
+      pf.ok = base + lane < n && (uint64_t)(uint32_t)pf.key < (uint64_t)a.n_faces;
+      pf.q = fetch_face(a, it.view, pf.ok ? (int32_t)(uint32_t)pf.key : 0);
+      // the next chunk's keys are fetched while this one is processed
+      next_key = base + MSP_WAVE + lane < n ? a.keys[beg + base + MSP_WAVE + lane] : ~0ull;
       bool keep = false;
       float R[kRec];
       if (pf.ok) {
@@ -552,8 +559,6 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      // ---- fetch the next chunk while this one is processed ----
-      pf = prefetch_entry(a, it, beg, n, base + MSP_WAVE + lane);
       // ---- stream the staged faces in nearest-depth order ----
       for (int j = 0; j < cnt; ++j) {
         const float* S = slab + j * kRec;
@@ -627,6 +632,7 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint64_t frags = 0;
   uint32_t restarts = 0;
+  if (*a.ovf) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[2], 1ull);
@@ -681,6 +687,7 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint32_t restarts = 0;
+  if (*a.ovf) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[3], 1ull);
@@ -784,6 +791,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  if (*a.ovf) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[4], 1ull);
@@ -914,6 +922,10 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   }
 }
 
+__global__ void k_cap_guard(const int64_t* total, int64_t cap, uint32_t* flag, uint32_t bit) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *total > cap) atomicOr(flag, bit);
+}
+
 inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -934,6 +946,11 @@ uint32_t n_items_of(const RasterArgs& a) {
 }
 
 }  // namespace
+
+hipError_t launch_cap_guard(hipStream_t s, const int64_t* total, int64_t cap, uint32_t* flag, uint32_t bit) {
+  hipLaunchKernelGGL(k_cap_guard, dim3(1), dim3(64), 0, s, total, cap, flag, bit);
+  return hipGetLastError();
+}
 
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a) {
   if (a.n_faces == 0) return hipSuccess;
