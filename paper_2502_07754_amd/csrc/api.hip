@@ -135,6 +135,7 @@ msp_status msp_destroy(msp_ctx* ctx) {
     for (hipEvent_t e : ctx->timer->pool) (void)hipEventDestroy(e);
     delete ctx->timer;
   }
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return MSP_OK;
 }
@@ -488,13 +489,18 @@ static msp_status capture_step(msp_ctx* ctx, const msp_faces* f, const msp_camer
       (rc = msp_ensure(ctx, st->frag_list, 8 * MSP_WAVE * rcap)))
     return (msp_status)rc;
   MSP_HIP(ctx, hipStreamSynchronize(s));
-  MSP_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  // capture on a private non-blocking stream (the legacy default stream cannot capture);
+  // the graph is launched on the caller's stream
+  if (!ctx->cap_stream) MSP_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  MSP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
   ctx->capturing = true;
+  ctx->stream = ctx->cap_stream;
   msp_status r1 = render_impl(ctx, f, cams, n_views, opts, img, st, true);
   msp_status r2 = r1 == MSP_OK ? backward_impl(ctx, st, f, dimg, grads, true) : r1;
+  ctx->stream = s;
   ctx->capturing = false;
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s, &g);
+  hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
   if (r1 != MSP_OK || r2 != MSP_OK) {
     if (g) (void)hipGraphDestroy(g);
     return r1 != MSP_OK ? r1 : r2;

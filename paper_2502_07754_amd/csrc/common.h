@@ -28,6 +28,7 @@ struct msp_ctx {
   // autotuned tile choice per (n_faces bucket, width, height, n_views), filled by msp_autotune
   int tuned_tile_w = 0, tuned_tile_h = 0, tuned_kbuf = 0;
   bool capturing = false;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
 };
 
 struct msp_state {
