@@ -120,6 +120,25 @@ def upstream_grad(n_views: int, height: int, width: int, seed: int, scale: float
     return _f32(rng.standard_normal(size=(n_views, 4, height, width)) * scale)
 
 
+def perturbed(g: Gaussians, seed: int) -> Gaussians:
+    """Seeded perturbation of a scene, used to make fine-tuning targets:
+    m += N(0, (0.25 s_max)^2); log s += N(0, 0.1^2) (zero scales stay zero);
+    opacity logit += N(0, 0.25^2); rgb += N(0, 0.05^2) clipped to [0, 1]."""
+    rng = np.random.default_rng(seed)
+    mean = np.asarray(g.mean, np.float64)
+    scale = np.asarray(g.scale, np.float64)
+    n = mean.shape[1]
+    smax = scale.max(axis=0)
+    mean = mean + rng.normal(0, 1, (3, n)) * 0.25 * smax
+    scale = scale * np.exp(rng.normal(0, 0.1, (3, n)))
+    o = np.clip(np.asarray(g.opacity, np.float64), 1e-6, 1 - 1e-6)
+    logit = np.log(o / (1 - o)) + rng.normal(0, 0.25, n)
+    op = 1 / (1 + np.exp(-logit))
+    rgb = np.clip(np.asarray(g.rgb, np.float64) + rng.normal(0, 0.05, (3, n)), 0, 1)
+    return Gaussians(mean=_f32(mean), scale=_f32(scale), quat=g.quat.copy(), opacity=_f32(op), rgb=_f32(rgb),
+                     sh=None if g.sh is None else g.sh.copy())
+
+
 # ---------------------------------------------------------------------------
 # The five workload shapes of the hot path (sizes as stated with the metric).
 # ---------------------------------------------------------------------------
