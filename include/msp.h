@@ -174,6 +174,62 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
 msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
                                msp_face_grads* grads);
 
+/* ---- fine-tuning (fine-tuning section: loss, optimiser, pruning) ---------- */
+
+enum { MSP_LOSS_MSE = 0, MSP_LOSS_L1 = 1, MSP_LOSS_L1_DSSIM = 2 };
+
+/* Image loss against targets and its gradient (Eq. loss of the fine-tuning
+ * section, read as lambda L1 + (1 - lambda) (1 - SSIM)).
+ * img: [V][4][H][W] rendered RGBA (the alpha plane is ignored); tgt: [V][3][H][W].
+ * MSE and L1 are means over V x 3 x H x W values; SSIM follows Wang et al.
+ * (2004): 11x11 Gaussian window, sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, valid
+ * windows only, mean over windows, channels and views (needs H, W >= 11, else
+ * the SSIM term is left out). loss_out: DEVICE float (written). dimg: DEVICE
+ * [V][4][H][W] dL/dimg written (alpha plane zero), or NULL. lambda is used by
+ * MSP_LOSS_L1_DSSIM only. Asynchronous. EINVAL on bad sizes or kind. */
+msp_status msp_loss(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views, int height,
+                    int width, float* loss_out, float* dimg);
+
+/* One parameter group of an Adam step (Kingma & Ba 2015, with bias correction):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), then p is clamped
+ * to [lo, hi] when clamp != 0 (opacities: [0, 1]). All arrays DEVICE, n floats. */
+typedef struct msp_adam_group {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+  float lo, hi;
+  int32_t clamp;
+} msp_adam_group;
+
+/* Adam update of every group in place; step counts from 1. Asynchronous. */
+msp_status msp_adam_step(msp_ctx* ctx, const msp_adam_group* groups, int n_groups, int step, float beta1, float beta2,
+                         float eps);
+
+/* Pruning (last paragraph of the fine-tuning section): a face is removed when
+ * all three of its vertex opacities are < thresh; then every vertex no kept
+ * face uses is removed. Survivors keep their relative order; face indices are
+ * renumbered. Rewrites IN PLACE, packed for the new sizes (row r of a [rows][n]
+ * array starts at r * n_new): f->pos, opacity, rgb (if set), idx, gid (if
+ * set), sh (if set), and each extra per-vertex array vstate[i] of
+ * vstate_rows[i] rows (e.g. optimiser moments). Updates f->n_verts/n_faces and
+ * writes the new sizes to *new_verts / *new_faces. Synchronises. */
+msp_status msp_prune(msp_ctx* ctx, msp_faces* f, float thresh, float* const* vstate, const int* vstate_rows,
+                     int n_vstate, int64_t* new_verts, int64_t* new_faces);
+
+/* Multi-ring conversion used to render fine-tuning targets: per Gaussian a
+ * centre vertex and `rings` rings of K vertices at radii sigma_max j / rings
+ * (j = 1..rings, in units of the two largest scales, same axes and angles as
+ * msp_convert), vertex opacity opacity exp(-r^2/2); faces: the centre fan to
+ * ring 1, then two triangles per quad between consecutive rings. Sizes:
+ * n (1 + rings K) vertices, n K (2 rings - 1) faces. K in [3, 64], rings in
+ * [1, 16]. */
+msp_status msp_rings_size(int64_t n, int K, int rings, int64_t* n_verts, int64_t* n_faces);
+msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int rings, float sigma_max, msp_faces* out);
+
 /* ---- captured steps and tuning ------------------------------------------ */
 
 /* One forward + backward step (msp_render then msp_render_backward with the

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import MspError
 
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
-           "camera_struct", "load_library", "GraphStep", "autotune"]
+           "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -282,6 +282,100 @@ def autotune(faces: dict, cams, base: "RenderOptions", dimg=None) -> "RenderOpti
                                    C.byref(G), C.byref(out)), "msp_autotune")
     return RenderOptions(tile_w=out.tile_w, tile_h=out.tile_h, kbuf=out.kbuf, t_eps=out.t_eps,
                          bg=tuple(out.bg), color_mode=out.color_mode)
+
+
+MSP_LOSS_MSE, MSP_LOSS_L1, MSP_LOSS_L1_DSSIM = 0, 1, 2
+
+
+def loss(img, tgt, kind=MSP_LOSS_MSE, lam=0.6, want_grad=True):
+    """msp_loss: (loss as a 1-element GPU tensor, dL/dimg [V,4,H,W] or None)."""
+    import torch
+    _need(img, torch.float32, "img")
+    _need(tgt, torch.float32, "tgt")
+    ctx = _ctx(img)
+    ctx.bind_stream()
+    V, _, H, W = img.shape
+    out = torch.empty((1,), dtype=torch.float32, device=img.device)
+    dimg = torch.empty_like(img) if want_grad else None
+    ctx.check(ctx.lib.msp_loss(ctx.h, kind, float(lam), _dev_ptr(img), _dev_ptr(tgt), V, H, W, _dev_ptr(out),
+                               _dev_ptr(dimg)), "msp_loss")
+    return out, dimg
+
+
+def adam_step(groups: list, step: int, beta1=0.9, beta2=0.999, eps=1e-8):
+    """msp_adam_step; each group: dict(param, grad, m, v, lr, clamp=(lo, hi) or None)."""
+    import torch
+    if not groups:
+        return
+    ctx = _ctx(groups[0]["param"])
+    ctx.bind_stream()
+    arr = (_lib.AdamGroup * len(groups))()
+    for i, g in enumerate(groups):
+        for k in ("param", "grad", "m", "v"):
+            _need(g[k], torch.float32, k)
+        cl = g.get("clamp")
+        arr[i] = _lib.AdamGroup(_dev_ptr(g["param"]), _dev_ptr(g["grad"]), _dev_ptr(g["m"]), _dev_ptr(g["v"]),
+                                g["param"].numel(), float(g["lr"]), float(cl[0]) if cl else 0.0,
+                                float(cl[1]) if cl else 0.0, 1 if cl else 0)
+    ctx.check(ctx.lib.msp_adam_step(ctx.h, arr, len(groups), int(step), beta1, beta2, eps), "msp_adam_step")
+
+
+def prune(faces: dict, thresh: float, vstate: list = ()):
+    """msp_prune in place; returns (faces dict, vstate list) as views sized for the survivors."""
+    import torch
+    pos = _need(faces["pos"], torch.float32, "pos")
+    ctx = _ctx(pos)
+    ctx.bind_stream()
+    Fc = _faces_struct(faces)
+    n = len(vstate)
+    ptrs = (C.c_void_p * max(1, n))(*[t.data_ptr() for t in vstate])
+    rows = (C.c_int * max(1, n))(*[int(t.shape[0]) if t.dim() == 2 else 1 for t in vstate])
+    nv, nf = C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.msp_prune(ctx.h, C.byref(Fc), float(thresh), ptrs, rows, n, C.byref(nv), C.byref(nf)),
+              "msp_prune")
+    V2, F2 = nv.value, nf.value
+
+    def pack(t, r, m):
+        flat = t.view(-1)[: r * m]
+        return flat.view(r, m) if t.dim() == 2 else flat
+
+    out = dict(faces)
+    out["pos"] = pack(faces["pos"], 3, V2)
+    out["opacity"] = pack(faces["opacity"], 1, V2)
+    if faces.get("rgb") is not None:
+        out["rgb"] = pack(faces["rgb"], 3, V2)
+    out["idx"] = pack(faces["idx"], 3, F2)
+    if faces.get("gid") is not None:
+        out["gid"] = pack(faces["gid"], 1, F2)
+    if faces.get("sh") is not None:
+        out["sh"] = pack(faces["sh"], 48, F2)
+    vs = [pack(t, int(t.shape[0]) if t.dim() == 2 else 1, V2) for t in vstate]
+    return out, vs
+
+
+def convert_rings(g: dict, K: int, rings: int, sigma_max: float = 3.0) -> dict:
+    """msp_convert_rings: the multi-ring conversion used for fine-tuning targets."""
+    import torch
+    mean = _need(g["mean"], torch.float32, "mean")
+    ctx = _ctx(mean)
+    ctx.bind_stream()
+    n = mean.shape[1]
+    nv, nf = C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.msp_rings_size(n, K, rings, C.byref(nv), C.byref(nf)), "msp_rings_size")
+    dev = mean.device
+    out = dict(pos=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               opacity=torch.empty((nv.value,), dtype=torch.float32, device=dev),
+               rgb=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               idx=torch.empty((3, nf.value), dtype=torch.int32, device=dev),
+               gid=torch.empty((nf.value,), dtype=torch.int32, device=dev), sh=None)
+    G = _lib.Gaussians(n, _dev_ptr(mean), _dev_ptr(_need(g["scale"], torch.float32, "scale")),
+                       _dev_ptr(_need(g["quat"], torch.float32, "quat")),
+                       _dev_ptr(_need(g["opacity"], torch.float32, "opacity")),
+                       _dev_ptr(_need(g["rgb"], torch.float32, "rgb")), None)
+    Fc = _faces_struct(out)
+    ctx.check(ctx.lib.msp_convert_rings(ctx.h, C.byref(G), K, rings, float(sigma_max), C.byref(Fc)),
+              "msp_convert_rings")
+    return out
 
 
 def _autograd():

@@ -41,6 +41,11 @@ class FaceGrads(C.Structure):
     _fields_ = [("dpos", C.c_void_p), ("dopacity", C.c_void_p), ("drgb", C.c_void_p), ("dsh", C.c_void_p)]
 
 
+class AdamGroup(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_float), ("lo", C.c_float), ("hi", C.c_float), ("clamp", C.c_int32)]
+
+
 class RenderStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_views", "width", "height", "tile_w", "tile_h", "entries",
                                          "max_tile_entries", "fragments", "restarts")]
@@ -70,6 +75,15 @@ EXPORTS = {
                                  C.POINTER(C.c_int64)]),
     "msp_autotune": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),
                                C.c_void_p, C.c_void_p, C.POINTER(FaceGrads), C.POINTER(RenderOpts)]),
+    "msp_loss": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                           C.c_void_p, C.c_void_p]),
+    "msp_adam_step": (C.c_int, [C.c_void_p, C.POINTER(AdamGroup), C.c_int, C.c_int, C.c_float, C.c_float,
+                                C.c_float]),
+    "msp_prune": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.c_float, C.POINTER(C.c_void_p), C.POINTER(C.c_int),
+                            C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "msp_rings_size": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "msp_convert_rings": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_int, C.c_float,
+                                    C.POINTER(Faces)]),
     "msp_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "msp_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }

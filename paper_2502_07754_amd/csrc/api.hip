@@ -136,6 +136,10 @@ msp_status msp_destroy(msp_ctx* ctx) {
     delete ctx->timer;
   }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  DevBuf* bufs[] = {&ctx->loss_scratch, &ctx->pr_keep, &ctx->pr_used, &ctx->pr_foff, &ctx->pr_voff,
+                    &ctx->pr_scan, &ctx->pr_tmpi, &ctx->pr_tmpf};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
   delete ctx;
   return MSP_OK;
 }
@@ -214,6 +218,119 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
 }
 
 static void free_graph(msp_state* st);
+
+msp_status msp_loss(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views, int height,
+                    int width, float* loss_out, float* dimg) {
+  if (!ctx) return MSP_EINVAL;
+  if (!img || !tgt || !loss_out || n_views < 1 || height < 1 || width < 1 ||
+      (kind != MSP_LOSS_MSE && kind != MSP_LOSS_L1 && kind != MSP_LOSS_L1_DSSIM) || !std::isfinite(lambda))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_loss: bad argument");
+  DeviceGuard dg(ctx->device);
+  int rc;
+  if ((rc = msp_ensure(ctx, ctx->loss_scratch, loss_scratch_bytes(n_views, height, width, kind)))) return (msp_status)rc;
+  MSP_TIMED(ctx, ST_OTHER, launch_loss(ctx->stream, kind, lambda, img, tgt, n_views, height, width, loss_out, dimg,
+                                      ctx->loss_scratch.p));
+  return MSP_OK;
+}
+
+msp_status msp_adam_step(msp_ctx* ctx, const msp_adam_group* groups, int n_groups, int step, float beta1, float beta2,
+                         float eps) {
+  if (!ctx) return MSP_EINVAL;
+  if (!groups || n_groups < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps >= 0.f))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_adam_step: bad argument");
+  for (int i = 0; i < n_groups; ++i)
+    if (groups[i].n < 0 || (groups[i].n > 0 && (!groups[i].param || !groups[i].grad || !groups[i].m || !groups[i].v)))
+      return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_adam_step: null array in a group");
+  DeviceGuard dg(ctx->device);
+  for (int i = 0; i < n_groups; ++i) MSP_TIMED(ctx, ST_OTHER, launch_adam(ctx->stream, groups[i], step, beta1, beta2, eps));
+  return MSP_OK;
+}
+
+msp_status msp_prune(msp_ctx* ctx, msp_faces* f, float thresh, float* const* vstate, const int* vstate_rows,
+                     int n_vstate, int64_t* new_verts, int64_t* new_faces) {
+  if (!ctx) return MSP_EINVAL;
+  if (!f || !new_verts || !new_faces || n_vstate < 0 || (n_vstate > 0 && (!vstate || !vstate_rows)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prune: bad argument");
+  const int64_t V = f->n_verts, F = f->n_faces;
+  if (F > 0 && (!f->pos || !f->opacity || !f->idx)) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prune: null array");
+  int max_rows = 3;
+  for (int i = 0; i < n_vstate; ++i) {
+    if (!vstate[i] || vstate_rows[i] < 1) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prune: bad vstate");
+    max_rows = vstate_rows[i] > max_rows ? vstate_rows[i] : max_rows;
+  }
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = ctx->stream;
+  int rc;
+  if ((rc = msp_ensure(ctx, ctx->pr_keep, 4 * (F + 1))) || (rc = msp_ensure(ctx, ctx->pr_used, 4 * (V + 1))) ||
+      (rc = msp_ensure(ctx, ctx->pr_foff, 8 * (F + 1))) || (rc = msp_ensure(ctx, ctx->pr_voff, 8 * (V + 1))) ||
+      (rc = msp_ensure(ctx, ctx->pr_scan, scan_scratch_bytes(F > V ? F : V))) ||
+      (rc = msp_ensure(ctx, ctx->pr_tmpi, 4 * 4 * (F + 1))) ||
+      (rc = msp_ensure(ctx, ctx->pr_tmpf, 4 * (size_t)(max_rows > 48 ? max_rows : 48) * ((V > F ? V : F) + 1))))
+    return (msp_status)rc;
+  uint32_t* keep = P<uint32_t>(ctx->pr_keep);
+  uint32_t* used = P<uint32_t>(ctx->pr_used);
+  int64_t* foff = P<int64_t>(ctx->pr_foff);
+  int64_t* voff = P<int64_t>(ctx->pr_voff);
+  MSP_HIP(ctx, launch_fill_u32(s, used, 0u, V));
+  MSP_HIP(ctx, launch_face_keep(s, f->idx, f->opacity, F, V, thresh, keep, used));
+  MSP_HIP(ctx, launch_scan_u32(s, keep, foff, F, ctx->pr_scan.p));
+  MSP_HIP(ctx, launch_scan_u32(s, used, voff, V, ctx->pr_scan.p));
+  int64_t F2 = 0, V2 = 0;
+  MSP_HIP(ctx, hipMemcpyAsync(&F2, foff + F, 8, hipMemcpyDeviceToHost, s));
+  MSP_HIP(ctx, hipMemcpyAsync(&V2, voff + V, 8, hipMemcpyDeviceToHost, s));
+  MSP_HIP(ctx, hipStreamSynchronize(s));
+  // faces: idx (3 rows), gid, sh through the temporaries, then back in place
+  int32_t* ti = P<int32_t>(ctx->pr_tmpi);
+  float* tf = P<float>(ctx->pr_tmpf);
+  MSP_HIP(ctx, launch_compact_faces(s, f->idx, f->gid, nullptr, F, keep, foff, voff, ti, ti + 3 * F2, nullptr));
+  MSP_HIP(ctx, hipMemcpyAsync(f->idx, ti, 4 * 3 * F2, hipMemcpyDeviceToDevice, s));
+  if (f->gid) MSP_HIP(ctx, hipMemcpyAsync(f->gid, ti + 3 * F2, 4 * F2, hipMemcpyDeviceToDevice, s));
+  if (f->sh) {
+    // sh rows are compacted with the vertex-row kernel over the face keep flags
+    MSP_HIP(ctx, launch_compact_rows(s, f->sh, 48, F, keep, foff, tf));
+    MSP_HIP(ctx, hipMemcpyAsync(f->sh, tf, 4 * 48 * F2, hipMemcpyDeviceToDevice, s));
+  }
+  auto rows = [&](float* a, int r) -> hipError_t {
+    if (!a) return hipSuccess;
+    hipError_t e = launch_compact_rows(s, a, r, V, used, voff, tf);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(a, tf, 4 * (size_t)r * V2, hipMemcpyDeviceToDevice, s);
+  };
+  MSP_HIP(ctx, rows(f->pos, 3));
+  MSP_HIP(ctx, rows(f->opacity, 1));
+  MSP_HIP(ctx, rows(f->rgb, 3));
+  for (int i = 0; i < n_vstate; ++i) MSP_HIP(ctx, rows(vstate[i], vstate_rows[i]));
+  MSP_HIP(ctx, hipStreamSynchronize(s));
+  f->n_verts = V2;
+  f->n_faces = F2;
+  *new_verts = V2;
+  *new_faces = F2;
+  return MSP_OK;
+}
+
+msp_status msp_rings_size(int64_t n, int K, int rings, int64_t* n_verts, int64_t* n_faces) {
+  if (n < 0 || K < 3 || K > 64 || rings < 1 || rings > 16 || !n_verts || !n_faces) return MSP_EINVAL;
+  *n_verts = n * (1 + (int64_t)rings * K);
+  *n_faces = n * (int64_t)K * (2 * rings - 1);
+  if (*n_verts >= (int64_t(1) << 31) || *n_faces >= (int64_t(1) << 31)) return MSP_EINVAL;
+  return MSP_OK;
+}
+
+msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int rings, float sigma_max, msp_faces* out) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!g || !out || msp_rings_size(g->n, K, rings, &V, &F) != MSP_OK || !std::isfinite(sigma_max) || !(sigma_max > 0.f))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert_rings: bad argument");
+  if (out->n_verts != V || out->n_faces != F)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert_rings: output sizes differ from msp_rings_size");
+  if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->rgb || !out->pos || !out->opacity ||
+                   !out->rgb || !out->idx))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert_rings: null array");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_CONVERT, launch_convert_rings(ctx->stream, g, K, rings, sigma_max, out));
+  return MSP_OK;
+}
 
 msp_status msp_state_create(msp_ctx* ctx, msp_state** out) {
   if (!ctx || !out) return MSP_EINVAL;

@@ -27,6 +27,7 @@ struct msp_ctx {
   std::string err;
   // autotuned tile choice per (n_faces bucket, width, height, n_views), filled by msp_autotune
   int tuned_tile_w = 0, tuned_tile_h = 0, tuned_kbuf = 0;
+  DevBuf loss_scratch, pr_keep, pr_used, pr_foff, pr_voff, pr_scan, pr_tmpi, pr_tmpf;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
 };
@@ -121,6 +122,20 @@ int sh_max_views();
 hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float4* col4);
 hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, const float* dcol,
                          float* dsh, float* dpos);
+
+size_t loss_scratch_bytes(int V, int H, int W, int kind);
+hipError_t launch_loss(hipStream_t s, int kind, float lambda, const float* img, const float* tgt, int V, int H, int W,
+                       float* loss_out, float* dimg, void* scratch);
+hipError_t launch_adam(hipStream_t s, const msp_adam_group& g, int step, float b1, float b2, float eps);
+hipError_t launch_face_keep(hipStream_t s, const int32_t* idx, const float* op, int64_t F, int64_t V, float thresh,
+                            uint32_t* keep, uint32_t* used);
+hipError_t launch_compact_faces(hipStream_t s, const int32_t* idx, const int32_t* gid, const float* sh, int64_t F,
+                                const uint32_t* keep, const int64_t* foff, const int64_t* voff, int32_t* idx2,
+                                int32_t* gid2, float* sh2);
+hipError_t launch_compact_rows(hipStream_t s, const float* src, int rows, int64_t V, const uint32_t* used,
+                               const int64_t* voff, float* dst);
+hipError_t launch_convert_rings(hipStream_t s, const msp_gaussians* g, int K, int rings, float sigma_max,
+                                msp_faces* out);
 
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a);
 hipError_t launch_cap_guard(hipStream_t s, const int64_t* total, int64_t cap, uint32_t* flag, uint32_t bit);
