@@ -230,6 +230,45 @@ msp_status msp_prune(msp_ctx* ctx, msp_faces* f, float thresh, float* const* vst
 msp_status msp_rings_size(int64_t n, int K, int rings, int64_t* n_verts, int64_t* n_faces);
 msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int rings, float sigma_max, msp_faces* out);
 
+/* ---- refiner: a small MLP that predicts better initial fans ------------- */
+
+/* The refiner is not in the paper: it maps each Gaussian to corrections of its
+ * fan so that fine-tuning starts closer to its optimum, and plain conversion
+ * (a zero last layer) stays its fallback. Network: x (15) -> 256 -> 256 ->
+ * n_out = 3K + 4, ReLU, bfloat16 operands with float32 accumulation on the
+ * matrix cores; weights are float32 masters held by the caller and packed to
+ * bfloat16 inside (msp_refiner_set_weights). */
+typedef struct msp_refiner msp_refiner;
+
+/* n_out in [1, 32] (3K + 4 for K <= 9). */
+msp_status msp_refiner_create(msp_ctx* ctx, int n_out, msp_refiner** out);
+msp_status msp_refiner_free(msp_ctx* ctx, msp_refiner* r);
+/* W1 [256][15], b1 [256], W2 [256][256], b2 [256], W3 [n_out][256], b3 [n_out]: DEVICE
+ * float32, row-major [out][in]. Rounded to bfloat16 (nearest, ties to even) and
+ * packed; asynchronous. */
+msp_status msp_refiner_set_weights(msp_ctx* ctx, msp_refiner* r, const float* W1, const float* b1, const float* W2,
+                                   const float* b2, const float* W3, const float* b3);
+/* Per-Gaussian inputs x [n][16] (float32; the last column is 0):
+ * (mean (3), scale / 0.1 (3), unit quaternion with w >= 0 (4), opacity, rgb (3), K / 16). */
+msp_status msp_refiner_features(msp_ctx* ctx, const msp_gaussians* g, int K, float* x);
+/* y [n][n_out] = W3 relu(W2 relu(W1 x + b1) + b2) + b3 with x, W1, W2, W3 and
+ * both hidden activations rounded to bfloat16 before each product. */
+msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* x, int64_t n, float* y);
+/* Gradients of sum(y * dy) over the n samples (forward recomputed from x):
+ * dW1 [256][15], db1 [256], dW2 [256][256], db2 [256], dW3 [n_out][256],
+ * db3 [n_out] (DEVICE, overwritten). dy, dh2 and dh1 are rounded to bfloat16
+ * before each product; bias gradients sum the unrounded values. */
+msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, const float* dy, int64_t n, float* dW1,
+                                float* db1, float* dW2, float* db2, float* dW3, float* db3);
+/* Fan conversion (as msp_convert, sizes from msp_convert_size) with the
+ * refiner's outputs applied: boundary vertex k moves by
+ * y[3k] a A^ + y[3k+1] b B^ + y[3k+2] sqrt(a b) (A^ x B^) from its plain
+ * position (a = sigma s_a, b = sigma s_b, A^, B^ the unit fan axes); opacity
+ * becomes clamp(o + y[3K], 0, 1) at the centre and opac_mul times that on the
+ * boundary; colours rgb + y[3K+1..3K+3] on every vertex. y: [n][3K+4]. */
+msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, const float* y,
+                             msp_faces* out);
+
 /* ---- captured steps and tuning ------------------------------------------ */
 
 /* One forward + backward step (msp_render then msp_render_backward with the

@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import MspError
 
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
-           "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings"]
+           "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
+           "Refiner", "refiner_features", "refiner_apply"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -375,6 +376,98 @@ def convert_rings(g: dict, K: int, rings: int, sigma_max: float = 3.0) -> dict:
     Fc = _faces_struct(out)
     ctx.check(ctx.lib.msp_convert_rings(ctx.h, C.byref(G), K, rings, float(sigma_max), C.byref(Fc)),
               "msp_convert_rings")
+    return out
+
+
+def _gauss_struct(g: dict) -> _lib.Gaussians:
+    import torch
+    mean = _need(g["mean"], torch.float32, "mean")
+    sh = g.get("sh")
+    return _lib.Gaussians(mean.shape[1], _dev_ptr(mean), _dev_ptr(_need(g["scale"], torch.float32, "scale")),
+                          _dev_ptr(_need(g["quat"], torch.float32, "quat")),
+                          _dev_ptr(_need(g["opacity"], torch.float32, "opacity")),
+                          _dev_ptr(_need(g["rgb"], torch.float32, "rgb")),
+                          None if sh is None else _dev_ptr(_need(sh, torch.float32, "sh")))
+
+
+class Refiner:
+    """The BF16-MFMA refiner MLP (msp_refiner_*): 15 -> 256 -> 256 -> n_out."""
+
+    def __init__(self, n_out: int, device: int = 0):
+        self.ctx = _lib.Context.get(device)
+        h = C.c_void_p()
+        self.ctx.check(self.ctx.lib.msp_refiner_create(self.ctx.h, int(n_out), C.byref(h)), "msp_refiner_create")
+        self.h = h
+        self.n_out = n_out
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.msp_refiner_free(self.ctx.h, self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_weights(self, p: dict):
+        import torch
+        args = [_dev_ptr(_need(p[k], torch.float32, k)) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_refiner_set_weights(self.ctx.h, self.h, *args), "msp_refiner_set_weights")
+
+    def forward(self, x):
+        import torch
+        _need(x, torch.float32, "x")
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_refiner_forward(self.ctx.h, self.h, _dev_ptr(x), x.shape[0], _dev_ptr(y)),
+                       "msp_refiner_forward")
+        return y
+
+    def backward(self, x, dy) -> dict:
+        import torch
+        _need(x, torch.float32, "x")
+        _need(dy, torch.float32, "dy")
+        dev = x.device
+        g = dict(W1=torch.empty((256, 15), device=dev), b1=torch.empty(256, device=dev),
+                 W2=torch.empty((256, 256), device=dev), b2=torch.empty(256, device=dev),
+                 W3=torch.empty((self.n_out, 256), device=dev), b3=torch.empty(self.n_out, device=dev))
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_refiner_backward(self.ctx.h, self.h, _dev_ptr(x), _dev_ptr(dy), x.shape[0],
+                                                         *[_dev_ptr(g[k]) for k in ("W1", "b1", "W2", "b2", "W3",
+                                                                                    "b3")]),
+                       "msp_refiner_backward")
+        return g
+
+
+def refiner_features(g: dict, K: int):
+    import torch
+    G = _gauss_struct(g)
+    ctx = _ctx(g["mean"])
+    ctx.bind_stream()
+    x = torch.empty((G.n, 16), dtype=torch.float32, device=g["mean"].device)
+    ctx.check(ctx.lib.msp_refiner_features(ctx.h, C.byref(G), int(K), _dev_ptr(x)), "msp_refiner_features")
+    return x
+
+
+def refiner_apply(g: dict, K: int, sigma: float, y, opac_mul: float = 0.2) -> dict:
+    """Fan conversion with refiner outputs y [N, 3K+4] applied (msp_refiner_apply)."""
+    import torch
+    G = _gauss_struct(g)
+    ctx = _ctx(g["mean"])
+    ctx.bind_stream()
+    _need(y, torch.float32, "y")
+    nv, nf = C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.msp_convert_size(G.n, K, 0, C.byref(nv), C.byref(nf)), "msp_convert_size")
+    dev = g["mean"].device
+    out = dict(pos=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               opacity=torch.empty((nv.value,), dtype=torch.float32, device=dev),
+               rgb=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               idx=torch.empty((3, nf.value), dtype=torch.int32, device=dev),
+               gid=torch.empty((nf.value,), dtype=torch.int32, device=dev), sh=None)
+    G.sh = None
+    Fc = _faces_struct(out)
+    ctx.check(ctx.lib.msp_refiner_apply(ctx.h, C.byref(G), int(K), float(sigma), float(opac_mul), _dev_ptr(y),
+                                        C.byref(Fc)), "msp_refiner_apply")
     return out
 
 

@@ -84,6 +84,14 @@ EXPORTS = {
     "msp_rings_size": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "msp_convert_rings": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_int, C.c_float,
                                     C.POINTER(Faces)]),
+    "msp_refiner_create": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "msp_refiner_free": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "msp_refiner_set_weights": (C.c_int, [C.c_void_p, C.c_void_p] + [C.c_void_p] * 6),
+    "msp_refiner_features": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_void_p]),
+    "msp_refiner_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "msp_refiner_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64] + [C.c_void_p] * 6),
+    "msp_refiner_apply": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float, C.c_void_p,
+                                    C.POINTER(Faces)]),
     "msp_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "msp_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }

@@ -332,6 +332,93 @@ msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int ri
   return MSP_OK;
 }
 
+msp_status msp_refiner_create(msp_ctx* ctx, int n_out, msp_refiner** out) {
+  if (!ctx || !out || n_out < 1 || n_out > 32) return MSP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  msp_refiner* r = refiner_new(n_out);
+  int rc = refiner_alloc(ctx, r);
+  if (rc != MSP_OK) {
+    refiner_free_bufs(r);
+    refiner_delete(r);
+    return (msp_status)rc;
+  }
+  *out = r;
+  return MSP_OK;
+}
+
+msp_status msp_refiner_free(msp_ctx* ctx, msp_refiner* r) {
+  if (!ctx || !r) return MSP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  refiner_free_bufs(r);
+  refiner_delete(r);
+  return MSP_OK;
+}
+
+msp_status msp_refiner_set_weights(msp_ctx* ctx, msp_refiner* r, const float* W1, const float* b1, const float* W2,
+                                   const float* b2, const float* W3, const float* b3) {
+  if (!ctx) return MSP_EINVAL;
+  if (!r || !W1 || !b1 || !W2 || !b2 || !W3 || !b3)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_set_weights: null argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_pack(ctx->stream, r, W1, b1, W2, b2, W3, b3));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_features(msp_ctx* ctx, const msp_gaussians* g, int K, float* x) {
+  if (!ctx) return MSP_EINVAL;
+  if (!g || !x || g->n < 0 || K < 3 || K > 64 ||
+      (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->rgb)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_features: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_features(ctx->stream, g, K, x));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* x, int64_t n, float* y) {
+  if (!ctx) return MSP_EINVAL;
+  if (!r || n < 0 || (n > 0 && (!x || !y))) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_forward: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_forward(ctx->stream, r, x, n, y, ctx->n_cu));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, const float* dy, int64_t n, float* dW1,
+                                float* db1, float* dW2, float* db2, float* dW3, float* db3) {
+  if (!ctx) return MSP_EINVAL;
+  if (!r || n < 0 || (n > 0 && (!x || !dy)) || !dW1 || !db1 || !dW2 || !db2 || !dW3 || !db3)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_backward: bad argument");
+  DeviceGuard dg(ctx->device);
+  int rc;
+  if ((rc = refiner_train_alloc(ctx, r, n))) return (msp_status)rc;
+  MSP_TIMED(ctx, ST_OTHER,
+            launch_refiner_backward(ctx->stream, r, x, dy, n, dW1, db1, dW2, db2, dW3, db3, ctx->n_cu));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, const float* y,
+                             msp_faces* out) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!g || !out || !y || msp_convert_size(g->n, K, MSP_FAN_FLAT, &V, &F) != MSP_OK || !std::isfinite(sigma) ||
+      !(sigma > 0.f) || out->n_verts != V || out->n_faces != F)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_apply: bad argument");
+  if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->rgb || !out->pos || !out->opacity ||
+                   !out->rgb || !out->idx))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_apply: null array");
+  DeviceGuard dg(ctx->device);
+  // faces (indices, ids) as in the plain conversion, then the refined vertices
+  std::vector<float> cs(2 * K);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < K; ++k) {
+    cs[k] = (float)std::cos(-pi + 2.0 * pi * k / K);
+    cs[K + k] = (float)std::sin(-pi + 2.0 * pi * k / K);
+  }
+  MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  MSP_TIMED(ctx, ST_CONVERT, launch_refiner_apply(ctx->stream, g, K, sigma, opac_mul, y, 3 * K + 4, out));
+  return MSP_OK;
+}
+
 msp_status msp_state_create(msp_ctx* ctx, msp_state** out) {
   if (!ctx || !out) return MSP_EINVAL;
   DeviceGuard dg(ctx->device);

@@ -137,6 +137,22 @@ hipError_t launch_compact_rows(hipStream_t s, const float* src, int rows, int64_
 hipError_t launch_convert_rings(hipStream_t s, const msp_gaussians* g, int K, int rings, float sigma_max,
                                 msp_faces* out);
 
+// refiner (refiner.hip)
+msp_refiner* refiner_new(int n_out);
+void refiner_delete(msp_refiner* r);
+int refiner_n_out(const msp_refiner* r);
+int refiner_alloc(msp_ctx* ctx, msp_refiner* r);
+int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N);
+void refiner_free_bufs(msp_refiner* r);
+hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, const float* b1, const float* W2,
+                               const float* b2, const float* W3, const float* b3);
+hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu);
+hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x, const float* dy, int64_t N,
+                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, int n_cu);
+hipError_t launch_refiner_features(hipStream_t s, const msp_gaussians* g, int K, float* x);
+hipError_t launch_refiner_apply(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                const float* y, int n_out, msp_faces* out);
+
 hipError_t launch_setup(hipStream_t s, const RasterArgs& a);
 hipError_t launch_cap_guard(hipStream_t s, const int64_t* total, int64_t cap, uint32_t* flag, uint32_t bit);
 hipError_t launch_emit(hipStream_t s, const RasterArgs& a);

@@ -1,0 +1,525 @@
+// Refiner MLP on the matrix cores: 15 -> 256 -> 256 -> (3K+4), ReLU, bfloat16
+// operands with float32 accumulation (v_mfma_f32_16x16x32_bf16), the one dense
+// contraction of the path. Not in the paper: it predicts corrections of each
+// Gaussian's fan so fine-tuning starts nearer its optimum; a zero last layer
+// reproduces the plain conversion.
+//
+// Forward: one wavefront per 16 samples, all three layers fused; the hidden
+// activations go through a per-wave LDS tile (bfloat16) to turn the MFMA
+// output layout into the next layer's operand layout. Weights are read from
+// global memory (L2-resident, 155 KB in bfloat16) as 16-byte operand
+// fragments, pre-packed as [out][in] rows so every fragment is contiguous.
+// Backward: the same tile recomputes the forward, then dH2 = (dY W3) * [h2>0],
+// dH1 = (dH2 W2) * [h1>0] (transposed weight copies keep fragments
+// contiguous), bias gradients by wave reductions, and bfloat16 feature-major
+// copies of x, h1, h2, dy, dh2, dh1 for the weight-gradient products
+// dW = dH^T H, which a second MFMA kernel computes with split-K over samples.
+//
+// MFMA 16x16x32 operand layout (lane l = 0..63, q = l / 16, r = l % 16):
+//   A[i][k]: lane (i, q) holds k = 8q..8q+7;  B[k][j]: lane (j, q) holds k = 8q..8q+7;
+//   D[i][j]: lane (j, q) holds i = 4q..4q+3.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int HID = 256;
+constexpr int LDH = HID + 8;  // LDS row stride (bf16 elements) of a 16 x 256 tile
+constexpr int WPB = 2;        // waves per block
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u | 0x00400000u) >> 16);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 frag_from_u4(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ bf16x8 load_frag(const uint16_t* p) {  // 16-byte aligned
+  return frag_from_u4(*reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 pack8(const float* v) {
+  u32x4 u;
+  u.x = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+  u.y = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+  u.z = (uint32_t)bf16_rne(v[4]) | ((uint32_t)bf16_rne(v[5]) << 16);
+  u.w = (uint32_t)bf16_rne(v[6]) | ((uint32_t)bf16_rne(v[7]) << 16);
+  return frag_from_u4(u);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+struct MlpArgs {
+  const uint16_t* w1;   // [256][32]
+  const uint16_t* w2;   // [256][256]
+  const uint16_t* w3;   // [32][256]
+  const uint16_t* w2t;  // [256][256]  w2t[i][o] = W2[o][i]
+  const uint16_t* w3t;  // [256][32]   w3t[j][o] = W3[o][j]
+  const float* b1;      // [256]
+  const float* b2;      // [256]
+  const float* b3;      // [32]
+  int n_out;
+};
+
+struct TrainBufs {
+  const float* dy;  // [N][n_out]
+  uint16_t *xt, *h1t, *h2t, *dyt, *dh2t, *dh1t;  // feature-major, row length n_pad
+  int64_t n_pad;
+  float *db1, *db2, *db3;  // accumulated with atomics (zeroed by the caller)
+};
+
+// Writes a D fragment (+bias, optional relu) of column block nb into an LDS tile as bf16.
+__device__ __forceinline__ void store_tile(uint16_t* T, int nb, int lane, const float v[4]) {
+  const int j = nb * 16 + (lane & 15), q = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) T[(4 * q + e) * LDH + j] = bf16_rne(v[e]);
+}
+
+__device__ __forceinline__ bf16x8 tile_frag(const uint16_t* T, int kb, int lane) {
+  return load_frag(T + (lane & 15) * LDH + kb * 32 + 8 * (lane >> 4));
+}
+
+// feature-major bf16 store of a D fragment: dst[j][s0 + 4q + e]
+__device__ __forceinline__ void store_t(uint16_t* dst, int64_t n_pad, int j, int64_t s, const float v[4]) {
+  uint16_t* p = dst + (int64_t)j * n_pad + s;
+  const uint32_t lo = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+  const uint32_t hi = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+  *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
+}
+
+// sum of the 16 rows of a D fragment for column j (lanes sharing lane % 16)
+__device__ __forceinline__ float col_sum(const float v[4]) {
+  float s = (v[0] + v[1]) + (v[2] + v[3]);
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+
+template <bool BWD>
+__global__ __launch_bounds__(64 * WPB) void k_mlp_tile(const float* __restrict__ x, int64_t N, MlpArgs m,
+                                                       float* __restrict__ y, TrainBufs tb) {
+  __shared__ uint16_t lds[WPB][3][16 * LDH];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int q = lane >> 4, r = lane & 15;
+  uint16_t* H1s = lds[wid][0];
+  uint16_t* H2s = lds[wid][1];
+  uint16_t* G2s = lds[wid][2];
+  const int64_t tiles = (N + 15) / 16;
+  for (int64_t t = (int64_t)blockIdx.x * WPB + wid; t < tiles; t += (int64_t)gridDim.x * WPB) {
+    const int64_t s0 = t * 16;
+    const int64_t srow = s0 + r;  // the sample whose A row this lane carries
+    // ---- layer 1: A = x rows (16 features, padded to K = 32) ----
+    float xv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xv[e] = (q == 0 || q == 1) && srow < N ? x[srow * 16 + 8 * q + e] : 0.f;
+    const bf16x8 ax = pack8(xv);
+    if (BWD && q < 2) {  // x^T for dW1 (features 0..15)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) tb.xt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(xv[e]);
+    }
+#pragma unroll 2
+    for (int nb = 0; nb < 16; ++nb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma(ax, load_frag(m.w1 + (nb * 16 + r) * 32 + 8 * q), acc);
+      const float b = m.b1[nb * 16 + r];
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
+      store_tile(H1s, nb, lane, v);
+      if (BWD) store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // ---- layer 2 ----
+    bf16x8 a[8];
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(H1s, kb, lane);
+    for (int nb = 0; nb < 16; ++nb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const uint16_t* wb = m.w2 + (nb * 16 + r) * HID + 8 * q;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
+      const float b = m.b2[nb * 16 + r];
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
+      store_tile(H2s, nb, lane, v);
+      if (BWD) store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // ---- layer 3 ----
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(H2s, kb, lane);
+    if (!BWD) {
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const uint16_t* wb = m.w3 + (nb * 16 + r) * HID + 8 * q;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
+        const int j = nb * 16 + r;
+        if (j < m.n_out) {
+          const float b = m.b3[j];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t s = s0 + 4 * q + e;
+            if (s < N) y[s * m.n_out + j] = acc[e] + b;
+          }
+        }
+      }
+      continue;
+    }
+    // ---- backward: dY (K = 32, outputs padded) ----
+    float dv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int o = 8 * q + e;
+      dv[e] = (o < m.n_out && srow < N) ? tb.dy[srow * m.n_out + o] : 0.f;
+    }
+    const bf16x8 ady = pack8(dv);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      tb.dyt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(dv[e]);
+      // db3: sum over the 16 samples (lanes sharing q)
+      float s = dv[e];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      if (r == 0 && 8 * q + e < m.n_out) atomicAdd(&tb.db3[8 * q + e], s);
+    }
+    // dH2 = (dY W3) * [h2 > 0]
+    for (int nb = 0; nb < 16; ++nb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma(ady, load_frag(m.w3t + (nb * 16 + r) * 32 + 8 * q), acc);
+      const int j = nb * 16 + r;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t h = H2s[(4 * q + e) * LDH + j];
+        v[e] = (h & 0x7fffu) != 0 && !(h & 0x8000u) ? acc[e] : 0.f;  // h2 > 0
+      }
+      const float sj = col_sum(v);
+      if (q == 0) atomicAdd(&tb.db2[j], sj);
+      store_tile(G2s, nb, lane, v);
+      store_t(tb.dh2t, tb.n_pad, j, s0 + 4 * q, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // dH1 = (dH2 W2) * [h1 > 0]
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(G2s, kb, lane);
+    for (int nb = 0; nb < 16; ++nb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const uint16_t* wb = m.w2t + (nb * 16 + r) * HID + 8 * q;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
+      const int j = nb * 16 + r;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t h = H1s[(4 * q + e) * LDH + j];
+        v[e] = (h & 0x7fffu) != 0 && !(h & 0x8000u) ? acc[e] : 0.f;
+      }
+      const float sj = col_sum(v);
+      if (q == 0) atomicAdd(&tb.db1[j], sj);
+      store_t(tb.dh1t, tb.n_pad, j, s0 + 4 * q, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+}
+
+// C[m][n] += sum_s A[m][s] B[n][s] for s in this wave's chunk (bf16 rows of length n_pad).
+// Grid: x = (M/16) * (Nc/16) blocks of 16x16, y = sample chunks.
+__global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int M,
+                                              int Nc, int64_t n_pad, int64_t chunk, float* __restrict__ C) {
+  const int lane = threadIdx.x, q = lane >> 4, r = lane & 15;
+  const int nbn = Nc / 16;
+  const int mb = blockIdx.x / nbn, nb = blockIdx.x % nbn;
+  const int64_t k0 = (int64_t)blockIdx.y * chunk;
+  int64_t k1 = k0 + chunk;
+  if (k1 > n_pad) k1 = n_pad;
+  const uint16_t* ap = A + (int64_t)(mb * 16 + r) * n_pad + 8 * q;
+  const uint16_t* bp = B + (int64_t)(nb * 16 + r) * n_pad + 8 * q;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t k = k0; k < k1; k += 32) acc = mfma(load_frag(ap + k), load_frag(bp + k), acc);
+  const int j = nb * 16 + r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) atomicAdd(&C[(mb * 16 + 4 * q + e) * Nc + j], acc[e]);
+}
+
+// ---- packing: fp32 masters -> padded bf16 operands and transposed copies ----
+__global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ W3,
+                       const float* __restrict__ b3, int n_in, int n_out, uint16_t* w1, uint16_t* w2, uint16_t* w3,
+                       uint16_t* w2t, uint16_t* w3t, float* b3p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < HID * 32) {
+    const int o = i / 32, k = i % 32;
+    w1[i] = k < n_in ? bf16_rne(W1[o * n_in + k]) : 0;
+    const int j = i / 32, oo = i % 32;  // w3t[j][o]
+    w3t[i] = oo < n_out ? bf16_rne(W3[oo * HID + j]) : 0;
+    const int o3 = i / HID, k3 = i % HID;  // w3[o][k]
+    w3[i] = o3 < n_out ? bf16_rne(W3[o3 * HID + k3]) : 0;
+  }
+  if (i < HID * HID) {
+    w2[i] = bf16_rne(W2[i]);
+    const int a = i / HID, b = i % HID;  // w2t[a][b] = W2[b][a]
+    w2t[i] = bf16_rne(W2[b * HID + a]);
+  }
+  if (i < 32) b3p[i] = i < n_out ? b3[i] : 0.f;
+}
+
+__global__ void k_unpack_grads(const float* __restrict__ g1, const float* __restrict__ g3, int n_in, int n_out,
+                               float* __restrict__ dW1, float* __restrict__ dW3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < HID * n_in) dW1[i] = g1[(i / n_in) * 32 + i % n_in];
+  if (i < n_out * HID) dW3[i] = g3[i];
+}
+
+// ---- features and application of the refiner outputs ----
+__device__ inline void rcol(float w, float x, float y, float z, int col, float& r0, float& r1, float& r2) {
+  const float n = sqrtf(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  if (col == 0) {
+    r0 = 1.f - 2.f * (y * y + z * z); r1 = 2.f * (x * y + w * z); r2 = 2.f * (x * z - w * y);
+  } else if (col == 1) {
+    r0 = 2.f * (x * y - w * z); r1 = 1.f - 2.f * (x * x + z * z); r2 = 2.f * (y * z + w * x);
+  } else {
+    r0 = 2.f * (x * z + w * y); r1 = 2.f * (y * z - w * x); r2 = 1.f - 2.f * (x * x + y * y);
+  }
+}
+
+__global__ void k_features(const float* __restrict__ mean, const float* __restrict__ scale,
+                           const float* __restrict__ quat, const float* __restrict__ opacity,
+                           const float* __restrict__ rgb, int64_t n, int K, float* __restrict__ x) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
+  const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float sg = qw < 0.f ? -1.f : 1.f;
+  float* o = x + g * 16;
+  o[0] = mean[g];
+  o[1] = mean[n + g];
+  o[2] = mean[2 * n + g];
+  o[3] = scale[g] / 0.1f;
+  o[4] = scale[n + g] / 0.1f;
+  o[5] = scale[2 * n + g] / 0.1f;
+  o[6] = sg * qw / qn;
+  o[7] = sg * qx / qn;
+  o[8] = sg * qy / qn;
+  o[9] = sg * qz / qn;
+  o[10] = opacity[g];
+  o[11] = rgb[g];
+  o[12] = rgb[n + g];
+  o[13] = rgb[2 * n + g];
+  o[14] = (float)K / 16.f;
+  o[15] = 0.f;
+}
+
+struct CS {
+  float c[64], s[64];
+};
+
+__global__ void k_apply(const float* __restrict__ mean, const float* __restrict__ scale,
+                        const float* __restrict__ quat, const float* __restrict__ opacity,
+                        const float* __restrict__ rgb, int64_t n, int K, float sigma, float opac_mul, CS cs,
+                        const float* __restrict__ y, int n_out, float* __restrict__ pos, float* __restrict__ vop,
+                        float* __restrict__ vrgb) {
+  const int64_t V = n * (K + 1);
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int64_t g = v / (K + 1);
+  const int j = (int)(v - g * (K + 1));
+  const float* yg = y + g * n_out;
+  float px = mean[g], py = mean[n + g], pz = mean[2 * n + g];
+  const float o = fminf(fmaxf(opacity[g] + yg[3 * K], 0.f), 1.f);
+  if (j > 0) {
+    const int k = j - 1;
+    const float s0 = scale[g], s1 = scale[n + g], s2 = scale[2 * n + g];
+    const int drop = (s2 <= s0 && s2 <= s1) ? 2 : (s1 <= s0 ? 1 : 0);
+    const int ia = drop == 0 ? 1 : 0, ib = drop == 2 ? 1 : 2;
+    const float sa = ia == 0 ? s0 : s1, sb = ib == 1 ? s1 : s2;
+    const float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
+    float a0, a1, a2, b0, b1, b2;
+    rcol(qw, qx, qy, qz, ia, a0, a1, a2);
+    rcol(qw, qx, qy, qz, ib, b0, b1, b2);
+    const float n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+    const float la = sigma * sa, lb = sigma * sb, lc = sqrtf(la * lb);
+    const float ca = cs.c[k] * la + yg[3 * k] * la;
+    const float cb = cs.s[k] * lb + yg[3 * k + 1] * lb;
+    const float cn = yg[3 * k + 2] * lc;
+    px += ca * a0 + cb * b0 + cn * n0;
+    py += ca * a1 + cb * b1 + cn * n1;
+    pz += ca * a2 + cb * b2 + cn * n2;
+  }
+  pos[v] = px;
+  pos[V + v] = py;
+  pos[2 * V + v] = pz;
+  vop[v] = j == 0 ? o : opac_mul * o;
+  vrgb[v] = rgb[g] + yg[3 * K + 1];
+  vrgb[V + v] = rgb[n + g] + yg[3 * K + 2];
+  vrgb[2 * V + v] = rgb[2 * n + g] + yg[3 * K + 3];
+}
+
+inline unsigned gfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
+
+}  // namespace
+
+struct msp_refiner {
+  int n_in = 15, n_out = 0;
+  DevBuf w1, w2, w3, w2t, w3t, b1, b2, b3p, train, grads;
+  int64_t train_pad = 0;
+};
+
+msp_refiner* refiner_new(int n_out) {
+  msp_refiner* r = new msp_refiner();
+  r->n_out = n_out;
+  return r;
+}
+
+void refiner_delete(msp_refiner* r) { delete r; }
+int refiner_n_out(const msp_refiner* r) { return r->n_out; }
+
+hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, const float* b1, const float* W2,
+                               const float* b2, const float* W3, const float* b3) {
+  hipLaunchKernelGGL(k_pack, dim3(gfor(HID * HID)), dim3(256), 0, s, W1, W2, W3, b3, r->n_in, r->n_out,
+                     (uint16_t*)r->w1.p, (uint16_t*)r->w2.p, (uint16_t*)r->w3.p, (uint16_t*)r->w2t.p,
+                     (uint16_t*)r->w3t.p, (float*)r->b3p.p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(r->b1.p, b1, 4 * HID, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(r->b2.p, b2, 4 * HID, hipMemcpyDeviceToDevice, s);
+}
+
+static MlpArgs margs(const msp_refiner* r) {
+  MlpArgs m;
+  m.w1 = (const uint16_t*)r->w1.p;
+  m.w2 = (const uint16_t*)r->w2.p;
+  m.w3 = (const uint16_t*)r->w3.p;
+  m.w2t = (const uint16_t*)r->w2t.p;
+  m.w3t = (const uint16_t*)r->w3t.p;
+  m.b1 = (const float*)r->b1.p;
+  m.b2 = (const float*)r->b2.p;
+  m.b3 = (const float*)r->b3p.p;
+  m.n_out = r->n_out;
+  return m;
+}
+
+static unsigned tile_grid(int64_t N, int n_cu) {
+  const int64_t tiles = (N + 15) / 16;
+  int64_t g = (tiles + WPB - 1) / WPB;
+  const int64_t cap = (int64_t)n_cu * 8;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu) {
+  if (N == 0) return hipSuccess;
+  TrainBufs tb = {};
+  hipLaunchKernelGGL(k_mlp_tile<false>, dim3(tile_grid(N, n_cu)), dim3(64 * WPB), 0, s, x, N, margs(r), y, tb);
+  return hipGetLastError();
+}
+
+size_t refiner_train_bytes(int64_t N) {
+  const int64_t np = (N + 31) / 32 * 32;
+  return (size_t)2 * np * (32 + 256 + 256 + 32 + 256 + 256) + 256;
+}
+
+hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x, const float* dy, int64_t N,
+                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, int n_cu) {
+  const int64_t np = (N + 31) / 32 * 32;
+  uint16_t* base = (uint16_t*)r->train.p;
+  TrainBufs tb;
+  tb.dy = dy;
+  tb.n_pad = np;
+  tb.xt = base;
+  tb.h1t = tb.xt + 32 * np;
+  tb.h2t = tb.h1t + 256 * np;
+  tb.dyt = tb.h2t + 256 * np;
+  tb.dh2t = tb.dyt + 32 * np;
+  tb.dh1t = tb.dh2t + 256 * np;
+  tb.db1 = db1;
+  tb.db2 = db2;
+  tb.db3 = db3;
+  hipError_t e;
+  // the padded samples and feature rows must read as zero
+  if ((e = hipMemsetAsync(base, 0, refiner_train_bytes(N) - 256, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(db1, 0, 4 * HID, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(db2, 0, 4 * HID, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(db3, 0, 4 * r->n_out, s)) != hipSuccess) return e;
+  float* g1 = (float*)r->grads.p;  // [256][32]
+  float* g3 = g1 + HID * 32;       // [32][256]
+  if ((e = hipMemsetAsync(g1, 0, 4 * (HID * 32 * 2), s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_mlp_tile<true>, dim3(tile_grid(N, n_cu)), dim3(64 * WPB), 0, s, x, N, margs(r),
+                       (float*)nullptr, tb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t chunk = 2048;
+    const unsigned ny = (unsigned)((np + chunk - 1) / chunk);
+    // dW3 = dY^T H2 : [32][256];  dW2 = dH2^T H1 : [256][256];  dW1 = dH1^T X : [256][32]
+    hipLaunchKernelGGL(k_wgrad, dim3(2 * 16, ny), dim3(64), 0, s, tb.dyt, tb.h2t, 32, 256, np, chunk, g3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad, dim3(16 * 16, ny), dim3(64), 0, s, tb.dh2t, tb.h1t, 256, 256, np, chunk, dW2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad, dim3(16 * 2, ny), dim3(64), 0, s, tb.dh1t, tb.xt, 256, 32, np, chunk, g1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_unpack_grads, dim3(gfor(HID * 32)), dim3(256), 0, s, g1, g3, r->n_in, r->n_out, dW1, dW3);
+  return hipGetLastError();
+}
+
+hipError_t launch_refiner_features(hipStream_t s, const msp_gaussians* g, int K, float* x) {
+  if (g->n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3(gfor(g->n)), dim3(256), 0, s, g->mean, g->scale, g->quat, g->opacity, g->rgb,
+                     g->n, K, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_refiner_apply(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                const float* y, int n_out, msp_faces* out) {
+  if (g->n == 0) return hipSuccess;
+  CS cs;
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < 64; ++k) {
+    const double th = -pi + 2.0 * pi * k / K;
+    cs.c[k] = k < K ? (float)std::cos(th) : 0.f;
+    cs.s[k] = k < K ? (float)std::sin(th) : 0.f;
+  }
+  const int64_t V = g->n * (K + 1);
+  hipLaunchKernelGGL(k_apply, dim3(gfor(V)), dim3(256), 0, s, g->mean, g->scale, g->quat, g->opacity, g->rgb, g->n, K,
+                     sigma, opac_mul, cs, y, n_out, out->pos, out->opacity, out->rgb);
+  return hipGetLastError();
+}
+
+int refiner_alloc(msp_ctx* ctx, msp_refiner* r) {
+  int rc;
+  if ((rc = msp_ensure(ctx, r->w1, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2, 2 * HID * HID)) ||
+      (rc = msp_ensure(ctx, r->w3, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->w2t, 2 * HID * HID)) ||
+      (rc = msp_ensure(ctx, r->w3t, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
+      (rc = msp_ensure(ctx, r->b2, 4 * HID)) || (rc = msp_ensure(ctx, r->b3p, 4 * 32)) ||
+      (rc = msp_ensure(ctx, r->grads, 4 * HID * 32 * 2)))
+    return rc;
+  return MSP_OK;
+}
+
+int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N) {
+  return msp_ensure(ctx, r->train, refiner_train_bytes(N));
+}
+
+void refiner_free_bufs(msp_refiner* r) {
+  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads};
+  for (DevBuf* x : b)
+    if (x->p) (void)hipFree(x->p);
+}

@@ -1,0 +1,72 @@
+"""GPU parity of the BF16-MFMA refiner (forward, backward, features, apply)
+against the oracle with identical bfloat16 rounding points."""
+import numpy as np
+import pytest
+
+from oracle import convert as oc
+from oracle import mlp as om
+from paper_2502_07754_amd import scenes
+from tests.helpers import gaussians_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _params_gpu(p):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v.astype(np.float32))).cuda() for k, v in p.items()}
+
+
+@pytest.mark.parametrize("N", [1, 37, 1000, 4099])
+def test_forward_parity(gpu, N):
+    import torch
+    p = om.init_params(28, seed=N, zero_last=False)
+    x = np.random.default_rng(N).normal(size=(N, 15)).astype(np.float32)
+    x16 = np.concatenate([x, np.zeros((N, 1), np.float32)], 1)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    y = r.forward(torch.from_numpy(x16).cuda()).cpu().numpy()
+    ref, _ = om.forward(p, x.astype(np.float64))
+    err = np.abs(y - ref).max()
+    print("forward max err", err, "max |y|", np.abs(ref).max(), flush=True)
+    assert err <= 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", [50, 2048, 5000])
+def test_backward_parity(gpu, N):
+    import torch
+    p = om.init_params(28, seed=7 + N, zero_last=False)
+    rng = np.random.default_rng(N)
+    x = rng.normal(size=(N, 15)).astype(np.float32)
+    dy = rng.normal(size=(N, 28)).astype(np.float32)
+    x16 = np.concatenate([x, np.zeros((N, 1), np.float32)], 1)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    g = r.backward(torch.from_numpy(x16).cuda(), torch.from_numpy(dy).cuda())
+    _, cache = om.forward(p, x.astype(np.float64))
+    ref = om.backward(p, cache, dy.astype(np.float64))
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a = g[k].cpu().numpy()
+        err = np.abs(a - ref[k]).max()
+        print(k, "max err", err, "max |g|", np.abs(ref[k]).max(), flush=True)
+        assert err <= 1e-3 * np.abs(ref[k]).max(), k
+
+
+def test_features_and_apply(gpu):
+    g = scenes.gaussians(500, 4, 0.01, 0.1, flat=True)
+    gg = gaussians_gpu(g)
+    x = gpu.refiner_features(gg, 8).cpu().numpy()
+    ref = om.features(g.mean, g.scale, g.quat, g.opacity, g.rgb, 8)
+    np.testing.assert_allclose(x[:, :15], ref, rtol=1e-6, atol=1e-7)
+    assert np.all(x[:, 15] == 0)
+    import torch
+    y = np.random.default_rng(1).normal(0, 0.05, (500, 28)).astype(np.float32)
+    out = gpu.refiner_apply(gg, 8, 2.0, torch.from_numpy(y).cuda())
+    want = om.refined_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, 8, 2.0, y.astype(np.float64))
+    np.testing.assert_array_equal(out["idx"].cpu().numpy(), want["idx"])
+    np.testing.assert_allclose(out["pos"].cpu().numpy(), want["pos"], atol=2e-6)
+    np.testing.assert_allclose(out["opacity"].cpu().numpy(), want["opacity"], atol=1e-6)
+    np.testing.assert_allclose(out["rgb"].cpu().numpy(), want["rgb"], atol=1e-6)
+    # zero corrections reproduce the plain conversion
+    z = gpu.refiner_apply(gg, 8, 2.0, torch.zeros((500, 28), device="cuda"))
+    plain = oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, 8, 2.0)
+    np.testing.assert_allclose(z["pos"].cpu().numpy(), plain["pos"], atol=2e-6)
