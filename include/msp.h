@@ -269,6 +269,20 @@ msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, co
 msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, const float* y,
                              msp_faces* out);
 
+/* Training targets for the refiner: per Gaussian, the y* for which
+ * msp_refiner_apply best matches `tuned` (a fine-tuned copy of the plain fan,
+ * same vertex layout, i.e. fine-tuned without pruning) in least squares:
+ * boundary offsets are the local-frame coordinates of (tuned - plain) vertex
+ * positions; the opacity delta fits the centre (weight 1) and the boundary
+ * (weight opac_mul) opacities; the colour delta is the mean tuned vertex colour
+ * minus rgb. y: [n][3K+4]. */
+msp_status msp_refiner_targets(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                               const msp_faces* tuned, float* y);
+/* Mean squared error between y and target ([n][n_out] each); loss_out DEVICE
+ * float, dy (or NULL) = d loss / d y. */
+msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, int64_t n, float* loss_out,
+                            float* dy);
+
 /* ---- captured steps and tuning ------------------------------------------ */
 
 /* One forward + backward step (msp_render then msp_render_backward with the

@@ -19,7 +19,7 @@ from ._lib import MspError
 
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
-           "Refiner", "refiner_features", "refiner_apply"]
+           "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_loss"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -437,6 +437,32 @@ class Refiner:
                                                                                     "b3")]),
                        "msp_refiner_backward")
         return g
+
+
+def refiner_targets(g: dict, K: int, sigma: float, tuned: dict, opac_mul: float = 0.2):
+    """Least-squares refiner targets from a fine-tuned copy of the plain fan (msp_refiner_targets)."""
+    import torch
+    G = _gauss_struct(g)
+    G.sh = None
+    ctx = _ctx(g["mean"])
+    ctx.bind_stream()
+    y = torch.empty((G.n, 3 * K + 4), dtype=torch.float32, device=g["mean"].device)
+    Fc = _faces_struct(tuned)
+    ctx.check(ctx.lib.msp_refiner_targets(ctx.h, C.byref(G), int(K), float(sigma), float(opac_mul), C.byref(Fc),
+                                          _dev_ptr(y)), "msp_refiner_targets")
+    return y
+
+
+def refiner_loss(refiner: "Refiner", y, target, want_grad=True):
+    import torch
+    _need(y, torch.float32, "y")
+    _need(target, torch.float32, "target")
+    out = torch.empty((1,), dtype=torch.float32, device=y.device)
+    dy = torch.empty_like(y) if want_grad else None
+    refiner.ctx.bind_stream()
+    refiner.ctx.check(refiner.ctx.lib.msp_refiner_loss(refiner.ctx.h, refiner.h, _dev_ptr(y), _dev_ptr(target),
+                                                       y.shape[0], _dev_ptr(out), _dev_ptr(dy)), "msp_refiner_loss")
+    return out, dy
 
 
 def refiner_features(g: dict, K: int):

@@ -419,6 +419,28 @@ msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float 
   return MSP_OK;
 }
 
+msp_status msp_refiner_targets(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                               const msp_faces* tuned, float* y) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!g || !tuned || !y || msp_convert_size(g->n, K, MSP_FAN_FLAT, &V, &F) != MSP_OK || tuned->n_verts != V ||
+      !(sigma > 0.f) || (g->n > 0 && (!tuned->pos || !tuned->opacity || !tuned->rgb)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_targets: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_targets(ctx->stream, g, K, sigma, opac_mul, tuned, y));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, int64_t n, float* loss_out,
+                            float* dy) {
+  if (!ctx) return MSP_EINVAL;
+  if (!r || !loss_out || n < 0 || (n > 0 && (!y || !target)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_loss: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_vec_mse(ctx->stream, y, target, n * refiner_n_out(r), loss_out, dy, refiner_part(r)));
+  return MSP_OK;
+}
+
 msp_status msp_state_create(msp_ctx* ctx, msp_state** out) {
   if (!ctx || !out) return MSP_EINVAL;
   DeviceGuard dg(ctx->device);

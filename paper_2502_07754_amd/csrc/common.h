@@ -141,6 +141,11 @@ hipError_t launch_convert_rings(hipStream_t s, const msp_gaussians* g, int K, in
 msp_refiner* refiner_new(int n_out);
 void refiner_delete(msp_refiner* r);
 int refiner_n_out(const msp_refiner* r);
+double* refiner_part(msp_refiner* r);
+hipError_t launch_refiner_targets(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                  const msp_faces* tuned, float* y);
+hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, int64_t n, float* loss, float* dy,
+                          double* part);
 int refiner_alloc(msp_ctx* ctx, msp_refiner* r);
 int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N);
 void refiner_free_bufs(msp_refiner* r);

@@ -372,13 +372,86 @@ __global__ void k_apply(const float* __restrict__ mean, const float* __restrict_
   vrgb[2 * V + v] = rgb[2 * n + g] + yg[3 * K + 3];
 }
 
+// least-squares refiner targets from fine-tuned fans (same vertex layout as the plain fan)
+__global__ void k_targets(const float* __restrict__ mean, const float* __restrict__ scale,
+                          const float* __restrict__ quat, const float* __restrict__ opacity,
+                          const float* __restrict__ rgb, int64_t n, int K, float sigma, float opac_mul, CS cs,
+                          const float* __restrict__ tpos, const float* __restrict__ top,
+                          const float* __restrict__ trgb, float* __restrict__ y) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int64_t V = n * (K + 1);
+  const int n_out = 3 * K + 4;
+  const float s0 = scale[g], s1 = scale[n + g], s2 = scale[2 * n + g];
+  const int drop = (s2 <= s0 && s2 <= s1) ? 2 : (s1 <= s0 ? 1 : 0);
+  const int ia = drop == 0 ? 1 : 0, ib = drop == 2 ? 1 : 2;
+  const float sa = ia == 0 ? s0 : s1, sb = ib == 1 ? s1 : s2;
+  const float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
+  float a0, a1, a2, b0, b1, b2;
+  rcol(qw, qx, qy, qz, ia, a0, a1, a2);
+  rcol(qw, qx, qy, qz, ib, b0, b1, b2);
+  const float n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+  const float la = sigma * sa, lb = sigma * sb, lc = sqrtf(la * lb);
+  const float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
+  float* yg = y + g * n_out;
+  for (int k = 0; k < K; ++k) {
+    const int64_t v = g * (K + 1) + 1 + k;
+    // plain boundary position
+    const float px = mx + cs.c[k] * la * a0 + cs.s[k] * lb * b0;
+    const float py = my + cs.c[k] * la * a1 + cs.s[k] * lb * b1;
+    const float pz = mz + cs.c[k] * la * a2 + cs.s[k] * lb * b2;
+    const float dx = tpos[v] - px, dy = tpos[V + v] - py, dz = tpos[2 * V + v] - pz;
+    yg[3 * k] = (dx * a0 + dy * a1 + dz * a2) / fmaxf(la, 1e-12f);
+    yg[3 * k + 1] = (dx * b0 + dy * b1 + dz * b2) / fmaxf(lb, 1e-12f);
+    yg[3 * k + 2] = (dx * n0 + dy * n1 + dz * n2) / fmaxf(lc, 1e-12f);
+  }
+  const float o0 = opacity[g];
+  float acc = top[g * (K + 1)] - o0;
+  float cr = 0.f, cg = 0.f, cb = 0.f;
+  for (int j = 0; j <= K; ++j) {
+    const int64_t v = g * (K + 1) + j;
+    if (j > 0) acc += opac_mul * (top[v] - opac_mul * o0);
+    cr += trgb[v];
+    cg += trgb[V + v];
+    cb += trgb[2 * V + v];
+  }
+  yg[3 * K] = acc / (1.f + opac_mul * opac_mul * K);
+  yg[3 * K + 1] = cr / (K + 1) - rgb[g];
+  yg[3 * K + 2] = cg / (K + 1) - rgb[n + g];
+  yg[3 * K + 3] = cb / (K + 1) - rgb[2 * n + g];
+}
+
+// mean squared error over n x m values and its gradient; partial sums per block
+__global__ __launch_bounds__(256) void k_vec_mse(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
+                                                 float gscale, float* __restrict__ dy, double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = y[i] - t[i];
+    acc += (double)d * d;
+    if (dy) dy[i] = 2.f * d * gscale;
+  }
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_vec_mse_sum(const double* __restrict__ part, int nb, double scale, float* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *out = (float)(s * scale);
+  }
+}
+
 inline unsigned gfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
 }  // namespace
 
 struct msp_refiner {
   int n_in = 15, n_out = 0;
-  DevBuf w1, w2, w3, w2t, w3t, b1, b2, b3p, train, grads;
+  DevBuf w1, w2, w3, w2t, w3t, b1, b2, b3p, train, grads, part;
   int64_t train_pad = 0;
 };
 
@@ -390,6 +463,7 @@ msp_refiner* refiner_new(int n_out) {
 
 void refiner_delete(msp_refiner* r) { delete r; }
 int refiner_n_out(const msp_refiner* r) { return r->n_out; }
+double* refiner_part(msp_refiner* r) { return (double*)r->part.p; }
 
 hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, const float* b1, const float* W2,
                                const float* b2, const float* W3, const float* b3) {
@@ -503,9 +577,33 @@ hipError_t launch_refiner_apply(hipStream_t s, const msp_gaussians* g, int K, fl
   return hipGetLastError();
 }
 
+hipError_t launch_refiner_targets(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                  const msp_faces* tuned, float* y) {
+  if (g->n == 0) return hipSuccess;
+  CS cs;
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < 64; ++k) {
+    cs.c[k] = k < K ? (float)std::cos(-pi + 2.0 * pi * k / K) : 0.f;
+    cs.s[k] = k < K ? (float)std::sin(-pi + 2.0 * pi * k / K) : 0.f;
+  }
+  hipLaunchKernelGGL(k_targets, dim3(gfor(g->n)), dim3(256), 0, s, g->mean, g->scale, g->quat, g->opacity, g->rgb,
+                     g->n, K, sigma, opac_mul, cs, tuned->pos, tuned->opacity, tuned->rgb, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, int64_t n, float* loss, float* dy,
+                          double* part) {
+  const unsigned nb = n > 0 ? (unsigned)std::min<int64_t>(1024, (n + 255) / 256) : 1;
+  hipLaunchKernelGGL(k_vec_mse, dim3(nb), dim3(256), 0, s, y, t, n, 1.f / (float)(n > 0 ? n : 1), dy, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vec_mse_sum, dim3(1), dim3(64), 0, s, part, (int)nb, 1.0 / (double)(n > 0 ? n : 1), loss);
+  return hipGetLastError();
+}
+
 int refiner_alloc(msp_ctx* ctx, msp_refiner* r) {
   int rc;
-  if ((rc = msp_ensure(ctx, r->w1, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2, 2 * HID * HID)) ||
+  if ((rc = msp_ensure(ctx, r->part, 8 * 1024)) || (rc = msp_ensure(ctx, r->w1, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2, 2 * HID * HID)) ||
       (rc = msp_ensure(ctx, r->w3, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->w2t, 2 * HID * HID)) ||
       (rc = msp_ensure(ctx, r->w3t, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
       (rc = msp_ensure(ctx, r->b2, 4 * HID)) || (rc = msp_ensure(ctx, r->b3p, 4 * 32)) ||
@@ -519,7 +617,7 @@ int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N) {
 }
 
 void refiner_free_bufs(msp_refiner* r) {
-  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads};
+  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part};
   for (DevBuf* x : b)
     if (x->p) (void)hipFree(x->p);
 }

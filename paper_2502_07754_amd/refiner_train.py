@@ -1,0 +1,215 @@
+"""Refiner training and evaluation (the learned part; not in the paper).
+
+Pairs come from the method's own optimisation: for each seeded scene the plain
+fans are fine-tuned (pruning off, so every fine-tuned fan still lines up with
+its Gaussian) against target views, and per-Gaussian least-squares targets
+y* are fitted to the fine-tuned fans (msp_refiner_targets). The MLP is trained
+full-batch with Adam on its float32 masters by the library's own MFMA forward
+and backward kernels. Evaluation compares, on held-out scenes, the image error
+of refiner-initialised fans with plain conversion (no fine-tuning), and the
+wall-clock time fine-tuning needs from each start to reach the same error.
+
+Targets: the scene is perturbed (scenes.perturbed) and converted with the
+multi-ring conversion (a smoother stand-in for a Gaussian than the fan), then
+rendered by msp_render; the fan has to learn the systematic difference.
+
+    python -m paper_2502_07754_amd.refiner_train --help
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+from . import (MSP_LOSS_MSE, Refiner, RenderOptions, adam_step, convert, convert_rings, loss, refiner_apply,
+               refiner_features, refiner_loss, refiner_targets, render, scenes)
+from .finetune import FineTuneConfig, FineTuner
+
+HIDDEN = 256
+
+
+def views(res: int):
+    """16 views: two rings of 8 at elevations +30 and -30 degrees, radius 3."""
+    return scenes.ring_cameras(8, res, res, 3.0, 30.0) + scenes.ring_cameras(8, res, res, 3.0, -30.0)
+
+
+def to_gpu(g: scenes.Gaussians):
+    import numpy as np
+    import torch
+    return {k: (None if v is None else torch.from_numpy(np.ascontiguousarray(v)).cuda())
+            for k, v in dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=None).items()}
+
+
+def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3):
+    tg = scenes.perturbed(g, seed)
+    tf = convert_rings(to_gpu(tg), ring_k, rings, 3.0)
+    img, _ = render(tf, cams, RenderOptions())
+    return img[:, :3].contiguous()
+
+
+def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-2, log=print):
+    import torch
+    xs, ys = [], []
+    for s in seeds:
+        g = scenes.gaussians(n, s, 0.01, 0.1, flat=True)
+        cams = views(res)
+        tgt = target_images(g, cams, s + 1)
+        gg = to_gpu(g)
+        faces = convert(gg, K, sigma)
+        ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=0))
+        l0 = None
+        for i in range(steps):
+            L = ft.step()
+            if i == 0:
+                l0 = float(L.item())
+        xs.append(refiner_features(gg, K))
+        ys.append(refiner_targets(gg, K, sigma, ft.faces))
+        log(f"pairs: scene {s}: fine-tune MSE {l0:.5f} -> {float(L.item()):.5f}")
+    return torch.cat(xs), torch.cat(ys)
+
+
+def init_params(n_out, seed=0):
+    """He-initialised hidden layers, zero last layer (the untrained refiner is the plain conversion)."""
+    import torch
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    p = dict(W1=torch.randn((HIDDEN, 15), generator=gen, device="cuda") * math.sqrt(2 / 15),
+             b1=torch.zeros(HIDDEN, device="cuda"),
+             W2=torch.randn((HIDDEN, HIDDEN), generator=gen, device="cuda") * math.sqrt(2 / HIDDEN),
+             b2=torch.zeros(HIDDEN, device="cuda"),
+             W3=torch.zeros((n_out, HIDDEN), device="cuda"), b3=torch.zeros(n_out, device="cuda"))
+    return {k: v.contiguous() for k, v in p.items()}
+
+
+def train(x, ys, steps=400, lr=1e-3, seed=0, log=print):
+    """Full-batch Adam on the float32 masters; forward/backward on the MFMA kernels."""
+    import torch
+    n_out = ys.shape[1]
+    R = Refiner(n_out)
+    p = init_params(n_out, seed)
+    m = {k: torch.zeros_like(v) for k, v in p.items()}
+    v = {k: torch.zeros_like(t) for k, t in p.items()}
+    R.set_weights(p)
+    hist = []
+    for t in range(1, steps + 1):
+        y = R.forward(x)
+        L, dy = refiner_loss(R, y, ys)
+        g = R.backward(x, dy)
+        adam_step([dict(param=p[k], grad=g[k], m=m[k], v=v[k], lr=lr) for k in p], t)
+        R.set_weights(p)
+        if t == 1 or t % 50 == 0 or t == steps:
+            hist.append((t, float(L.item())))
+            log(f"train: step {t} loss {hist[-1][1]:.6f}")
+    return R, p, hist
+
+
+def image_mse(faces, cams, tgt) -> float:
+    img, _ = render(faces, cams, RenderOptions())
+    L, _ = loss(img, tgt, MSP_LOSS_MSE, want_grad=False)
+    return float(L.item())
+
+
+def evaluate(R, seeds, n=12_500, K=8, sigma=2.0, res=256):
+    """Image MSE against the targets of plain and refiner-initialised fans (no fine-tuning)."""
+    out = []
+    for s in seeds:
+        g = scenes.gaussians(n, s, 0.01, 0.1, flat=True)
+        cams = views(res)
+        tgt = target_images(g, cams, s + 1)
+        gg = to_gpu(g)
+        plain = image_mse(convert(gg, K, sigma), cams, tgt)
+        y = R.forward(refiner_features(gg, K))
+        refined = image_mse(refiner_apply(gg, K, sigma, y), cams, tgt)
+        out.append(dict(seed=s, plain=plain, refined=refined))
+    return out
+
+
+def time_to_mse(g: scenes.Gaussians, cams, tgt, K=8, sigma=2.0, steps=1000, R=None, target=None, lr_color=1e-2,
+                prune_every=10, opts=None):
+    """Wall-clock seconds of conversion (+ refiner inference) + fine-tuning until the
+    training MSE reaches `target` (or `steps` steps when target is None)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gg = to_gpu(g)
+    if R is None:
+        faces = convert(gg, K, sigma)
+    else:
+        faces = refiner_apply(gg, K, sigma, R.forward(refiner_features(gg, K)))
+    ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=prune_every), opts)
+    curve = []
+    reached = None
+    for i in range(steps):
+        L = ft.step()
+        if target is not None or i == steps - 1 or i % 10 == 0:
+            lv = float(L.item())          # the MSE of the render this step started from
+            curve.append((i, lv))
+            if target is not None and lv <= target:
+                reached = i
+                break
+    torch.cuda.synchronize()
+    return dict(seconds=time.perf_counter() - t0, steps=(reached if reached is not None else steps),
+                reached=reached is not None or target is None, final_mse=curve[-1][1], curve=curve[::max(1, len(curve) // 20)])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--train-seeds", type=int, default=20)
+    ap.add_argument("--n", type=int, default=12_500)
+    ap.add_argument("--pair-steps", type=int, default=500)
+    ap.add_argument("--res", type=int, default=256)
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--infer-n", type=int, default=1_000_000)
+    ap.add_argument("--ft-n", type=int, default=0, help="Gaussians of the time-to-MSE run (0: skip)")
+    ap.add_argument("--ft-views", type=int, default=16)
+    ap.add_argument("--ft-res", type=int, nargs=2, default=(1920, 1080))
+    ap.add_argument("--ft-steps", type=int, default=1000)
+    args = ap.parse_args()
+    import torch
+
+    def log(*a):
+        print(*a, flush=True)
+
+    res = {}
+    t = time.perf_counter()
+    x, ys = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res, log=log)
+    res["pairs"] = dict(samples=int(x.shape[0]), faces=int(x.shape[0]) * 8, seconds=time.perf_counter() - t)
+    t = time.perf_counter()
+    R, p, hist = train(x, ys, steps=args.train_steps, lr=args.lr, log=log)
+    torch.cuda.synchronize()
+    res["train"] = dict(seconds=time.perf_counter() - t, loss=hist)
+    ev = evaluate(R, range(2000, 2005), n=args.n, res=args.res)
+    import statistics as st
+    gain = [e["plain"] / e["refined"] for e in ev]
+    res["heldout"] = dict(per_seed=ev, plain_mean=st.mean(e["plain"] for e in ev),
+                          refined_mean=st.mean(e["refined"] for e in ev), ratio_mean=st.mean(gain),
+                          ratio_sd=st.pstdev(gain))
+    # inference throughput on 1M Gaussians (MFMA forward)
+    g = scenes.gaussians(args.infer_n, 7, 0.01, 0.1, flat=True)
+    xi = refiner_features(to_gpu(g), 8)
+    R.forward(xi)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        R.forward(xi)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    flop = 2.0 * (16 * 256 + 256 * 256 + 256 * 32) * args.infer_n   # padded operands as executed
+    res["inference"] = dict(n=args.infer_n, ms=dt * 1e3, tflops=flop / dt / 1e12, frac_of_bf16_peak=flop / dt / 2.5e15)
+    log(json.dumps(res["inference"]))
+    if args.ft_n:
+        g = scenes.gaussians(args.ft_n, 0, 0.01, 0.1, flat=True)
+        cams = scenes.ring_cameras(args.ft_views, args.ft_res[0], args.ft_res[1])
+        tgt = target_images(g, cams, 1)
+        plain = time_to_mse(g, cams, tgt, steps=args.ft_steps)
+        log(f"plain: {plain['seconds']:.1f} s, final MSE {plain['final_mse']:.6f}")
+        refined = time_to_mse(g, cams, tgt, steps=args.ft_steps, R=R, target=plain["final_mse"])
+        log(f"refined: {refined['seconds']:.1f} s to MSE {plain['final_mse']:.6f} ({refined['steps']} steps)")
+        res["time_to_mse"] = dict(n=args.ft_n, views=args.ft_views, res=list(args.ft_res), plain=plain, refined=refined)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
