@@ -93,6 +93,10 @@ typedef struct msp_render_opts {
   int32_t color_mode;     /* MSP_COLOR_RGB or MSP_COLOR_SH3 */
   float t_eps;            /* a pixel stops once its transmittance falls below t_eps (>= 0) */
   float bg[3];            /* background colour */
+  int32_t list_rows;      /* > 0: the forward stores every pixel's ordered fragment list (up to
+                             list_rows fragments per pixel) for msp_render_backward, which then
+                             does not recompute them; lists longer than that fall back to
+                             recomputation. 0: the backward recomputes the lists (least memory). */
 } msp_render_opts;
 
 /* Gradients, caller-owned, OVERWRITTEN by msp_render_backward (not accumulated).

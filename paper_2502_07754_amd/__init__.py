@@ -100,10 +100,11 @@ class RenderOptions:
     t_eps: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
     color_mode: int = MSP_COLOR_RGB
+    list_rows: int = 0     # > 0: the forward stores fragment lists for the backward (0: recomputed)
 
     def struct(self) -> _lib.RenderOpts:
         return _lib.RenderOpts(self.tile_w, self.tile_h, self.kbuf, self.color_mode, self.t_eps,
-                               (C.c_float * 3)(*self.bg))
+                               (C.c_float * 3)(*self.bg), self.list_rows)
 
 
 class RenderState:
@@ -282,7 +283,7 @@ def autotune(faces: dict, cams, base: "RenderOptions", dimg=None) -> "RenderOpti
                                    None if dimg is None else _dev_ptr(_need(dimg, torch.float32, "dimg")),
                                    C.byref(G), C.byref(out)), "msp_autotune")
     return RenderOptions(tile_w=out.tile_w, tile_h=out.tile_h, kbuf=out.kbuf, t_eps=out.t_eps,
-                         bg=tuple(out.bg), color_mode=out.color_mode)
+                         bg=tuple(out.bg), color_mode=out.color_mode, list_rows=out.list_rows)
 
 
 MSP_LOSS_MSE, MSP_LOSS_L1, MSP_LOSS_L1_DSSIM = 0, 1, 2

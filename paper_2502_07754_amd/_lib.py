@@ -34,7 +34,7 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("kbuf", C.c_int32), ("color_mode", C.c_int32),
-                ("t_eps", C.c_float), ("bg", C.c_float * 3)]
+                ("t_eps", C.c_float), ("bg", C.c_float * 3), ("list_rows", C.c_int32)]
 
 
 class FaceGrads(C.Structure):

@@ -550,6 +550,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   if (opts->color_mode == MSP_COLOR_RGB && f->n_faces > 0 && !f->rgb) return bad("RGB mode needs f->rgb");
   if (opts->color_mode == MSP_COLOR_SH3 && f->n_faces > 0 && !f->sh) return bad("SH mode needs f->sh");
   if (opts->color_mode == MSP_COLOR_SH3 && n_views > sh_max_views()) return bad("SH mode supports at most 64 views");
+  if (opts->list_rows < 0 || opts->list_rows > 4096) return bad("list_rows must be in [0, 4096]");
 
   DeviceGuard dg(ctx->device);
   st->n_views = n_views;
@@ -612,6 +613,18 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   }
   fill_args(st, f, a);
   a.img = img;
+  // stored fragment lists: a fixed number of rows per 8x8 block (sticky fallback to
+  // recomputation once a render of this state has overflowed them)
+  const int64_t nblk = V * ((W + 7) / 8) * ((H + 7) / 8);
+  st->store_rows = (opts->list_rows > 0 && !st->lists_overflowed) ? opts->list_rows : 0;
+  if (st->store_rows) {
+    if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * nblk * st->store_rows))) {
+      if (graph) return (msp_status)rc;
+      st->store_rows = 0;  // not enough memory: recompute instead
+    }
+  }
+  a.frag_list = P<uint2>(st->frag_list);
+  a.store_rows = st->store_rows;
   MSP_HIP(ctx, launch_fill_u32(s, a.cursor, 0u, NT));
   MSP_TIMED(ctx, ST_EMIT, launch_emit(s, a));
   MSP_TIMED(ctx, ST_SORT, launch_tile_sort(s, a));
@@ -649,6 +662,38 @@ static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f,
   fill_args(st, f, a);
   a.blk_cap = P<uint32_t>(st->blk_cap);
   a.blk_off = P<int64_t>(st->blk_off);
+  bool stored = st->store_rows > 0;
+  if (stored && !graph) {
+    // lists stored by the forward are used unless a block overflowed them
+    MSP_HIP(ctx, hipMemcpyAsync(st->h_flag, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5),
+                                sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP(ctx, hipStreamSynchronize(s));
+    if (*st->h_flag & 4u) {
+      stored = false;
+      st->lists_overflowed = true;
+      st->store_rows = 0;
+    }
+  }
+  if (stored) {
+    a.dimg = dimg;
+    a.dpos = grads->dpos;
+    a.dop = grads->dopacity;
+    a.drgb = shm ? nullptr : grads->drgb;
+    a.frag_list = P<uint2>(st->frag_list);
+    a.store_rows = st->store_rows;
+    if (shm) {
+      const int64_t nc = 3 * (int64_t)st->n_views * f->n_faces;
+      if ((rc = msp_ensure(ctx, st->dcol, sizeof(float) * nc))) return (msp_status)rc;
+      MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
+      a.dcol = P<float>(st->dcol);
+    }
+    MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 4));
+    MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
+    if (shm && grads->dsh)
+      MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
+    return MSP_OK;
+  }
+  a.store_rows = 0;
   MSP_TIMED(ctx, ST_BLOCK_MAX, launch_block_max(s, a));
   MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
   if (graph) {
@@ -769,6 +814,10 @@ msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* ca
       return MSP_OK;
     }
     ++st->graph_overflows;  // a capacity was short: run uncaptured and capture again
+    if (ovf & 4u) {         // stored lists overflowed: recompute them from now on
+      st->lists_overflowed = true;
+      st->store_rows = 0;
+    }
   }
   msp_status r = render_impl(ctx, f, cams, n_views, opts, img, st, false);
   if (r != MSP_OK) return r;

@@ -46,6 +46,8 @@ struct msp_state {
   msp_camera* h_cams = nullptr;  // host copy
   int h_cams_cap = 0;
   int64_t rows = 0;              // backward list rows of the last uncaptured run
+  int64_t store_rows = 0;        // rows per block the forward stores lists into (0: none)
+  bool lists_overflowed = false; // a render of this state overflowed its stored lists: recompute from now on
   // captured fwd+bwd step
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -109,7 +111,8 @@ struct RasterArgs {
   // backward
   const float* dimg;
   const int64_t* blk_off;  // [n_blocks + 1] in units of 64-slot rows
-  uint2* frag_list;        // recomputed fragment lists
+  uint2* frag_list;        // fragment lists (stored by the forward when store_rows > 0, else recomputed)
+  int64_t store_rows;      // rows per 8x8 block of lists stored by the forward (0: recompute in backward)
   int64_t frag_cap;
   uint32_t* blk_cap;       // [n_blocks]
   float* dpos;

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
 // emit: scatter keys into the tile segments
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
-  if (*a.ovf) return;
+  if (*a.ovf & 3u) return;
   const int view = blockIdx.y;
   const int64_t F = a.n_faces;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,7 +288,7 @@ template <int CAP, bool BIG>
 __global__ __launch_bounds__(256) void k_tile_sort(RasterArgs a, int64_t n_seg) {
   __shared__ uint64_t s[CAP];
   const int64_t seg = blockIdx.x;
-  if (seg >= n_seg || *a.ovf) return;
+  if (seg >= n_seg || (*a.ovf & 3u)) return;
   const int64_t beg = a.tile_off[seg];
   const int64_t n = a.tile_off[seg + 1] - beg;
   if (n <= 1) return;
@@ -467,7 +467,7 @@ __device__ __forceinline__ Prefetch prefetch_entry(const RasterArgs& a, const It
 // Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1 also
 // records each composited fragment (face id, transmittance before it) into the
 // block's list slab.
-template <int KB, int MODE>
+template <int KB, int MODE, bool SHP>
 __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, int lane, float& T, float& Cr,
                             float& Cg, float& Cb, int& nf, uint32_t& restarts, uint2* list, int64_t list_rows) {
   const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
@@ -493,13 +493,23 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
   int state = valid ? ACTIVE : DONE;
 
   auto pop_front = [&]() {
-    if (MODE == 1) {
+    if (list != nullptr) {
       if (nf < list_rows) list[(int64_t)nf * MSP_WAVE + lane] = make_uint2(kb.f[0], __float_as_uint(T));
     }
-    const float w = T * kb.al[0];
-    Cr = fmaf(w, kb.cr[0], Cr);
-    Cg = fmaf(w, kb.cg[0], Cg);
-    Cb = fmaf(w, kb.cb[0], Cb);
+    if (MODE == 0) {
+      const float w = T * kb.al[0];
+      if (SHP) {
+        // per-face colour of this view, fetched when the fragment is composited
+        const float4 c = a.col4[(int64_t)it.view * a.n_faces + kb.f[0]];
+        Cr = fmaf(w, c.x, Cr);
+        Cg = fmaf(w, c.y, Cg);
+        Cb = fmaf(w, c.z, Cb);
+      } else {
+        Cr = fmaf(w, kb.cr[0], Cr);
+        Cg = fmaf(w, kb.cg[0], Cg);
+        Cb = fmaf(w, kb.cb[0], Cb);
+      }
+    }
     T = T * (1.f - kb.al[0]);
     last = mkkey(kb.z[0], kb.f[0]);
     ++nf;
@@ -508,9 +518,11 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       kb.z[i] = kb.z[i + 1];
       kb.f[i] = kb.f[i + 1];
       kb.al[i] = kb.al[i + 1];
-      kb.cr[i] = kb.cr[i + 1];
-      kb.cg[i] = kb.cg[i + 1];
-      kb.cb[i] = kb.cb[i + 1];
+      if (!SHP && MODE == 0) {
+        kb.cr[i] = kb.cr[i + 1];
+        kb.cg[i] = kb.cg[i + 1];
+        kb.cb[i] = kb.cb[i + 1];
+      }
     }
     kb.z[KB - 1] = __uint_as_float(0x7f800000u);
     kb.f[KB - 1] = kEmpty;
@@ -532,23 +544,49 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       drop = ~0ull;
       ++restarts;
     }
-    uint64_t next_key = lane < n ? a.keys[beg + lane] : ~0ull;
+    // keys run two chunks ahead and footprints one chunk ahead of the staging, so
+    // the dependent loads overlap the processing of the current chunk
+    const float4* geo_v = a.geo + (int64_t)it.view * a.n_faces * 3;
+    uint64_t key_cur = lane < n ? a.keys[beg + lane] : ~0ull;
+    uint64_t key_nxt = MSP_WAVE + lane < n ? a.keys[beg + MSP_WAVE + lane] : ~0ull;
+    float4 fp_cur = geo_v[(int64_t)((uint64_t)(uint32_t)key_cur < (uint64_t)a.n_faces ? (uint32_t)key_cur : 0) * 3 + 2];
     for (int64_t base = 0; base < n; base += MSP_WAVE) {
       if (!__any(state == ACTIVE)) break;
       // ---- stage this chunk (ballot-compacted to faces meeting the block) ----
-      Prefetch pf;
-      pf.key = next_key;
-      pf.ok = base + lane < n && (uint64_t)(uint32_t)pf.key < (uint64_t)a.n_faces;
-      pf.q = fetch_face(a, it.view, pf.ok ? (int32_t)(uint32_t)pf.key : 0);
-      // the next chunk's keys are fetched while this one is processed
-      next_key = base + MSP_WAVE + lane < n ? a.keys[beg + base + MSP_WAVE + lane] : ~0ull;
+      const uint64_t key = key_cur;
+      const float4 g2 = fp_cur;
+      const uint32_t fk = (uint32_t)key;
+      const bool ok = base + lane < n && (uint64_t)fk < (uint64_t)a.n_faces;
+      // prefetch: footprints of the next chunk, keys of the one after
+      const uint32_t fn = (uint32_t)key_nxt;
+      fp_cur = geo_v[(int64_t)((uint64_t)fn < (uint64_t)a.n_faces ? fn : 0) * 3 + 2];
+      key_cur = key_nxt;
+      key_nxt = base + 2 * MSP_WAVE + lane < n ? a.keys[beg + base + 2 * MSP_WAVE + lane] : ~0ull;
       bool keep = false;
       float R[kRec];
-      if (pf.ok) {
-        const uint32_t xr = __float_as_uint(pf.q.g2.y), yr = __float_as_uint(pf.q.g2.z);
+      if (ok) {
+        const uint32_t xr = __float_as_uint(g2.y), yr = __float_as_uint(g2.z);
         const int px0 = xr & 0xffff, px1 = xr >> 16, py0 = yr & 0xffff, py1 = yr >> 16;
         keep = px0 <= px1 && px0 <= it.bx0 + 7 && px1 >= it.bx0 && py0 <= it.by0 + 7 && py1 >= it.by0;
-        if (keep) keep = build_record(pf.q, (uint32_t)pf.key, rx, ry, R);
+      }
+      if (keep) {
+        // full records only for the faces that meet this block
+        Fetched q;
+        const float4* gp = geo_v + (int64_t)fk * 3;
+        q.g0 = gp[0];
+        q.g1 = gp[1];
+        q.g2 = g2;
+        const float4* ap = a.attr + (int64_t)fk * 4;
+        q.a0 = ap[0];
+        if (a.col4) {
+          q.a1 = a.col4[(int64_t)it.view * a.n_faces + fk];
+          q.a2 = q.a3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          q.a1 = ap[1];
+          q.a2 = ap[2];
+          q.a3 = ap[3];
+        }
+        keep = build_record(q, fk, rx, ry, R);
       }
       const uint64_t m = __ballot(keep);
       const int cnt = __popcll(m);
@@ -594,17 +632,21 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
                       kb.z[i] = up ? kb.z[i - 1] : (put ? z : kb.z[i]);
                       kb.f[i] = up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
                       kb.al[i] = up ? kb.al[i - 1] : (put ? al : kb.al[i]);
-                      kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
-                      kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
-                      kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
+                      if (!SHP && MODE == 0) {
+                        kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
+                        kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
+                        kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
+                      }
                     }
                     if (cpos[0]) {
                       kb.z[0] = z;
                       kb.f[0] = fid;
                       kb.al[0] = al;
-                      kb.cr[0] = cr;
-                      kb.cg[0] = cg;
-                      kb.cb[0] = cb;
+                      if (!SHP && MODE == 0) {
+                        kb.cr[0] = cr;
+                        kb.cg[0] = cg;
+                        kb.cb[0] = cb;
+                      }
                     }
                   }
                 }
@@ -625,14 +667,14 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
   }
 }
 
-template <int KB>
+template <int KB, bool SHP>
 __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_items) {
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint64_t frags = 0;
   uint32_t restarts = 0;
-  if (*a.ovf) return;
+  if (*a.ovf & 3u) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[2], 1ull);
@@ -642,7 +684,14 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
     if (!decode_item(a, item, it)) continue;
     float T, Cr, Cg, Cb;
     int nf;
-    trace_block<KB, 0>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, nullptr, 0);
+    uint2* list = a.store_rows ? a.frag_list + it.blk * a.store_rows * MSP_WAVE : nullptr;
+    trace_block<KB, 0, SHP>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, list, a.store_rows);
+    if (a.store_rows) {
+      // a block whose longest list does not fit is recomputed by the backward pass
+      int mx = nf;
+      for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+      if (lane == 0 && mx > a.store_rows) atomicOr(a.ovf, 4u);
+    }
     const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
     if (px < a.W && py < a.H) {
       const int64_t plane = (int64_t)a.H * a.W;
@@ -687,7 +736,7 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
   uint32_t restarts = 0;
-  if (*a.ovf) return;
+  if (*a.ovf & 3u) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[3], 1ull);
@@ -699,7 +748,7 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
     const int64_t rows = a.blk_off[it.blk + 1] - row0;
     float T, Cr, Cg, Cb;
     int nf;
-    trace_block<KB, 1>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, a.frag_list + row0 * MSP_WAVE, rows);
+    trace_block<KB, 1, false>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, a.frag_list + row0 * MSP_WAVE, rows);
   }
 }
 
@@ -791,7 +840,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  if (*a.ovf) return;
+  if (*a.ovf & (a.store_rows ? 7u : 3u)) return;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[4], 1ull);
@@ -799,8 +848,14 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     if (item >= n_items) break;
     Item it;
     if (!decode_item(a, item, it)) continue;
-    const int64_t row0 = a.blk_off[it.blk];
-    const int64_t rows = a.blk_off[it.blk + 1] - row0;
+    int64_t row0, rows;
+    if (a.store_rows) {
+      row0 = it.blk * a.store_rows;
+      rows = a.store_rows;
+    } else {
+      row0 = a.blk_off[it.blk];
+      rows = a.blk_off[it.blk + 1] - row0;
+    }
     const uint2* list = a.frag_list + row0 * MSP_WAVE;
     const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
     const bool valid = px < a.W && py < a.H;
@@ -976,14 +1031,21 @@ hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a) {
   return hipGetLastError();
 }
 
+template <int KB, bool SHP>
+static void launch_comp(hipStream_t s, const RasterArgs& a, int n_cu, uint32_t n_items) {
+  const int g = persistent_grid(k_composite<KB, SHP>, n_cu, n_items);
+  hipLaunchKernelGGL((k_composite<KB, SHP>), dim3(g), dim3(256), 0, s, a, n_items);
+}
+
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
   const uint32_t n_items = n_items_of(a);
+  const bool sh = a.col4 != nullptr;
   if (kbuf == 8) {
-    const int g = persistent_grid(k_composite<8>, n_cu, n_items);
-    hipLaunchKernelGGL(k_composite<8>, dim3(g), dim3(256), 0, s, a, n_items);
+    if (sh) launch_comp<8, true>(s, a, n_cu, n_items);
+    else launch_comp<8, false>(s, a, n_cu, n_items);
   } else {
-    const int g = persistent_grid(k_composite<16>, n_cu, n_items);
-    hipLaunchKernelGGL(k_composite<16>, dim3(g), dim3(256), 0, s, a, n_items);
+    if (sh) launch_comp<16, true>(s, a, n_cu, n_items);
+    else launch_comp<16, false>(s, a, n_cu, n_items);
   }
   return hipGetLastError();
 }

@@ -354,3 +354,33 @@ def test_sh_backward_multiview(gpu):
     for k, rk in (("dpos", "dpos"), ("dopacity", "dop"), ("dsh", "dsh")):
         ok, ex = grad_close(gr[k].cpu().numpy(), ref[rk])
         assert ok, (k, ex)
+
+
+@pytest.mark.parametrize("sh", [False, True])
+def test_stored_lists_backward_matches_recompute(gpu, sh):
+    """Lists stored by the forward give the same gradients as recomputed ones; a
+    row budget too small for the scene falls back to recomputation."""
+    import torch
+    f = to_gpu(_sh_scene(n=500, K=8, seed=40) if sh else _oracle_faces(scenes.gaussians(500, 40, 0.02, 0.15, True), 8, 2.0))
+    cams = scenes.ring_cameras(2, 80, 64)
+    dimg = torch.from_numpy(scenes.upstream_grad(2, 64, 80, seed=6)).cuda()
+    cm = 1 if sh else 0
+    base = gpu.RenderOptions(color_mode=cm)
+    i0, s0 = gpu.render(f, cams, base)
+    g0 = gpu.render_backward(s0, f, dimg)
+    for rows in (64, 1):
+        o = gpu.RenderOptions(color_mode=cm, list_rows=rows)
+        i1, s1 = gpu.render(f, cams, o)
+        g1 = gpu.render_backward(s1, f, dimg)
+        torch.cuda.synchronize()
+        assert torch.equal(i0, i1)
+        for k in g0:
+            assert torch.allclose(g0[k], g1[k], rtol=1e-4, atol=1e-6 * float(g0[k].abs().max())), (rows, k)
+    # the captured step with stored lists
+    step = gpu.GraphStep(f, cams, gpu.RenderOptions(color_mode=cm, list_rows=64))
+    for _ in range(3):
+        img, gr = step(dimg)
+    torch.cuda.synchronize()
+    assert torch.equal(img, i0)
+    for k in g0:
+        assert torch.allclose(g0[k], gr[k], rtol=1e-4, atol=1e-6 * float(g0[k].abs().max()))
