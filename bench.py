@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="0: autotuned")
     ap.add_argument("--kbuf", type=int, default=0, help="0: autotuned")
     ap.add_argument("--no-graph", action="store_true", help="eager calls instead of the captured step")
+    ap.add_argument("--list-rows", type=int, default=128,
+                    help="fragment-list rows per pixel the forward stores for the backward (0: recompute)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -106,13 +108,14 @@ def main():
     ctx.timing(True)
     faces = msp.convert(gg, K, sigma)
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
-    opts = msp.RenderOptions(tile_w=args.tile, tile_h=args.tile, kbuf=args.kbuf, t_eps=1e-6, color_mode=1)
+    opts = msp.RenderOptions(tile_w=args.tile, tile_h=args.tile, kbuf=args.kbuf, t_eps=1e-6, color_mode=1,
+                             list_rows=args.list_rows)
     if args.tile == 0 or args.kbuf == 0:
         t0 = time.perf_counter()
         tuned = msp.autotune(faces, cams, opts, dimg)
         log(f"autotuned tile {tuned.tile_w}x{tuned.tile_h}, kbuf {tuned.kbuf} in {time.perf_counter() - t0:.1f} s")
         opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=args.tile or tuned.tile_h,
-                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=1)
+                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=1, list_rows=args.list_rows)
     state = msp.RenderState(ctx)
     if args.no_graph:
         def step():
@@ -190,7 +193,7 @@ def main():
         "config": {"workload": f"{args.n} flat Gaussians, K={K}, sigma={sigma}, SH degree 3, {args.views} views "
                                f"{W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
                    "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
-                   "hip_graph": not args.no_graph,
+                   "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
                    "entries_per_step": entries, "fragments_per_step": frags,
                    "fragments_per_s": frags / dt},
         "roofline": roof,
