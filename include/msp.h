@@ -322,7 +322,10 @@ msp_status msp_autotune(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams
 #define MSP_N_STAGES 12
 
 /* When on, every kernel stage is bracketed by a pair of HIP events recorded on
- * the context stream (adds two event records per stage; off by default). */
+ * the context stream (adds two event records per stage; off by default). A
+ * graph captured by msp_step_graph while timing is on carries the same pairs
+ * as event-record nodes; msp_step_graph reads them after each replay it has
+ * synchronised, so replays are timed on the stream they run on. */
 msp_status msp_timing_enable(msp_ctx* ctx, int on);
 /* Synchronises, then returns the summed milliseconds and call counts per stage
  * since the last read (HOST arrays of n_stages entries), and resets them. */

@@ -46,11 +46,10 @@ T* P(const DevBuf& b) {
 
 struct StageTimer {
   bool on = false;
-  struct Rec {
-    int stage;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> done;
+  std::vector<TimerRec> done;     // eager stages awaiting msp_timing_read
+  std::vector<TimerRec> captured; // stages recorded during the capture in progress
+  double acc_ms[ST_COUNT] = {};   // graph replays read so far
+  int64_t acc_calls[ST_COUNT] = {};
   std::vector<hipEvent_t> pool;
   hipEvent_t open[ST_COUNT] = {};
   hipEvent_t get() {
@@ -65,18 +64,43 @@ struct StageTimer {
   }
 };
 
+// While a graph is being captured the two events become event-record nodes of
+// the graph (added to the capture explicitly); every replay records them again.
+static bool timer_record(msp_ctx* ctx, hipEvent_t e) {
+  if (!ctx->capturing) {
+    const hipError_t r = hipEventRecord(e, ctx->stream);
+    if (r != hipSuccess) (void)hipGetLastError();  // timing is best effort: leave no sticky error behind
+    return r == hipSuccess;
+  }
+  // In a capture: an event-record node after the current capture frontier, made
+  // the new frontier, so the work captured next runs after it.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  hipGraphNode_t node = nullptr;
+  if (hipStreamGetCaptureInfo_v2(ctx->stream, &cs, nullptr, &g, &deps, &nd) != hipSuccess ||
+      cs != hipStreamCaptureStatusActive || !g || hipGraphAddEventRecordNode(&node, g, deps, nd, e) != hipSuccess ||
+      hipStreamUpdateCaptureDependencies(ctx->stream, &node, 1, hipStreamSetCaptureDependencies) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 void timer_begin(msp_ctx* ctx, int stage) {
   StageTimer* t = ctx->timer;
-  if (!t || !t->on || ctx->capturing) return;
+  if (!t || !t->on) return;
   hipEvent_t e = t->get();
-  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->open[stage] = e;
+  if (e && timer_record(ctx, e)) t->open[stage] = e;
 }
 
 void timer_end(msp_ctx* ctx, int stage) {
   StageTimer* t = ctx->timer;
-  if (!t || !t->on || ctx->capturing || !t->open[stage]) return;
+  if (!t || !t->on || !t->open[stage]) return;
   hipEvent_t e = t->get();
-  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) t->done.push_back({stage, t->open[stage], e});
+  if (e && timer_record(ctx, e))
+    (ctx->capturing ? t->captured : t->done).push_back({stage, t->open[stage], e});
   t->open[stage] = nullptr;
 }
 
@@ -128,10 +152,11 @@ msp_status msp_create(int device, void* hip_stream, msp_ctx** out) {
 msp_status msp_destroy(msp_ctx* ctx) {
   if (!ctx) return MSP_EINVAL;
   if (ctx->timer) {
-    for (auto& r : ctx->timer->done) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
+    for (auto* v : {&ctx->timer->done, &ctx->timer->captured})
+      for (auto& r : *v) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+      }
     for (hipEvent_t e : ctx->timer->pool) (void)hipEventDestroy(e);
     delete ctx->timer;
   }
@@ -162,7 +187,9 @@ msp_status msp_timing_read(msp_ctx* ctx, double* ms, int64_t* calls, int n_stage
   MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& r : ctx->timer->done) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.stage < n_stages) {
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+    } else if (r.stage < n_stages) {
       ms[r.stage] += t;
       calls[r.stage] += 1;
     }
@@ -170,6 +197,12 @@ msp_status msp_timing_read(msp_ctx* ctx, double* ms, int64_t* calls, int n_stage
     ctx->timer->pool.push_back(r.b);
   }
   ctx->timer->done.clear();
+  for (int i = 0; i < ST_COUNT && i < n_stages; ++i) {
+    ms[i] += ctx->timer->acc_ms[i];
+    calls[i] += ctx->timer->acc_calls[i];
+    ctx->timer->acc_ms[i] = 0.0;
+    ctx->timer->acc_calls[i] = 0;
+  }
   return MSP_OK;
 }
 
@@ -217,7 +250,7 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
   return MSP_OK;
 }
 
-static void free_graph(msp_state* st);
+static void free_graph(msp_ctx* ctx, msp_state* st);
 
 msp_status msp_loss(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views, int height,
                     int width, float* loss_out, float* dimg) {
@@ -463,7 +496,7 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
                     &st->blk_off, &st->frag_list, &st->col4, &st->dcol};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
-  free_graph(st);
+  free_graph(ctx, st);
   if (st->h_flag) (void)hipHostFree(st->h_flag);
   delete[] st->h_cams;
   delete st;
@@ -739,19 +772,42 @@ static void put(std::vector<unsigned char>& k, const T& v) {
 
 extern "C" {
 
-static void free_graph(msp_state* st) {
+static void free_graph(msp_ctx* ctx, msp_state* st) {
   if (st->graph_exec) (void)hipGraphExecDestroy(st->graph_exec);
   if (st->graph) (void)hipGraphDestroy(st->graph);
   st->graph_exec = nullptr;
   st->graph = nullptr;
   st->graph_key.clear();
+  for (auto& r : st->graph_timer)
+    for (hipEvent_t e : {r.a, r.b}) {
+      if (ctx->timer) ctx->timer->pool.push_back(e);
+      else (void)hipEventDestroy(e);
+    }
+  st->graph_timer.clear();
+}
+
+// adds the stage times of the replay that just finished (the stream has been synchronised)
+static void read_graph_timer(msp_ctx* ctx, msp_state* st) {
+  StageTimer* t = ctx->timer;
+  if (!t || !t->on) return;
+  for (auto& r : st->graph_timer) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    if (r.stage >= 0 && r.stage < ST_COUNT) {
+      t->acc_ms[r.stage] += ms;
+      t->acc_calls[r.stage] += 1;
+    }
+  }
 }
 
 static msp_status capture_step(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
                                const msp_render_opts* opts, float* img, const float* dimg, msp_face_grads* grads,
                                msp_state* st) {
   hipStream_t s = ctx->stream;
-  free_graph(st);
+  free_graph(ctx, st);
   // capacities with headroom over the uncaptured run that just sized them
   int rc;
   const int64_t ecap = st->entries + st->entries / 2 + 1024;
@@ -770,6 +826,10 @@ static msp_status capture_step(msp_ctx* ctx, const msp_faces* f, const msp_camer
   msp_status r2 = r1 == MSP_OK ? backward_impl(ctx, st, f, dimg, grads, true) : r1;
   ctx->stream = s;
   ctx->capturing = false;
+  if (ctx->timer) {
+    st->graph_timer.swap(ctx->timer->captured);
+    ctx->timer->captured.clear();
+  }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
   if (r1 != MSP_OK || r2 != MSP_OK) {
@@ -780,7 +840,7 @@ static msp_status capture_step(msp_ctx* ctx, const msp_faces* f, const msp_camer
   st->graph = g;
   e = hipGraphInstantiate(&st->graph_exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
-    free_graph(st);
+    free_graph(ctx, st);
     return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
   return MSP_OK;
@@ -811,6 +871,7 @@ msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* ca
     ovf = *st->h_flag;
     if (ovf == 0) {
       ++st->graph_replays;
+      read_graph_timer(ctx, st);
       return MSP_OK;
     }
     ++st->graph_overflows;  // a capacity was short: run uncaptured and capture again

@@ -19,6 +19,12 @@ struct DevBuf {
 
 struct StageTimer;
 
+// a pair of events bracketing one stage (eager: recorded on the stream; captured: event-record nodes of a graph)
+struct TimerRec {
+  int stage;
+  hipEvent_t a, b;
+};
+
 struct msp_ctx {
   StageTimer* timer = nullptr;
   int device = 0;
@@ -55,6 +61,7 @@ struct msp_state {
   std::vector<unsigned char> graph_key;
   uint32_t* h_flag = nullptr;    // pinned host copy of the overflow flag
   int64_t graph_captures = 0, graph_replays = 0, graph_overflows = 0;
+  std::vector<TimerRec> graph_timer;  // stage events captured into the graph (timing on at capture)
 
   DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
       scan_part, blk_cap, blk_off, frag_list, col4, dcol;

@@ -78,3 +78,31 @@ def test_autotune_choice_renders_identically(gpu):
     b, _ = gpu.render(f, cams, gpu.RenderOptions(tile_w=8, tile_h=8, kbuf=8))
     c, _ = gpu.render(f, cams, gpu.RenderOptions())  # context default is now the tuned choice
     assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_graph_replays_are_timed(gpu):
+    """Stage events captured into the graph are read back after every replay."""
+    import torch
+
+    from paper_2502_07754_amd import _lib
+    f = _scene(n=400, seed=24)
+    cams = scenes.ring_cameras(2, 64, 64)
+    opts = gpu.RenderOptions(tile_w=16, tile_h=16)
+    ctx = _lib.Context.get(0)
+    ctx.timing(True)
+    try:
+        step = gpu.GraphStep(f, cams, opts)
+        dimg = torch.from_numpy(scenes.upstream_grad(2, 64, 64, seed=3)).cuda()
+        step(dimg)                     # eager run + capture
+        torch.cuda.synchronize()
+        ctx.read_timing()
+        for _ in range(3):
+            step(dimg)
+        t = ctx.read_timing()
+        assert step.info()["replays"] == 3
+        assert t["composite"][1] == 3 and t["composite"][0] > 0.0
+        assert t["bwd_grads"][1] == 3 and t["setup"][1] == 3
+        assert ctx.read_timing()["composite"] == (0.0, 0)
+    finally:
+        ctx.timing(False)
+        ctx.read_timing()
