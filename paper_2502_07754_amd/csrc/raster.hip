@@ -379,13 +379,26 @@ __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float
   return true;
 }
 
+// Edge functions of the pixel at block offset (dx, dy).
+__device__ __forceinline__ void edges(const float* R, float dx, float dy, float& E0, float& E1, float& E2) {
+  E0 = fmaf(R[3], dy, fmaf(R[2], dx, R[1]));
+  E1 = fmaf(R[6], dy, fmaf(R[5], dx, R[4]));
+  E2 = fmaf(R[9], dy, fmaf(R[8], dx, R[7]));
+}
+
+// Closed-edge coverage test (the first test pixel_eval makes).
+__device__ __forceinline__ bool covers(const float* R, float dx, float dy) {
+  float E0, E1, E2;
+  edges(R, dx, dy, E0, E1, E2);
+  return E0 >= 0.f && E1 >= 0.f && E2 >= 0.f;
+}
+
 // Coverage and perspective-correct barycentrics of the pixel at block offset (dx, dy).
 __device__ __forceinline__ bool pixel_eval(const float* R, float dx, float dy, float& z, float& b0, float& b1,
                                            float& b2) {
 #pragma clang fp contract(off)
-  const float E0 = fmaf(R[3], dy, fmaf(R[2], dx, R[1]));
-  const float E1 = fmaf(R[6], dy, fmaf(R[5], dx, R[4]));
-  const float E2 = fmaf(R[9], dy, fmaf(R[8], dx, R[7]));
+  float E0, E1, E2;
+  edges(R, dx, dy, E0, E1, E2);
   if (E0 < 0.f || E1 < 0.f || E2 < 0.f) return false;
   const float w0 = E0 * R[10], w1 = E1 * R[11], w2 = E2 * R[12];
   const float s = (w0 + w1) + w2;
@@ -597,64 +610,72 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      // ---- stream the staged faces in nearest-depth order ----
-      for (int j = 0; j < cnt; ++j) {
+      // ---- coverage of this lane's pixel by every staged face (the edge tests
+      // pixel_eval repeats, bit for bit), so that each lane walks only the
+      // faces that cover it: a sliver face meets a handful of the 64 pixels ----
+      uint64_t cov = 0;
+      if (state == ACTIVE) {
+        for (int j = 0; j < cnt; ++j)
+          if (covers(slab + j * kRec, dx, dy)) cov |= 1ull << j;
+      }
+      // ---- each lane streams its covering faces in nearest-depth order; pops
+      // owed to the faces it skips happen at its next covering face (whose
+      // nearest depth is no smaller), which composites the same fragments ----
+      while (cov) {
+        const int j = __builtin_ctzll(cov);
+        cov &= cov - 1;
         const float* S = slab + j * kRec;
-        if (state == ACTIVE) {
-          const float W = S[0];
-          if (W > __uint_as_float((uint32_t)(drop >> 32))) {
-            // everything below the drop threshold has been seen: finish it, then re-scan
-            flush_all();
-            state = RESTART;
-          } else {
-            while (kb.z[0] < W && T >= eps) pop_front();
-            if (T < eps) {
-              state = DONE;
-            } else {
-              float z, b0, b1, b2;
-              if (pixel_eval(S, dx, dy, z, b0, b1, b2)) {
-                const uint32_t fid = __float_as_uint(S[16]);
-                const uint64_t nk = mkkey(z, fid);
-                if (nk > lo && nk < drop) {
-                  float raw, al, cr, cg, cb;
-                  frag_attr(S, sh, b0, b1, b2, raw, al, cr, cg, cb);
-                  const bool full = kb.f[KB - 1] != kEmpty;
-                  const uint64_t lastk = mkkey(kb.z[KB - 1], kb.f[KB - 1]);
-                  if (full) drop = nk < lastk ? lastk : nk;  // the largest of buffer + new is dropped
-                  if (!(full && nk > lastk)) {
-                    bool cpos[KB];
+        const float W = S[0];
+        if (W > __uint_as_float((uint32_t)(drop >> 32))) {
+          // everything below the drop threshold has been seen: finish it, then re-scan
+          flush_all();
+          state = RESTART;
+          cov = 0;
+          continue;
+        }
+        while (kb.z[0] < W && T >= eps) pop_front();
+        if (T < eps) {
+          state = DONE;
+          cov = 0;
+          continue;
+        }
+        float z, b0, b1, b2;
+        if (!pixel_eval(S, dx, dy, z, b0, b1, b2)) continue;
+        const uint32_t fid = __float_as_uint(S[16]);
+        const uint64_t nk = mkkey(z, fid);
+        if (!(nk > lo && nk < drop)) continue;
+        float raw, al, cr, cg, cb;
+        frag_attr(S, sh, b0, b1, b2, raw, al, cr, cg, cb);
+        const bool full = kb.f[KB - 1] != kEmpty;
+        const uint64_t lastk = mkkey(kb.z[KB - 1], kb.f[KB - 1]);
+        if (full) drop = nk < lastk ? lastk : nk;  // the largest of buffer + new is dropped
+        if (full && nk > lastk) continue;
+        bool cpos[KB];
 #pragma unroll
-                    for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(kb.z[i], kb.f[i]);
+        for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(kb.z[i], kb.f[i]);
 #pragma unroll
-                    for (int i = KB - 1; i >= 1; --i) {
-                      const bool up = cpos[i - 1];
-                      const bool put = !up && cpos[i];
-                      kb.z[i] = up ? kb.z[i - 1] : (put ? z : kb.z[i]);
-                      kb.f[i] = up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
-                      kb.al[i] = up ? kb.al[i - 1] : (put ? al : kb.al[i]);
-                      if (!SHP && MODE == 0) {
-                        kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
-                        kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
-                        kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
-                      }
-                    }
-                    if (cpos[0]) {
-                      kb.z[0] = z;
-                      kb.f[0] = fid;
-                      kb.al[0] = al;
-                      if (!SHP && MODE == 0) {
-                        kb.cr[0] = cr;
-                        kb.cg[0] = cg;
-                        kb.cb[0] = cb;
-                      }
-                    }
-                  }
-                }
-              }
-            }
+        for (int i = KB - 1; i >= 1; --i) {
+          const bool up = cpos[i - 1];
+          const bool put = !up && cpos[i];
+          kb.z[i] = up ? kb.z[i - 1] : (put ? z : kb.z[i]);
+          kb.f[i] = up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
+          kb.al[i] = up ? kb.al[i - 1] : (put ? al : kb.al[i]);
+          if (!SHP && MODE == 0) {
+            kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
+            kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
+            kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
           }
         }
-        if (!__any(state == ACTIVE)) break;
+        if (cpos[0]) {
+          kb.z[0] = z;
+          kb.f[0] = fid;
+          kb.al[0] = al;
+          if (!SHP && MODE == 0) {
+            kb.cr[0] = cr;
+            kb.cg[0] = cg;
+            kb.cb[0] = cb;
+          }
+        }
       }
       __builtin_amdgcn_wave_barrier();
     }
