@@ -491,8 +491,8 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
   if (!ctx || !st) return MSP_EINVAL;
   DeviceGuard dg(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&st->cams, &st->geo, &st->attr, &st->tile_cnt, &st->tile_off, &st->cursor, &st->vis,
-                    &st->vis_cnt, &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap,
+  DevBuf* bufs[] = {&st->cams, &st->geo, &st->attr, &st->tile_cnt, &st->tile_off, &st->cursor,
+                    &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap,
                     &st->blk_off, &st->frag_list, &st->col4, &st->dcol};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -525,8 +525,6 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.tile_cnt = P<uint32_t>(st->tile_cnt);
   a.tile_off = P<int64_t>(st->tile_off);
   a.cursor = P<uint32_t>(st->cursor);
-  a.vis = P<int32_t>(st->vis);
-  a.vis_cnt = P<uint32_t>(st->vis_cnt);
   a.keys = P<uint64_t>(st->keys);
   a.tmp = P<uint64_t>(st->tmp);
   a.key_cap = (int64_t)(st->keys.bytes / sizeof(uint64_t));
@@ -610,8 +608,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   if ((rc = msp_ensure(ctx, st->cams, sizeof(msp_camera) * V)) ||
       (rc = msp_ensure(ctx, st->geo, 48 * V * F)) || (rc = msp_ensure(ctx, st->attr, 64 * F)) ||
       (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
-      (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->vis, 4 * V * F)) ||
-      (rc = msp_ensure(ctx, st->vis_cnt, 4 * V)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
+      (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
       (rc = msp_ensure(ctx, st->counters, 8 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))))
     return (msp_status)rc;
   if (st->h_cams_cap < n_views) {
@@ -623,7 +620,6 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   hipStream_t s = ctx->stream;
   if (!graph) MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->tile_cnt), 0u, NT));
-  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->vis_cnt), 0u, V));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
 
   if (opts->color_mode == MSP_COLOR_SH3) {

@@ -63,7 +63,7 @@ struct msp_state {
   int64_t graph_captures = 0, graph_replays = 0, graph_overflows = 0;
   std::vector<TimerRec> graph_timer;  // stage events captured into the graph (timing on at capture)
 
-  DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, vis, vis_cnt, keys, tmp, nfrag, counters,
+  DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, keys, tmp, nfrag, counters,
       scan_part, blk_cap, blk_off, frag_list, col4, dcol;
 };
 
@@ -103,8 +103,6 @@ struct RasterArgs {
   uint32_t* tile_cnt;      // [V * n_tiles]
   int64_t* tile_off;       // [V * n_tiles + 1]
   uint32_t* cursor;        // [V * n_tiles]
-  int32_t* vis;            // [V][F]
-  uint32_t* vis_cnt;       // [V]
   uint64_t* keys;          // [entries]
   uint64_t* tmp;           // [entries]
   int64_t key_cap;

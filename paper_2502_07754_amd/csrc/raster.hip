@@ -6,13 +6,15 @@
 // Pipeline per render (all views in one launch per stage):
 //   setup      per (view, face): fixed-order float32 projection, near cull,
 //              pixel footprint with a 2^-8 px margin, nearest depth; writes a
-//              48-byte geometry record; per-tile counts with wavefront-
-//              aggregated atomics; visible faces compacted with a ballot.
+//              48-byte geometry record; per-tile counts gathered in a
+//              per-workgroup LDS tile table, then one global atomic per
+//              (workgroup, tile).
 //   attr       per face: corner opacities, colours and vertex ids packed in a
 //              64-byte record (view independent).
 //   scan       tile counts -> tile-list offsets (scan.hip).
-//   emit       per visible face: its key (bits(zmin) << 32 | face id) into
-//              every tile it touches (wavefront-aggregated slot reservation).
+//   emit       per face: its key (bits(zmin) << 32 | face id) into every
+//              tile it touches; each workgroup reserves one range per tile
+//              and hands out its slots from LDS.
 //   tile_sort  each tile list sorted ascending in LDS (bitonic; lists longer
 //              than the LDS tile are chunk-sorted then merged in place).
 //   composite  persistent: each wavefront pulls (view, 8x8 pixel block) work
@@ -72,28 +74,56 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (MSP_WAVE - 1); }
 
-// Adds `inc` to counter[t] for every active lane, one atomic per distinct t in
-// the wavefront; returns each lane's old-value-plus-rank (a unique slot).
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* counter, int64_t t, bool active, bool want_slot) {
-  const int lane = lane_id();
-  uint64_t pending = __ballot(active);
-  uint32_t slot = 0;
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int64_t t0 = __shfl(t, leader);
-    const uint64_t m = __ballot(active && t == t0);
-    uint32_t base = 0;
-    if (lane == leader) {
-      if (want_slot) base = atomicAdd(&counter[t0], (uint32_t)__popcll(m));
-      else atomicAdd(&counter[t0], (uint32_t)__popcll(m));
-    }
-    if (want_slot) {
-      base = __shfl(base, leader);
-      if (active && t == t0) slot = base + (uint32_t)__popcll(m & lanemask_lt(lane));
-    }
-    pending &= ~m;
+// Per-workgroup table of the tiles its faces touch (open addressing in LDS).
+// Binning through it turns one global atomic per (face, tile) into one per
+// (workgroup, tile): the 256 faces of a workgroup are 16 fans whose tiles repeat.
+constexpr int kTableSlots = 1024;
+
+__device__ __forceinline__ uint32_t table_hash(int32_t t) { return ((uint32_t)t * 2654435761u) >> 22; }
+
+// slot of tile t, inserting it if absent; -1 if the table is full
+__device__ __forceinline__ int table_insert(int32_t* key, int32_t t) {
+  const uint32_t h = table_hash(t);
+  for (int i = 0; i < kTableSlots; ++i) {
+    const int sl = (int)((h + i) & (kTableSlots - 1));
+    int32_t k = __atomic_load_n(&key[sl], __ATOMIC_RELAXED);
+    if (k == -1) k = atomicCAS(&key[sl], -1, t);
+    if (k == -1 || k == t) return sl;
   }
-  return slot;
+  return -1;
+}
+
+// slot of tile t after all insertions, -1 if it was not inserted
+__device__ __forceinline__ int table_find(const int32_t* key, int32_t t) {
+  const uint32_t h = table_hash(t);
+  for (int i = 0; i < kTableSlots; ++i) {
+    const int sl = (int)((h + i) & (kTableSlots - 1));
+    const int32_t k = key[sl];
+    if (k == t) return sl;
+    if (k == -1) return -1;
+  }
+  return -1;
+}
+
+// tile rectangle of a footprint record (xr, yr packed pixel bounds); empty if culled
+struct TileRect {
+  int tx0, tx1, ty0, ty1;
+};
+
+__device__ __forceinline__ TileRect tile_rect(const RasterArgs& a, const float4& g2) {
+  const uint32_t xr = __float_as_uint(g2.y), yr = __float_as_uint(g2.z);
+  const int px0 = xr & 0xffff, px1 = xr >> 16, py0 = yr & 0xffff, py1 = yr >> 16;
+  TileRect r;
+  if (px0 > px1 || py0 > py1) {
+    r.tx0 = r.ty0 = 0;
+    r.tx1 = r.ty1 = -1;
+  } else {
+    r.tx0 = px0 / a.tile_w;
+    r.tx1 = px1 / a.tile_w;
+    r.ty0 = py0 / a.tile_h;
+    r.ty1 = py1 / a.tile_h;
+  }
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,10 +135,9 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
   const int view = blockIdx.y;
   const int64_t F = a.n_faces, V = a.n_verts;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = lane_id();
   const msp_camera c = a.cams[view];
   bool ok = false;
-  int tx0 = 0, ty0 = 0, tw = 0, nt = 0;
+  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
   if (f < F) {
     float4 g0 = make_float4(0, 0, 0, 0), g1 = g0;
     float4 g2 = make_float4(0.f, __uint_as_float(1u), __uint_as_float(0u), 0.f);
@@ -135,8 +164,8 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
           const float zmin = fminf(fminf(p0.zc, p1.zc), p2.zc);
           tx0 = px0 / a.tile_w;
           ty0 = py0 / a.tile_h;
-          tw = px1 / a.tile_w - tx0 + 1;
-          nt = tw * (py1 / a.tile_h - ty0 + 1);
+          tx1 = px1 / a.tile_w;
+          ty1 = py1 / a.tile_h;
           ok = true;
           g0 = make_float4(p0.u, p0.v, p1.u, p1.v);
           g1 = make_float4(p2.u, p2.v, p0.zc, p1.zc);
@@ -150,21 +179,27 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
     geo[1] = g1;
     geo[2] = g2;
   }
-  // per-tile counts, one atomic per distinct tile per wavefront step
-  int maxnt = nt;
-  for (int d = 32; d >= 1; d >>= 1) maxnt = max(maxnt, __shfl_xor(maxnt, d));
-  uint32_t* cnt = a.tile_cnt + (int64_t)view * a.n_tiles;
-  for (int j = 0; j < maxnt; ++j) {
-    const bool act = j < nt;
-    const int64_t t = act ? (int64_t)(ty0 + j / tw) * a.ntx + tx0 + j % tw : -1;
-    wave_aggregated_add(cnt, t, act, false);
+  // per-tile counts through the workgroup's tile table
+  __shared__ int32_t tkey[kTableSlots];
+  __shared__ uint32_t tcnt[kTableSlots];
+  for (int i = threadIdx.x; i < kTableSlots; i += blockDim.x) {
+    tkey[i] = -1;
+    tcnt[i] = 0;
   }
-  // wavefront ballot compaction of the visible faces of this view
-  const uint64_t m = __ballot(ok);
-  uint32_t base = 0;
-  if (lane == 0 && m) base = atomicAdd(&a.vis_cnt[view], (uint32_t)__popcll(m));
-  base = __shfl(base, 0);
-  if (ok) a.vis[(int64_t)view * F + base + __popcll(m & lanemask_lt(lane))] = (int32_t)f;
+  __syncthreads();
+  uint32_t* cnt = a.tile_cnt + (int64_t)view * a.n_tiles;
+  if (ok) {
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const int32_t t = ty * a.ntx + tx;
+        const int sl = table_insert(tkey, t);
+        if (sl >= 0) atomicAdd(&tcnt[sl], 1u);
+        else atomicAdd(&cnt[t], 1u);
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTableSlots; i += blockDim.x)
+    if (tkey[i] >= 0) atomicAdd(&cnt[tkey[i]], tcnt[i]);
 }
 
 // attribute record (4 float4): (o0, o1, o2, id0) (r0, g0, b0, id1) (r1, g1, b1, id2) (r2, g2, b2, 0)
@@ -193,37 +228,49 @@ __global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
 // emit: scatter keys into the tile segments
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
-  if (*a.ovf & 3u) return;
+  if (*a.ovf & 3u) return;  // uniform: set before this launch
   const int view = blockIdx.y;
   const int64_t F = a.n_faces;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nvis = (int64_t)a.vis_cnt[view];
-  if ((int64_t)blockIdx.x * blockDim.x >= nvis) return;  // whole block idle (uniform)
-  int tx0 = 0, ty0 = 0, tw = 1, nt = 0;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  TileRect r{0, -1, 0, -1};
   uint64_t key = 0;
-  if (i < nvis) {
-    const int32_t f = a.vis[(int64_t)view * F + i];
+  if (f < F) {
     const float4 g2 = a.geo[((int64_t)view * F + f) * 3 + 2];
-    const uint32_t xr = __float_as_uint(g2.y), yr = __float_as_uint(g2.z);
-    const int px0 = xr & 0xffff, px1 = xr >> 16, py0 = yr & 0xffff, py1 = yr >> 16;
-    tx0 = px0 / a.tile_w;
-    ty0 = py0 / a.tile_h;
-    tw = px1 / a.tile_w - tx0 + 1;
-    nt = tw * (py1 / a.tile_h - ty0 + 1);
+    r = tile_rect(a, g2);
     key = ((uint64_t)__float_as_uint(g2.w) << 32) | (uint32_t)f;
   }
-  int maxnt = nt;
-  for (int d = 32; d >= 1; d >>= 1) maxnt = max(maxnt, __shfl_xor(maxnt, d));
-  const int64_t tb = (int64_t)view * a.n_tiles;
-  for (int j = 0; j < maxnt; ++j) {
-    const bool act = j < nt;
-    const int64_t t = act ? tb + (int64_t)(ty0 + j / tw) * a.ntx + tx0 + j % tw : -1;
-    const uint32_t slot = wave_aggregated_add(a.cursor, t, act, true);
-    if (act) {
-      const int64_t p = a.tile_off[t] + slot;
-      if (p < a.tile_off[t + 1] && p < a.key_cap) a.keys[p] = key;
-    }
+  __shared__ int32_t tkey[kTableSlots];
+  __shared__ uint32_t tcnt[kTableSlots];
+  __shared__ uint32_t tbase[kTableSlots];
+  for (int i = threadIdx.x; i < kTableSlots; i += blockDim.x) {
+    tkey[i] = -1;
+    tcnt[i] = 0;
   }
+  __syncthreads();
+  // 1: this workgroup's count per tile
+  for (int ty = r.ty0; ty <= r.ty1; ++ty)
+    for (int tx = r.tx0; tx <= r.tx1; ++tx) {
+      const int sl = table_insert(tkey, ty * a.ntx + tx);
+      if (sl >= 0) atomicAdd(&tcnt[sl], 1u);
+    }
+  __syncthreads();
+  // 2: one reservation per tile in the tile's segment
+  const int64_t tb = (int64_t)view * a.n_tiles;
+  for (int i = threadIdx.x; i < kTableSlots; i += blockDim.x) {
+    if (tkey[i] >= 0) tbase[i] = atomicAdd(&a.cursor[tb + tkey[i]], tcnt[i]);
+    tcnt[i] = 0;
+  }
+  __syncthreads();
+  // 3: every (face, tile) takes a slot of its workgroup's range (faces whose tile
+  // did not fit the table reserve their slot on their own)
+  for (int ty = r.ty0; ty <= r.ty1; ++ty)
+    for (int tx = r.tx0; tx <= r.tx1; ++tx) {
+      const int32_t t = ty * a.ntx + tx;
+      const int sl = table_find(tkey, t);
+      const uint32_t slot = sl >= 0 ? tbase[sl] + atomicAdd(&tcnt[sl], 1u) : atomicAdd(&a.cursor[tb + t], 1u);
+      const int64_t p = a.tile_off[tb + t] + slot;
+      if (p < a.tile_off[tb + t + 1] && p < a.key_cap) a.keys[p] = key;
+    }
 }
 
 // ---------------------------------------------------------------------------
