@@ -46,6 +46,8 @@ constexpr float kMargin = 0.00390625f;  // 2^-8 pixel
 constexpr int kRec = 28;                // floats per staged face record
 constexpr int kWavesPerWG = 4;
 constexpr int kHashSlots = 128;         // per-wave gradient table
+constexpr int kHashFill = 64;           // flushed once it holds more faces than this (short probe chains)
+constexpr int kHashProbes = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 enum : int { DONE = 0, ACTIVE = 1, RESTART = 2 };
@@ -831,9 +833,9 @@ struct GradLayout {
 };
 
 template <bool SH>
-__device__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float* vals, int lane) {
+__device__ void flush_table(const RasterArgs& a, int view, const float (&Wc)[12], uint32_t* keys, float* vals,
+                            uint32_t* fill, int lane) {
   using L = GradLayout<SH>;
-  const float* Wc = a.cams[view].world_to_cam;
   const int64_t F = a.n_faces, V = a.n_verts;
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) {
     const uint32_t f = keys[s];
@@ -843,8 +845,8 @@ __device__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float
     float v[L::NV];
 #pragma unroll
     for (int q = 0; q < L::NV; ++q) {
-      v[q] = vals[q * kHashSlots + s];
-      vals[q * kHashSlots + s] = 0.f;
+      v[q] = vals[s * L::NV + q];
+      vals[s * L::NV + q] = 0.f;
     }
     keys[s] = kEmpty;
     if (a.dop) {
@@ -877,18 +879,39 @@ __device__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float
       }
     }
   }
+  if (lane == 0) *fill = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 }
 
-__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t f) {
-  uint32_t h = (f * 0x9E3779B1u) >> 25;  // 7 bits
-  for (int p = 0; p < 32; ++p) {
+// One step of a segmented merge across lanes: lane l and its DPP partner
+// (l ^ D for the given control) that both still hold values of the same face
+// combine them in the lane with bit D clear; the other lane drops out. Must be
+// executed by the whole wave (DPP reads the partner's registers).
+template <int CTRL, int D, int NV>
+__device__ __forceinline__ void merge_step(uint32_t f, bool& alive, float (&val)[NV], int lane) {
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, CTRL, 0xf, 0xf, false);
+  const int ap = __builtin_amdgcn_mov_dpp(alive ? 1 : 0, CTRL, 0xf, 0xf, false);
+  const bool same = alive && ap != 0 && fp == f;
+  const bool take = same && (lane & D) == 0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const float vp = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(val[q]), CTRL, 0xf, 0xf, false));
+    val[q] = take ? val[q] + vp : val[q];
+  }
+  if (same && (lane & D) != 0) alive = false;
+}
+
+// slot of face f in the wave's table (inserted if absent; the fill count grows), -1 if none
+__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_t f) {
+  const uint32_t h = (f * 0x9E3779B1u) >> 25;  // 7 bits = log2(kHashSlots)
+  for (int p = 0; p < kHashProbes; ++p) {
     const uint32_t s = (h + p) & (kHashSlots - 1);
     const uint32_t k = keys[s];
     if (k == f) return (int)s;
     if (k == kEmpty) {
       const uint32_t prev = atomicCAS(&keys[s], kEmpty, f);
+      if (prev == kEmpty) atomicAdd(fill, 1u);
       if (prev == kEmpty || prev == f) return (int)s;
     }
   }
@@ -899,13 +922,18 @@ template <bool SH>
 __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_items) {
   using L = GradLayout<SH>;
   __shared__ uint32_t hkeys[kWavesPerWG][kHashSlots];
-  __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];
+  __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];  // [slot][value]: one face's values side by side
+  __shared__ uint32_t hfill[kWavesPerWG];
+  __shared__ uint32_t howner[kWavesPerWG][kHashSlots];
   const int lane = lane_id();
   const int wid = threadIdx.x / MSP_WAVE;
   uint32_t* keys = hkeys[wid];
   float* vals = hvals[wid];
+  uint32_t* fill = &hfill[wid];
+  uint32_t* owner = howner[wid];
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
+  if (lane == 0) *fill = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   if (*a.ovf & (a.store_rows ? 7u : 3u)) return;
@@ -928,6 +956,11 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
     const bool valid = px < a.W && py < a.H;
     const msp_camera c = a.cams[it.view];
+    // world-to-camera rotation in registers: the flushes' global atomics could
+    // otherwise alias it and force a reload (and a wait) after every atomic
+    float Wc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Wc[q] = c.world_to_cam[q];
     const int64_t plane = (int64_t)a.H * a.W;
     int nf = 0;
     float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
@@ -942,12 +975,17 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     }
     const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
     const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
-    const float d0 = ((float)px + 0.5f - c.cx) / c.fx, d1 = ((float)py + 0.5f - c.cy) / c.fy;
+    const float ifx = 1.f / c.fx, ify = 1.f / c.fy;
+    const float d0 = ((float)px + 0.5f - c.cx) * ifx, d1 = ((float)py + 0.5f - c.cy) * ify;
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, P = 1.f;
     int maxn = nf;
     for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d));
-    for (int k = maxn - 1; k >= 0; --k) {
-      bool act = k < nf;
+    // Each lane walks its own list back to front from its own last fragment, so
+    // the pixels a large face covers reach it at different steps (their list
+    // lengths differ) instead of all at once: fewer same-address LDS atomics.
+    for (int t = 0; t < maxn; ++t) {
+      bool act = t < nf;
+      const int k = nf - 1 - t;
       float val[L::NV];
       uint32_t f = kEmpty;
       if (act) {
@@ -996,8 +1034,8 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
           float X[3][3];
 #pragma unroll
           for (int qq = 0; qq < 3; ++qq) {
-            X[qq][0] = (u[qq] - c.cx) / c.fx * zz[qq];
-            X[qq][1] = (v[qq] - c.cy) / c.fy * zz[qq];
+            X[qq][0] = (u[qq] - c.cx) * ifx * zz[qq];
+            X[qq][1] = (v[qq] - c.cy) * ify * zz[qq];
             X[qq][2] = zz[qq];
           }
           const float e1[3] = {X[1][0] - X[0][0], X[1][1] - X[0][1], X[1][2] - X[0][2]};
@@ -1025,23 +1063,46 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
           }
         }
       }
-      // accumulate into the wave's table; flush it when a face finds no slot
-      bool need = act;
-      while (__any(need)) {
-        if (need) {
-          const int s = hash_slot(keys, f);
-          if (s >= 0) {
+      // Accumulate into the wave's table. LDS float atomics cost per lane, so
+      // lanes of neighbouring pixels that hold the same face first merge their
+      // values through DPP moves (x neighbours, then x+2, then y neighbours).
+      if (*fill > (uint32_t)kHashFill) flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
+      if (!act) {
 #pragma unroll
-            for (int qq = 0; qq < L::NV; ++qq) atomicAdd(&vals[qq * kHashSlots + s], val[qq]);
-            need = false;
-          }
+        for (int qq = 0; qq < L::NV; ++qq) val[qq] = 0.f;
+      }
+      merge_step<0xB1, 1, L::NV>(f, act, val, lane);   // quad_perm [1,0,3,2]: lane ^ 1
+      merge_step<0x4E, 2, L::NV>(f, act, val, lane);   // quad_perm [2,3,0,1]: lane ^ 2
+      merge_step<0x128, 8, L::NV>(f, act, val, lane);  // row_ror:8: lane ^ 8 within 16 lanes
+      // a slot for every remaining lane (a full table is flushed and all retry)
+      int slot = -1;
+      for (;;) {
+        slot = act ? hash_slot(keys, fill, f) : 0;
+        if (!__any(act && slot < 0)) break;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // Plain read-add-write instead of LDS float atomics (which run one lane
+      // at a time): in each round one lane per slot (the last writer of the
+      // slot's owner word) updates it; the others wait for the next round.
+      bool pend = act;
+      while (__any(pend)) {
+        if (pend) __hip_atomic_store(&owner[slot], (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        if (pend && __hip_atomic_load(&owner[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint32_t)lane) {
+#pragma unroll
+          for (int qq = 0; qq < L::NV; ++qq) vals[slot * L::NV + qq] += val[qq];
+          pend = false;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        if (__any(need)) flush_table<SH>(a, it.view, keys, vals, lane);
       }
     }
-    flush_table<SH>(a, it.view, keys, vals, lane);
+    flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
   }
 }
 
