@@ -15,8 +15,9 @@
 //   emit       per face: its key (bits(zmin) << 32 | face id) into every
 //              tile it touches; each workgroup reserves one range per tile
 //              and hands out its slots from LDS.
-//   tile_sort  each tile list sorted ascending in LDS (bitonic; lists longer
-//              than the LDS tile are chunk-sorted then merged in place).
+//   tile_sort  each tile list sorted ascending: per-thread register sorts
+//              merged in LDS by merge path; lists longer than one chunk are
+//              chunk-sorted, then merged pairwise through global memory.
 //   composite  persistent: each wavefront pulls (view, 8x8 pixel block) work
 //              items; the block's tile list is staged 64 entries at a time in
 //              a per-wave LDS slab (ballot-compacted to the faces whose
@@ -278,95 +279,184 @@ __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
 // ---------------------------------------------------------------------------
 // tile_sort: per-tile ascending sort of 64-bit keys
 // ---------------------------------------------------------------------------
-__device__ void bitonic_lds(uint64_t* s, int P) {
-  for (int k = 2; k <= P; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = s[i], y = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            s[i] = y;
-            s[ixj] = x;
-          }
+// A chunk of up to kSortChunk keys is sorted by one workgroup: each thread
+// sorts kSortItems keys in registers (bitonic network, no barriers), then runs
+// of kSortItems, 2 kSortItems, ... are merged in LDS, every thread producing
+// kSortItems outputs of its merge from a merge-path split. Lists longer than a
+// chunk are chunk-sorted, then merged pairwise through global memory, one
+// chunk of output at a time (split found by a cooperative search, both input
+// ranges staged in LDS).
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 32;
+constexpr int kSortChunk = kSortThreads * kSortItems;  // 8192 keys, 64 KiB (+ padding) of LDS
+constexpr uint64_t kSentinel = ~0ull;                 // above every key (float bits of a finite z)
+
+__device__ __forceinline__ int spad(int j) { return j + (j >> 5); }  // one pad word per 32 keys: no bank conflicts
+
+__device__ __forceinline__ void sort_regs(uint64_t (&x)[kSortItems]) {
+#pragma unroll
+  for (int k = 2; k <= kSortItems; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t u = x[i], v = x[l];
+          const bool sw = ((i & k) == 0) ? (u > v) : (u < v);
+          x[i] = sw ? v : u;
+          x[l] = sw ? u : v;
         }
       }
-      __syncthreads();
-    }
 }
 
-__device__ inline int next_pow2(int n) {
-  int p = 2;
-  while (p < n) p <<= 1;
-  return p;
-}
-
-template <int CAP>
-__device__ void sort_chunk(uint64_t* keys, int n, uint64_t* s) {
-  const int P = next_pow2(n);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < n ? keys[i] : ~0ull;
-  __syncthreads();
-  bitonic_lds(s, P);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = s[i];
-  __syncthreads();
-}
-
-__device__ void merge_runs(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out) {
-  const int64_t total = na + nb;
-  const int64_t per = (total + blockDim.x - 1) / blockDim.x;
-  int64_t d0 = (int64_t)threadIdx.x * per;
-  if (d0 > total) d0 = total;
-  int64_t d1 = d0 + per;
-  if (d1 > total) d1 = total;
-  if (d0 >= d1) return;
-  int64_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
+// kSortItems outputs starting at merge-path diagonal `diag` of runs
+// A = s[spad(oa + i)], i < na and B = s[spad(ob + j)], j < nb (A first on ties).
+__device__ __forceinline__ void merge_lds(const uint64_t* s, int oa, int na, int ob, int nb, int diag,
+                                          uint64_t (&x)[kSortItems]) {
+  int lo = diag > nb ? diag - nb : 0, hi = diag < na ? diag : na;
   while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (A[mid] <= B[d0 - 1 - mid]) lo = mid + 1;
+    const int mid = (lo + hi) >> 1;
+    if (s[spad(oa + mid)] <= s[spad(ob + diag - 1 - mid)]) lo = mid + 1;
     else hi = mid;
   }
-  int64_t i = lo, j = d0 - lo;
-  for (int64_t d = d0; d < d1; ++d) {
-    if (j >= nb || (i < na && A[i] <= B[j])) out[d] = A[i++];
-    else out[d] = B[j++];
+  int i = lo, j = diag - lo;
+  uint64_t av = i < na ? s[spad(oa + i)] : kSentinel;
+  uint64_t bv = j < nb ? s[spad(ob + j)] : kSentinel;
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const bool ta = av <= bv;
+    x[k] = ta ? av : bv;
+    if (ta) {
+      ++i;
+      av = i < na ? s[spad(oa + i)] : kSentinel;
+    } else {
+      ++j;
+      bv = j < nb ? s[spad(ob + j)] : kSentinel;
+    }
   }
 }
 
-template <int CAP, bool BIG>
-__global__ __launch_bounds__(256) void k_tile_sort(RasterArgs a, int64_t n_seg) {
-  __shared__ uint64_t s[CAP];
+// sorts p[0, m) in place, m <= kSortChunk (all threads of the workgroup call it)
+__device__ void sort_chunk(uint64_t* p, int m, uint64_t* s) {
+  const int t = threadIdx.x;
+  int P = 1;  // threads in use: a power of two with P * kSortItems >= m
+  while (P * kSortItems < m) P <<= 1;
+  const int n = P * kSortItems;
+  for (int j = t; j < n; j += kSortThreads) s[spad(j)] = j < m ? p[j] : kSentinel;
+  __syncthreads();
+  uint64_t x[kSortItems];
+  if (t < P) {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) x[i] = s[spad(t * kSortItems + i)];
+    sort_regs(x);
+  }
+  for (int L = kSortItems; L < n; L <<= 1) {
+    __syncthreads();
+    if (t < P) {
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) s[spad(t * kSortItems + i)] = x[i];
+    }
+    __syncthreads();
+    if (t < P) {
+      const int g = 2 * L / kSortItems;  // threads per merge
+      const int base = (t / g) * 2 * L;
+      merge_lds(s, base, L, base + L, L, (t % g) * kSortItems, x);
+    }
+  }
+  __syncthreads();
+  if (t < P) {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) s[spad(t * kSortItems + i)] = x[i];
+  }
+  __syncthreads();
+  for (int j = t; j < m; j += kSortThreads) p[j] = s[spad(j)];
+  __syncthreads();
+}
+
+// merge-path split of diagonal d over global runs A (na) and B (nb): the number
+// of A elements among the first d outputs. Cooperative: each round tests
+// kSortThreads candidates, so two rounds cover 65536 positions.
+__device__ int coop_split(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, int64_t d, int64_t* sh) {
+  const int t = threadIdx.x;
+  int64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (hi > lo) {  // uniform
+    const int64_t span = hi - lo;
+    const int64_t m = lo + (span * t) / kSortThreads;  // candidates in [lo, hi)
+    const bool below = A[m] <= B[d - 1 - m];             // true: the split is above m
+    __syncthreads();
+    if (t == 0) {
+      sh[0] = lo;
+      sh[1] = hi;
+    }
+    __syncthreads();
+    if (below) atomicMax((unsigned long long*)&sh[0], (unsigned long long)(m + 1));
+    else atomicMin((unsigned long long*)&sh[1], (unsigned long long)m);
+    __syncthreads();
+    lo = sh[0];
+    hi = sh[1];
+  }
+  return (int)lo;
+}
+
+// out[0, cnt) = outputs [o0, o0 + cnt) of merging global runs A and B
+__device__ void merge_chunk(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, int64_t o0, int cnt,
+                            uint64_t* out, uint64_t* s, int64_t* sh) {
+  const int t = threadIdx.x;
+  const int64_t a0 = coop_split(A, na, B, nb, o0, sh);
+  const int64_t a1 = coop_split(A, na, B, nb, o0 + cnt, sh);
+  const int la = (int)(a1 - a0), lb = cnt - la;
+  const int64_t b0 = o0 - a0;
+  for (int j = t; j < la; j += kSortThreads) s[spad(j)] = A[a0 + j];
+  for (int j = t; j < lb; j += kSortThreads) s[spad(la + j)] = B[b0 + j];
+  __syncthreads();
+  uint64_t x[kSortItems];
+  const bool busy = t * kSortItems < cnt;
+  if (busy) merge_lds(s, 0, la, la, lb, t * kSortItems, x);
+  __syncthreads();
+  if (busy) {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+      if (t * kSortItems + i < cnt) s[spad(t * kSortItems + i)] = x[i];
+  }
+  __syncthreads();
+  for (int j = t; j < cnt; j += kSortThreads) out[j] = s[spad(j)];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(RasterArgs a, int64_t n_seg) {
+  __shared__ uint64_t s[kSortChunk + kSortChunk / 32];
+  __shared__ int64_t sh[2];
   const int64_t seg = blockIdx.x;
-  if (seg >= n_seg || (*a.ovf & 3u)) return;
+  if (seg >= n_seg || (*a.ovf & 3u)) return;  // uniform
   const int64_t beg = a.tile_off[seg];
   const int64_t n = a.tile_off[seg + 1] - beg;
   if (n <= 1) return;
-  if (!BIG) {
-    if (n > CAP) return;
-    sort_chunk<CAP>(a.keys + beg, (int)n, s);
-    return;
-  }
-  if (n <= 1024) return;  // handled by the small-list kernel
   uint64_t* src = a.keys + beg;
+  for (int64_t c0 = 0; c0 < n; c0 += kSortChunk) sort_chunk(src + c0, (int)(n - c0 < kSortChunk ? n - c0 : kSortChunk), s);
+  if (n <= kSortChunk) return;
   uint64_t* dst = a.tmp + beg;
-  for (int64_t c0 = 0; c0 < n; c0 += CAP) {
-    const int64_t m = n - c0 < CAP ? n - c0 : CAP;
-    sort_chunk<CAP>(src + c0, (int)m, s);
-  }
-  for (int64_t w = CAP; w < n; w <<= 1) {
+  for (int64_t w = kSortChunk; w < n; w <<= 1) {
     for (int64_t s0 = 0; s0 < n; s0 += 2 * w) {
-      const int64_t na = (n - s0 < w) ? n - s0 : w;
+      const int64_t na = n - s0 < w ? n - s0 : w;
       const int64_t rest = n - s0 - na;
       const int64_t nb = rest < w ? rest : w;
-      merge_runs(src + s0, na, src + s0 + na, nb, dst + s0);
+      for (int64_t o0 = 0; o0 < na + nb; o0 += kSortChunk) {
+        const int cnt = (int)(na + nb - o0 < kSortChunk ? na + nb - o0 : kSortChunk);
+        if (nb == 0) {
+          for (int j = threadIdx.x; j < cnt; j += kSortThreads) dst[s0 + o0 + j] = src[s0 + o0 + j];
+        } else {
+          merge_chunk(src + s0, na, src + s0 + na, nb, o0, cnt, dst + s0 + o0, s, sh);
+        }
+      }
     }
     __syncthreads();
-    uint64_t* t = src;
+    uint64_t* tswap = src;
     src = dst;
-    dst = t;
+    dst = tswap;
   }
   if (src != a.keys + beg) {
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a.keys[beg + i] = src[i];
+    for (int64_t i = threadIdx.x; i < n; i += kSortThreads) a.keys[beg + i] = src[i];
   }
 }
 
@@ -1153,10 +1243,8 @@ hipError_t launch_emit(hipStream_t s, const RasterArgs& a) {
 
 hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a) {
   const int64_t n_seg = a.n_tiles * a.n_views;
-  hipLaunchKernelGGL((k_tile_sort<1024, false>), dim3((unsigned)n_seg), dim3(256), 0, s, a, n_seg);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_tile_sort<8192, true>), dim3((unsigned)n_seg), dim3(256), 0, s, a, n_seg);
+  if (n_seg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_seg), dim3(kSortThreads), 0, s, a, n_seg);
   return hipGetLastError();
 }
 

@@ -105,6 +105,22 @@ def test_tile_lists_bit_exact_config2(gpu):
     assert np.array_equal(keys, rkeys)
 
 
+@pytest.mark.parametrize("n,seed", [(2000, 41), (6000, 42)])
+def test_tile_lists_bit_exact_long_lists(gpu, n, seed):
+    """Large Gaussians over a small image: tile lists of ~9k and ~27k entries,
+    longer than one sorting chunk, so they go through the pairwise merges."""
+    g = scenes.gaussians(n, seed, 0.3, 0.6, flat=True)
+    f = _oracle_faces(g, 8, 2.0)
+    cams = scenes.ring_cameras(1, 64, 48)
+    _say("tiles long lists", n)
+    _, st = gpu.render(to_gpu(f), cams, gpu.RenderOptions(tile_w=32, tile_h=32))
+    off, keys = st.tiles(0)
+    roff, rkeys = ob.tile_lists(f["pos"], f["idx"], cams[0], 32, 32)
+    assert np.diff(roff).max() > 8192
+    assert np.array_equal(off, roff)
+    assert np.array_equal(keys, rkeys)
+
+
 # ---------------------------------------------------------------------------
 # images
 # ---------------------------------------------------------------------------
