@@ -920,13 +920,101 @@ struct GradLayout {
   static constexpr int NV = SH ? 15 : 21;
   static constexpr int COL = 3;
   static constexpr int POS = SH ? 6 : 12;
+  // per-vertex entry: dop | (RGB: drgb[3]) | dpos world[3]
+  static constexpr int VW = SH ? 4 : 7;
+  static constexpr int VSLOTS = SH ? 512 : 256;
+  static constexpr int VBITS = SH ? 9 : 8;
+  static constexpr int VFILL = VSLOTS * 3 / 4;
+};
+
+// Per-wave vertex table: the face table's flushes pour their three vertices'
+// opacity/colour/position gradients in here, so a vertex that several faces of
+// a region share (the centre of a fan above all) costs one set of global
+// atomics per region instead of one per face and flush.
+template <bool SH>
+struct VertTable {
+  uint32_t* keys;
+  float* vals;
+  uint32_t* fill;
 };
 
 template <bool SH>
-__device__ void flush_table(const RasterArgs& a, int view, const float (&Wc)[12], uint32_t* keys, float* vals,
-                            uint32_t* fill, int lane) {
+__device__ __forceinline__ int vert_slot(const VertTable<SH>& t, uint32_t v) {
   using L = GradLayout<SH>;
-  const int64_t F = a.n_faces, V = a.n_verts;
+  const uint32_t h = (v * 0x9E3779B1u) >> (32 - L::VBITS);
+  for (int p = 0; p < kHashProbes; ++p) {
+    const uint32_t sl = (h + p) & (L::VSLOTS - 1);
+    const uint32_t k = t.keys[sl];
+    if (k == v) return (int)sl;
+    if (k == kEmpty) {
+      const uint32_t prev = atomicCAS(&t.keys[sl], kEmpty, v);
+      if (prev == kEmpty) atomicAdd(t.fill, 1u);
+      if (prev == kEmpty || prev == v) return (int)sl;
+    }
+  }
+  return -1;
+}
+
+// one vertex's contribution c[VW]: into the table, or straight to global memory if no slot
+template <bool SH>
+__device__ __forceinline__ void vert_add(const RasterArgs& a, const VertTable<SH>& t, int32_t v, const float* c) {
+  using L = GradLayout<SH>;
+  const int sl = vert_slot(t, (uint32_t)v);
+  if (sl >= 0) {
+#pragma unroll
+    for (int q = 0; q < L::VW; ++q) atomicAdd(&t.vals[sl * L::VW + q], c[q]);
+    return;
+  }
+  const int64_t V = a.n_verts;
+  if (a.dop) atomicAdd(&a.dop[v], c[0]);
+  if (!SH && a.drgb) {
+    atomicAdd(&a.drgb[v], c[1]);
+    atomicAdd(&a.drgb[V + v], c[2]);
+    atomicAdd(&a.drgb[2 * V + v], c[3]);
+  }
+  if (a.dpos) {
+    atomicAdd(&a.dpos[v], c[L::VW - 3]);
+    atomicAdd(&a.dpos[V + v], c[L::VW - 2]);
+    atomicAdd(&a.dpos[2 * V + v], c[L::VW - 1]);
+  }
+}
+
+template <bool SH>
+__device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable<SH>& t, int lane) {
+  using L = GradLayout<SH>;
+  const int64_t V = a.n_verts;
+  for (int sl = lane; sl < L::VSLOTS; sl += MSP_WAVE) {
+    const uint32_t v = t.keys[sl];
+    if (v == kEmpty) continue;
+    float c[L::VW];
+#pragma unroll
+    for (int q = 0; q < L::VW; ++q) {
+      c[q] = t.vals[sl * L::VW + q];
+      t.vals[sl * L::VW + q] = 0.f;
+    }
+    t.keys[sl] = kEmpty;
+    if (a.dop) atomicAdd(&a.dop[v], c[0]);
+    if (!SH && a.drgb) {
+      atomicAdd(&a.drgb[v], c[1]);
+      atomicAdd(&a.drgb[V + v], c[2]);
+      atomicAdd(&a.drgb[2 * V + v], c[3]);
+    }
+    if (a.dpos) {
+      atomicAdd(&a.dpos[v], c[L::VW - 3]);
+      atomicAdd(&a.dpos[V + v], c[L::VW - 2]);
+      atomicAdd(&a.dpos[2 * V + v], c[L::VW - 1]);
+    }
+  }
+  if (lane == 0) *t.fill = 0;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+template <bool SH>
+__device__ __forceinline__ void flush_table(const RasterArgs& a, int view, const float (&Wc)[12], uint32_t* keys, float* vals,
+                            uint32_t* fill, const VertTable<SH>& vt, int lane) {
+  using L = GradLayout<SH>;
+  const int64_t F = a.n_faces;
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) {
     const uint32_t f = keys[s];
     if (f == kEmpty) continue;
@@ -939,39 +1027,33 @@ __device__ void flush_table(const RasterArgs& a, int view, const float (&Wc)[12]
       vals[s * L::NV + q] = 0.f;
     }
     keys[s] = kEmpty;
-    if (a.dop) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) atomicAdd(&a.dop[id[k]], v[k]);
+    if (SH && a.dcol) {
+      const int64_t cb = (int64_t)view * 3 * F;
+      atomicAdd(&a.dcol[cb + f], v[3]);
+      atomicAdd(&a.dcol[cb + F + f], v[4]);
+      atomicAdd(&a.dcol[cb + 2 * F + f], v[5]);
     }
-    if (SH) {
-      if (a.dcol) {
-        const int64_t cb = (int64_t)view * 3 * F;
-        atomicAdd(&a.dcol[cb + f], v[3]);
-        atomicAdd(&a.dcol[cb + F + f], v[4]);
-        atomicAdd(&a.dcol[cb + 2 * F + f], v[5]);
-      }
-    } else if (a.drgb) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        atomicAdd(&a.drgb[id[k]], v[L::COL + 3 * k]);
-        atomicAdd(&a.drgb[V + id[k]], v[L::COL + 3 * k + 1]);
-        atomicAdd(&a.drgb[2 * V + id[k]], v[L::COL + 3 * k + 2]);
+    for (int k = 0; k < 3; ++k) {
+      float c[L::VW];
+      c[0] = v[k];
+      if (!SH) {
+        c[1] = v[L::COL + 3 * k];
+        c[2] = v[L::COL + 3 * k + 1];
+        c[3] = v[L::COL + 3 * k + 2];
       }
-    }
-    if (a.dpos) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float w0 = v[L::POS + 3 * k], w1 = v[L::POS + 3 * k + 1], w2 = v[L::POS + 3 * k + 2];
-        // camera -> world: R^T g
-        atomicAdd(&a.dpos[id[k]], Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2);
-        atomicAdd(&a.dpos[V + id[k]], Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2);
-        atomicAdd(&a.dpos[2 * V + id[k]], Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2);
-      }
+      // camera -> world: R^T g
+      const float w0 = v[L::POS + 3 * k], w1 = v[L::POS + 3 * k + 1], w2 = v[L::POS + 3 * k + 2];
+      c[L::VW - 3] = Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2;
+      c[L::VW - 2] = Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2;
+      c[L::VW - 1] = Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2;
+      vert_add<SH>(a, vt, id[k], c);
     }
   }
   if (lane == 0) *fill = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  if (*vt.fill > (uint32_t)L::VFILL) flush_verts<SH>(a, vt, lane);
 }
 
 // One step of a segmented merge across lanes: lane l and its DPP partner
@@ -1015,25 +1097,53 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];  // [slot][value]: one face's values side by side
   __shared__ uint32_t hfill[kWavesPerWG];
   __shared__ uint32_t howner[kWavesPerWG][kHashSlots];
+  __shared__ uint32_t vkeys[kWavesPerWG][L::VSLOTS];
+  __shared__ float vvals[kWavesPerWG][L::VW * L::VSLOTS];
+  __shared__ uint32_t vfill[kWavesPerWG];
   const int lane = lane_id();
   const int wid = threadIdx.x / MSP_WAVE;
   uint32_t* keys = hkeys[wid];
   float* vals = hvals[wid];
   uint32_t* fill = &hfill[wid];
   uint32_t* owner = howner[wid];
+  const VertTable<SH> vt{vkeys[wid], vvals[wid], &vfill[wid]};
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
-  if (lane == 0) *fill = 0;
+  for (int s = lane; s < L::VSLOTS; s += MSP_WAVE) vt.keys[s] = kEmpty;
+  for (int s = lane; s < L::VW * L::VSLOTS; s += MSP_WAVE) vt.vals[s] = 0.f;
+  if (lane == 0) {
+    *fill = 0;
+    *vt.fill = 0;
+  }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   if (*a.ovf & (a.store_rows ? 7u : 3u)) return;
+  const int nbx = (a.W + 7) / 8, nby = (a.H + 7) / 8;
+  const int nrx = (nbx + 1) / 2, nry = (nby + 1) / 2;
   for (;;) {
+    // work item: a 2x2 group of 8x8 blocks of one view; the tables persist over the group
     uint32_t item = 0;
     if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[4], 1ull);
     item = __shfl(item, 0);
     if (item >= n_items) break;
+    const int view = (int)(item / ((uint32_t)nrx * nry));
+    const int rr = (int)(item - (uint32_t)view * nrx * nry);
+    const int rx = rr % nrx, ry = rr / nrx;
+    const msp_camera c = a.cams[view];
+    // world-to-camera rotation in registers: the flushes' global atomics could
+    // otherwise alias it and force a reload (and a wait) after every atomic
+    float Wc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Wc[q] = c.world_to_cam[q];
+    for (int sub = 0; sub < 4; ++sub) {
+    const int bx = 2 * rx + (sub & 1), by = 2 * ry + (sub >> 1);
+    if (bx >= nbx || by >= nby) continue;
     Item it;
-    if (!decode_item(a, item, it)) continue;
+    it.view = view;
+    it.bx0 = bx * 8;
+    it.by0 = by * 8;
+    it.seg = 0;
+    it.blk = ((int64_t)view * nby + by) * nbx + bx;
     int64_t row0, rows;
     if (a.store_rows) {
       row0 = it.blk * a.store_rows;
@@ -1045,12 +1155,6 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     const uint2* list = a.frag_list + row0 * MSP_WAVE;
     const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
     const bool valid = px < a.W && py < a.H;
-    const msp_camera c = a.cams[it.view];
-    // world-to-camera rotation in registers: the flushes' global atomics could
-    // otherwise alias it and force a reload (and a wait) after every atomic
-    float Wc[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) Wc[q] = c.world_to_cam[q];
     const int64_t plane = (int64_t)a.H * a.W;
     int nf = 0;
     float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
@@ -1156,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       // Accumulate into the wave's table. LDS float atomics cost per lane, so
       // lanes of neighbouring pixels that hold the same face first merge their
       // values through DPP moves (x neighbours, then x+2, then y neighbours).
-      if (*fill > (uint32_t)kHashFill) flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
+      if (*fill > (uint32_t)kHashFill) flush_table<SH>(a, it.view, Wc, keys, vals, fill, vt, lane);
       if (!act) {
 #pragma unroll
         for (int qq = 0; qq < L::NV; ++qq) val[qq] = 0.f;
@@ -1171,7 +1275,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
         if (!__any(act && slot < 0)) break;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
+        flush_table<SH>(a, it.view, Wc, keys, vals, fill, vt, lane);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1192,7 +1296,9 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       }
     }
-    flush_table<SH>(a, it.view, Wc, keys, vals, fill, lane);
+    }  // sub-block
+    flush_table<SH>(a, view, Wc, keys, vals, fill, vt, lane);
+    flush_verts<SH>(a, vt, lane);
   }
 }
 
@@ -1286,7 +1392,8 @@ hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_
 }
 
 hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu) {
-  const uint32_t n_items = n_items_of(a);
+  const uint32_t nbx = (uint32_t)((a.W + 7) / 8), nby = (uint32_t)((a.H + 7) / 8);
+  const uint32_t n_items = ((nbx + 1) / 2) * ((nby + 1) / 2) * (uint32_t)a.n_views;
   if (a.col4) {
     const int g = persistent_grid(k_bwd_grads<true>, n_cu, n_items);
     hipLaunchKernelGGL(k_bwd_grads<true>, dim3(g), dim3(256), 0, s, a, n_items);
