@@ -282,10 +282,30 @@ msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float 
  * minus rgb. y: [n][3K+4]. */
 msp_status msp_refiner_targets(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
                                const msp_faces* tuned, float* y);
-/* Mean squared error between y and target ([n][n_out] each); loss_out DEVICE
+/* Adjoint of msp_refiner_apply: given the gradients of a loss with respect to
+ * the refined fan's vertex positions, opacities and colours (grads->dpos,
+ * dopacity, drgb over the fan layout; NULL = zero; dsh unused), writes dL/dy
+ * [n][3K+4]: boundary offset k gets a A^.dpos, b B^.dpos, sqrt(ab) n^.dpos of
+ * its vertex; the opacity delta gets dop(centre) + opac_mul sum dop(boundary)
+ * where 0 < opacity + delta < 1 (0 where the clamp holds); the colour delta the
+ * colour gradients summed over the fan's K + 1 vertices. This lets the refiner
+ * be trained through msp_render_backward on the fine-tuning loss itself. */
+msp_status msp_refiner_apply_backward(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                      const float* y, const msp_face_grads* grads, float* dy);
+/* Loss weights w [n][3K+4] for the refiner outputs of Gaussians g, so that
+ * the weighted squared error of y measures the refined fan itself: offset
+ * coordinate k along A, B and the normal gets (a^2, b^2, a b) / ref_len^2 with
+ * a = sigma s_a, b = sigma s_b the fan's semi-axes (the squared world-space
+ * displacement of that boundary vertex per unit squared error); the opacity
+ * and colour deltas get a b / ref_len^2 (the fan's area relative to the same
+ * K-gon of radius ref_len). EINVAL: K outside [3, 64], sigma or ref_len not
+ * finite and > 0, NULL arrays with n > 0. */
+msp_status msp_refiner_weights(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float ref_len, float* w);
+/* (Weighted) mean squared error between y and target ([n][n_out] each):
+ * sum w (y - t)^2 / (n n_out) with w = 1 where weight is NULL; loss_out DEVICE
  * float, dy (or NULL) = d loss / d y. */
-msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, int64_t n, float* loss_out,
-                            float* dy);
+msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, const float* weight,
+                            int64_t n, float* loss_out, float* dy);
 
 /* ---- captured steps and tuning ------------------------------------------ */
 

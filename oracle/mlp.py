@@ -151,3 +151,60 @@ def fit_targets(mean, scale, quat, opacity, rgb, K, sigma, tuned, opac_mul=0.2):
     ct = np.asarray(tuned["rgb"], np.float64).T.reshape(n, K + 1, 3)
     y[:, 3 * K + 1: 3 * K + 4] = ct.mean(1) - np.asarray(rgb, np.float64).T
     return y
+
+
+def loss_weights(scale, K, sigma, ref_len=0.1):
+    """Per-output weights [N][3K+4] for training the refiner: offset coordinate
+    k along A^, B^, n^ weighs (a^2, b^2, a b) / ref^2 (its squared world-space
+    length per unit), the opacity and colour deltas a b / ref^2 (fan area over
+    the area of the same K-gon of radius ref)."""
+    s = np.asarray(scale, np.float64).T
+    n = s.shape[0]
+    a_i, b_i = oc.top2_axes(s)
+    gi = np.arange(n)
+    a = sigma * s[gi, a_i]
+    b = sigma * s[gi, b_i]
+    w = np.empty((n, 3 * K + 4))
+    w[:, 0:3 * K:3] = (a * a / ref_len ** 2)[:, None]
+    w[:, 1:3 * K:3] = (b * b / ref_len ** 2)[:, None]
+    w[:, 2:3 * K:3] = (a * b / ref_len ** 2)[:, None]
+    w[:, 3 * K:] = (a * b / ref_len ** 2)[:, None]
+    return w
+
+
+def weighted_mse(y, t, w=None):
+    """sum w (y - t)^2 / numel and its gradient with respect to y."""
+    y = np.asarray(y, np.float64)
+    d = y - np.asarray(t, np.float64)
+    w = np.ones_like(d) if w is None else np.asarray(w, np.float64)
+    return float(np.sum(w * d * d) / d.size), 2.0 * w * d / d.size
+
+
+def refined_fan_backward(mean, scale, quat, opacity, rgb, K, sigma, y, dpos, dop, drgb, opac_mul=0.2):
+    """dL/dy for L with gradients dpos [3][V], dop [V], drgb [3][V] at refined_fan(y).
+    Boundary offset k: (a A^, b B^, sqrt(ab) n^) . dpos of vertex k; opacity:
+    dop(centre) + opac_mul * sum dop(boundary) where 0 < o + y_op < 1; colour:
+    sum of the fan's vertex colour gradients."""
+    s = np.asarray(scale, np.float64).T
+    n = s.shape[0]
+    R = oc.quat_to_rot(np.asarray(quat, np.float64).T)
+    a_i, b_i = oc.top2_axes(s)
+    gi = np.arange(n)
+    Ah, Bh = R[gi, :, a_i], R[gi, :, b_i]
+    Nh = np.cross(Ah, Bh)
+    a = sigma * s[gi, a_i]
+    b = sigma * s[gi, b_i]
+    y = np.asarray(y, np.float64)
+    gp = np.asarray(dpos, np.float64).T.reshape(n, K + 1, 3)
+    go = np.asarray(dop, np.float64).reshape(n, K + 1)
+    gc = np.asarray(drgb, np.float64).T.reshape(n, K + 1, 3)
+    dy = np.zeros((n, 3 * K + 4))
+    for k in range(K):
+        d = gp[:, 1 + k]
+        dy[:, 3 * k] = a * np.einsum("ij,ij->i", d, Ah)
+        dy[:, 3 * k + 1] = b * np.einsum("ij,ij->i", d, Bh)
+        dy[:, 3 * k + 2] = np.sqrt(a * b) * np.einsum("ij,ij->i", d, Nh)
+    u = np.asarray(opacity, np.float64) + y[:, 3 * K]
+    dy[:, 3 * K] = np.where((u > 0) & (u < 1), go[:, 0] + opac_mul * go[:, 1:].sum(1), 0.0)
+    dy[:, 3 * K + 1:] = gc.sum(1)
+    return dy

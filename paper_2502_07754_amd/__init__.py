@@ -19,7 +19,8 @@ from ._lib import MspError
 
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
-           "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_loss"]
+           "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_weights",
+           "refiner_apply_backward", "refiner_loss"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -454,15 +455,47 @@ def refiner_targets(g: dict, K: int, sigma: float, tuned: dict, opac_mul: float 
     return y
 
 
-def refiner_loss(refiner: "Refiner", y, target, want_grad=True):
+def refiner_apply_backward(g: dict, K: int, sigma: float, y, grads: dict, opac_mul: float = 0.2):
+    """dL/dy [N, 3K+4] from the gradients of the refined fan (msp_refiner_apply_backward)."""
+    import torch
+    G = _gauss_struct(g)
+    G.sh = None
+    ctx = _ctx(g["mean"])
+    ctx.bind_stream()
+    _need(y, torch.float32, "y")
+    dy = torch.empty_like(y)
+    gr = _lib.FaceGrads(_dev_ptr(grads.get("dpos")), _dev_ptr(grads.get("dopacity")), _dev_ptr(grads.get("drgb")),
+                        None)
+    ctx.check(ctx.lib.msp_refiner_apply_backward(ctx.h, C.byref(G), int(K), float(sigma), float(opac_mul),
+                                                 _dev_ptr(y), C.byref(gr), _dev_ptr(dy)), "msp_refiner_apply_backward")
+    return dy
+
+
+def refiner_weights(g: dict, K: int, sigma: float, ref_len: float = 0.1):
+    """Per-output loss weights [N, 3K+4] (msp_refiner_weights)."""
+    import torch
+    G = _gauss_struct(g)
+    ctx = _ctx(g["mean"])
+    ctx.bind_stream()
+    w = torch.empty((G.n, 3 * K + 4), dtype=torch.float32, device=g["mean"].device)
+    ctx.check(ctx.lib.msp_refiner_weights(ctx.h, C.byref(G), int(K), float(sigma), float(ref_len), _dev_ptr(w)),
+              "msp_refiner_weights")
+    return w
+
+
+def refiner_loss(refiner: "Refiner", y, target, weight=None, want_grad=True):
+    """(Weighted) mean squared error and its gradient (msp_refiner_loss)."""
     import torch
     _need(y, torch.float32, "y")
     _need(target, torch.float32, "target")
+    if weight is not None:
+        _need(weight, torch.float32, "weight")
     out = torch.empty((1,), dtype=torch.float32, device=y.device)
     dy = torch.empty_like(y) if want_grad else None
     refiner.ctx.bind_stream()
     refiner.ctx.check(refiner.ctx.lib.msp_refiner_loss(refiner.ctx.h, refiner.h, _dev_ptr(y), _dev_ptr(target),
-                                                       y.shape[0], _dev_ptr(out), _dev_ptr(dy)), "msp_refiner_loss")
+                                                       _dev_ptr(weight), y.shape[0], _dev_ptr(out), _dev_ptr(dy)),
+                      "msp_refiner_loss")
     return out, dy
 
 

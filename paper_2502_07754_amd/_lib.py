@@ -94,8 +94,12 @@ EXPORTS = {
                                     C.POINTER(Faces)]),
     "msp_refiner_targets": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float,
                                       C.POINTER(Faces), C.c_void_p]),
-    "msp_refiner_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
-                                   C.c_void_p]),
+    "msp_refiner_apply_backward": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float,
+                                             C.c_void_p, C.POINTER(FaceGrads), C.c_void_p]),
+    "msp_refiner_weights": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float,
+                                      C.c_void_p]),
+    "msp_refiner_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.c_void_p, C.c_void_p]),
     "msp_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "msp_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }

@@ -464,13 +464,35 @@ msp_status msp_refiner_targets(msp_ctx* ctx, const msp_gaussians* g, int K, floa
   return MSP_OK;
 }
 
-msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, int64_t n, float* loss_out,
-                            float* dy) {
+msp_status msp_refiner_apply_backward(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                      const float* y, const msp_face_grads* grads, float* dy) {
+  if (!ctx) return MSP_EINVAL;
+  if (!g || !grads || g->n < 0 || K < 3 || K > 64 || !(sigma > 0.f) || !std::isfinite(sigma) ||
+      !std::isfinite(opac_mul) || (g->n > 0 && (!g->scale || !g->quat || !g->opacity || !y || !dy)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_apply_backward: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_apply_backward(ctx->stream, g, K, sigma, opac_mul, y, grads, dy));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_weights(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float ref_len, float* w) {
+  if (!ctx) return MSP_EINVAL;
+  if (!g || g->n < 0 || K < 3 || K > 64 || !(sigma > 0.f) || !std::isfinite(sigma) || !(ref_len > 0.f) ||
+      !std::isfinite(ref_len) || (g->n > 0 && (!g->scale || !w)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_weights: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_refiner_weights(ctx->stream, g, K, sigma, ref_len, w));
+  return MSP_OK;
+}
+
+msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const float* target, const float* weight,
+                            int64_t n, float* loss_out, float* dy) {
   if (!ctx) return MSP_EINVAL;
   if (!r || !loss_out || n < 0 || (n > 0 && (!y || !target)))
     return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_loss: bad argument");
   DeviceGuard dg(ctx->device);
-  MSP_TIMED(ctx, ST_OTHER, launch_vec_mse(ctx->stream, y, target, n * refiner_n_out(r), loss_out, dy, refiner_part(r)));
+  MSP_TIMED(ctx, ST_OTHER,
+            launch_vec_mse(ctx->stream, y, target, weight, n * refiner_n_out(r), loss_out, dy, refiner_part(r)));
   return MSP_OK;
 }
 

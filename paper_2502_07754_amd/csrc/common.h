@@ -152,8 +152,11 @@ int refiner_n_out(const msp_refiner* r);
 double* refiner_part(msp_refiner* r);
 hipError_t launch_refiner_targets(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
                                   const msp_faces* tuned, float* y);
-hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, int64_t n, float* loss, float* dy,
-                          double* part);
+hipError_t launch_refiner_apply_backward(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                         const float* y, const msp_face_grads* gr, float* dy);
+hipError_t launch_refiner_weights(hipStream_t s, const msp_gaussians* g, int K, float sigma, float ref_len, float* w);
+hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, const float* w, int64_t n, float* loss,
+                          float* dy, double* part);
 int refiner_alloc(msp_ctx* ctx, msp_refiner* r);
 int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N);
 void refiner_free_bufs(msp_refiner* r);

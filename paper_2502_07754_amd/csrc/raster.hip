@@ -49,6 +49,7 @@ constexpr int kWavesPerWG = 4;
 constexpr int kHashSlots = 128;         // per-wave gradient table
 constexpr int kHashFill = 64;           // flushed once it holds more faces than this (short probe chains)
 constexpr int kHashProbes = 16;
+static_assert(kHashSlots >= 2 * MSP_WAVE, "a flushed table must hold one row's faces after a full table");
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 enum : int { DONE = 0, ACTIVE = 1, RESTART = 2 };
@@ -1075,9 +1076,9 @@ __device__ __forceinline__ void merge_step(uint32_t f, bool& alive, float (&val)
 }
 
 // slot of face f in the wave's table (inserted if absent; the fill count grows), -1 if none
-__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_t f) {
+__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_t f, int probes) {
   const uint32_t h = (f * 0x9E3779B1u) >> 25;  // 7 bits = log2(kHashSlots)
-  for (int p = 0; p < kHashProbes; ++p) {
+  for (int p = 0; p < probes; ++p) {
     const uint32_t s = (h + p) & (kHashSlots - 1);
     const uint32_t k = keys[s];
     if (k == f) return (int)s;
@@ -1268,32 +1269,35 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       merge_step<0xB1, 1, L::NV>(f, act, val, lane);   // quad_perm [1,0,3,2]: lane ^ 1
       merge_step<0x4E, 2, L::NV>(f, act, val, lane);   // quad_perm [2,3,0,1]: lane ^ 2
       merge_step<0x128, 8, L::NV>(f, act, val, lane);  // row_ror:8: lane ^ 8 within 16 lanes
-      // a slot for every remaining lane (a full table is flushed and all retry)
-      int slot = -1;
-      for (;;) {
-        slot = act ? hash_slot(keys, fill, f) : 0;
-        if (!__any(act && slot < 0)) break;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        flush_table<SH>(a, it.view, Wc, keys, vals, fill, vt, lane);
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      // Plain read-add-write instead of LDS float atomics (which run one lane
-      // at a time): in each round one lane per slot (the last writer of the
-      // slot's owner word) updates it; the others wait for the next round.
+      // Slots for the remaining lanes, then plain read-add-write instead of LDS
+      // float atomics (which run one lane at a time): in each round one lane
+      // per slot (the last writer of the slot's owner word) updates it. Lanes
+      // that found no slot retry after a flush; the emptied table then holds
+      // at most 64 keys in kHashSlots = 128 slots and a full probe finds one.
       bool pend = act;
-      while (__any(pend)) {
-        if (pend) __hip_atomic_store(&owner[slot], (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      int probes = kHashProbes;
+      for (;;) {
+        const int slot = pend ? hash_slot(keys, fill, f, probes) : -1;
+        const bool got = pend && slot >= 0;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        if (pend && __hip_atomic_load(&owner[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint32_t)lane) {
+        bool todo = got;
+        while (__any(todo)) {
+          if (todo) __hip_atomic_store(&owner[slot], (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          if (todo && __hip_atomic_load(&owner[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint32_t)lane) {
 #pragma unroll
-          for (int qq = 0; qq < L::NV; ++qq) vals[slot * L::NV + qq] += val[qq];
-          pend = false;
+            for (int qq = 0; qq < L::NV; ++qq) vals[slot * L::NV + qq] += val[qq];
+            todo = false;
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        pend = pend && !got;
+        if (!__any(pend)) break;
+        flush_table<SH>(a, view, Wc, keys, vals, fill, vt, lane);
+        probes = kHashSlots;
       }
     }
     }  // sub-block

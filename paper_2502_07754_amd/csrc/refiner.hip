@@ -372,6 +372,61 @@ __global__ void k_apply(const float* __restrict__ mean, const float* __restrict_
   vrgb[2 * V + v] = rgb[2 * n + g] + yg[3 * K + 3];
 }
 
+// adjoint of k_apply: dL/dy from the gradients of the refined fan's vertices
+__global__ void k_apply_backward(const float* __restrict__ scale, const float* __restrict__ quat,
+                                 const float* __restrict__ opacity, int64_t n, int K, float sigma, float opac_mul,
+                                 const float* __restrict__ y, int n_out, const float* __restrict__ dpos,
+                                 const float* __restrict__ dop, const float* __restrict__ drgb,
+                                 float* __restrict__ dy) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int64_t V = n * (K + 1);
+  const float s0 = scale[g], s1 = scale[n + g], s2 = scale[2 * n + g];
+  const int drop = (s2 <= s0 && s2 <= s1) ? 2 : (s1 <= s0 ? 1 : 0);
+  const int ia = drop == 0 ? 1 : 0, ib = drop == 2 ? 1 : 2;
+  const float sa = ia == 0 ? s0 : s1, sb = ib == 1 ? s1 : s2;
+  const float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
+  float a0, a1, a2, b0, b1, b2;
+  rcol(qw, qx, qy, qz, ia, a0, a1, a2);
+  rcol(qw, qx, qy, qz, ib, b0, b1, b2);
+  const float n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+  const float la = sigma * sa, lb = sigma * sb, lc = sqrtf(la * lb);
+  const float* yg = y + g * n_out;
+  float* dg = dy + g * n_out;
+  const int64_t v0 = g * (K + 1);
+  for (int k = 0; k < K; ++k) {
+    const int64_t v = v0 + 1 + k;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (dpos) {
+      gx = dpos[v];
+      gy = dpos[V + v];
+      gz = dpos[2 * V + v];
+    }
+    dg[3 * k] = la * (gx * a0 + gy * a1 + gz * a2);
+    dg[3 * k + 1] = lb * (gx * b0 + gy * b1 + gz * b2);
+    dg[3 * k + 2] = lc * (gx * n0 + gy * n1 + gz * n2);
+  }
+  const float u = opacity[g] + yg[3 * K];
+  float go = 0.f;
+  if (dop && u > 0.f && u < 1.f) {
+    float sb_ = 0.f;
+    for (int k = 1; k <= K; ++k) sb_ += dop[v0 + k];
+    go = dop[v0] + opac_mul * sb_;
+  }
+  dg[3 * K] = go;
+  float cr = 0.f, cg = 0.f, cb = 0.f;
+  if (drgb) {
+    for (int j = 0; j <= K; ++j) {
+      cr += drgb[v0 + j];
+      cg += drgb[V + v0 + j];
+      cb += drgb[2 * V + v0 + j];
+    }
+  }
+  dg[3 * K + 1] = cr;
+  dg[3 * K + 2] = cg;
+  dg[3 * K + 3] = cb;
+}
+
 // least-squares refiner targets from fine-tuned fans (same vertex layout as the plain fan)
 __global__ void k_targets(const float* __restrict__ mean, const float* __restrict__ scale,
                           const float* __restrict__ quat, const float* __restrict__ opacity,
@@ -421,15 +476,38 @@ __global__ void k_targets(const float* __restrict__ mean, const float* __restric
   yg[3 * K + 3] = cb / (K + 1) - rgb[2 * n + g];
 }
 
-// mean squared error over n x m values and its gradient; partial sums per block
-__global__ __launch_bounds__(256) void k_vec_mse(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
-                                                 float gscale, float* __restrict__ dy, double* __restrict__ part) {
+// per-output loss weights: boundary offsets by the squared world length of a
+// unit of that local coordinate (a^2, b^2, a b) / ref^2, opacity and colour
+// deltas by the fan's area over the area of the same K-gon of radius ref
+__global__ void k_weights(const float* __restrict__ scale, int64_t n, int K, float sigma, float inv_ref2,
+                          float* __restrict__ w) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const float s0 = scale[g], s1 = scale[n + g], s2 = scale[2 * n + g];
+  const int drop = (s2 <= s0 && s2 <= s1) ? 2 : (s1 <= s0 ? 1 : 0);
+  const float sa = drop == 0 ? s1 : s0, sb = drop == 2 ? s1 : s2;
+  const float la = sigma * sa, lb = sigma * sb;
+  const float wa = la * la * inv_ref2, wb = lb * lb * inv_ref2, wab = la * lb * inv_ref2;
+  float* wg = w + g * (int64_t)(3 * K + 4);
+  for (int k = 0; k < K; ++k) {
+    wg[3 * k] = wa;
+    wg[3 * k + 1] = wb;
+    wg[3 * k + 2] = wab;
+  }
+  for (int q = 0; q < 4; ++q) wg[3 * K + q] = wab;
+}
+
+// (weighted) mean squared error over n values and its gradient; partial sums per block
+__global__ __launch_bounds__(256) void k_vec_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                                 const float* __restrict__ w, int64_t n, float gscale,
+                                                 float* __restrict__ dy, double* __restrict__ part) {
   __shared__ double red[4];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float d = y[i] - t[i];
-    acc += (double)d * d;
-    if (dy) dy[i] = 2.f * d * gscale;
+    const float wi = w ? w[i] : 1.f;
+    acc += (double)wi * d * d;
+    if (dy) dy[i] = 2.f * wi * d * gscale;
   }
   for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -591,10 +669,25 @@ hipError_t launch_refiner_targets(hipStream_t s, const msp_gaussians* g, int K, 
   return hipGetLastError();
 }
 
-hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, int64_t n, float* loss, float* dy,
-                          double* part) {
+hipError_t launch_refiner_apply_backward(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                         const float* y, const msp_face_grads* gr, float* dy) {
+  if (g->n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_backward, dim3(gfor(g->n)), dim3(256), 0, s, g->scale, g->quat, g->opacity, g->n, K,
+                     sigma, opac_mul, y, 3 * K + 4, gr->dpos, gr->dopacity, gr->drgb, dy);
+  return hipGetLastError();
+}
+
+hipError_t launch_refiner_weights(hipStream_t s, const msp_gaussians* g, int K, float sigma, float ref_len, float* w) {
+  if (g->n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weights, dim3(gfor(g->n)), dim3(256), 0, s, g->scale, g->n, K, sigma,
+                     1.f / (ref_len * ref_len), w);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, const float* w, int64_t n, float* loss,
+                          float* dy, double* part) {
   const unsigned nb = n > 0 ? (unsigned)std::min<int64_t>(1024, (n + 255) / 256) : 1;
-  hipLaunchKernelGGL(k_vec_mse, dim3(nb), dim3(256), 0, s, y, t, n, 1.f / (float)(n > 0 ? n : 1), dy, part);
+  hipLaunchKernelGGL(k_vec_mse, dim3(nb), dim3(256), 0, s, y, t, w, n, 1.f / (float)(n > 0 ? n : 1), dy, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vec_mse_sum, dim3(1), dim3(64), 0, s, part, (int)nb, 1.0 / (double)(n > 0 ? n : 1), loss);

@@ -9,9 +9,14 @@ and backward kernels. Evaluation compares, on held-out scenes, the image error
 of refiner-initialised fans with plain conversion (no fine-tuning), and the
 wall-clock time fine-tuning needs from each start to reach the same error.
 
-Targets: the scene is perturbed (scenes.perturbed) and converted with the
-multi-ring conversion (a smoother stand-in for a Gaussian than the fan), then
-rendered by msp_render; the fan has to learn the systematic difference.
+Targets: the scene (for the end-to-end comparison, a seeded perturbed copy of
+it: scenes.perturbed) is converted with the multi-ring conversion (a smoother
+stand-in for a Gaussian than the fan) and rendered by msp_render. Pairs come
+from the unperturbed scene: a perturbation adds per-Gaussian changes that no
+function of the Gaussian's own parameters predicts, and the mean of those
+changes is no image-space improvement (applied to every fan it raises the
+image error), whereas against the Gaussians' own ring rendering the fine-tuned
+change is the systematic fan-versus-Gaussian difference the refiner can learn.
 
     python -m paper_2502_07754_amd.refiner_train --help
 """
@@ -22,8 +27,10 @@ import json
 import math
 import time
 
-from . import (MSP_LOSS_MSE, Refiner, RenderOptions, adam_step, convert, convert_rings, loss, refiner_apply,
-               refiner_features, refiner_loss, refiner_targets, render, scenes)
+from . import (MSP_LOSS_MSE, Refiner, RenderOptions, RenderState, adam_step, convert, convert_rings, loss,
+               refiner_apply, refiner_apply_backward, refiner_features, refiner_loss, refiner_targets,
+               refiner_weights, render, render_backward, scenes)
+from . import _lib
 from .finetune import FineTuneConfig, FineTuner
 
 HIDDEN = 256
@@ -41,20 +48,22 @@ def to_gpu(g: scenes.Gaussians):
             for k, v in dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=None).items()}
 
 
-def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3):
-    tg = scenes.perturbed(g, seed)
+def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3, perturb=True):
+    tg = scenes.perturbed(g, seed) if perturb else g
     tf = convert_rings(to_gpu(tg), ring_k, rings, 3.0)
     img, _ = render(tf, cams, RenderOptions())
     return img[:, :3].contiguous()
 
 
-def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-2, log=print):
+def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-2, log=print, ref_len=0.1,
+               perturb=False):
+    """(features, targets, loss weights) of every Gaussian of the seeded scenes."""
     import torch
-    xs, ys = [], []
+    xs, ys, ws = [], [], []
     for s in seeds:
         g = scenes.gaussians(n, s, 0.01, 0.1, flat=True)
         cams = views(res)
-        tgt = target_images(g, cams, s + 1)
+        tgt = target_images(g, cams, s + 1, perturb=perturb)
         gg = to_gpu(g)
         faces = convert(gg, K, sigma)
         ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=0))
@@ -65,8 +74,9 @@ def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-
                 l0 = float(L.item())
         xs.append(refiner_features(gg, K))
         ys.append(refiner_targets(gg, K, sigma, ft.faces))
+        ws.append(refiner_weights(gg, K, sigma, ref_len))
         log(f"pairs: scene {s}: fine-tune MSE {l0:.5f} -> {float(L.item()):.5f}")
-    return torch.cat(xs), torch.cat(ys)
+    return torch.cat(xs), torch.cat(ys), torch.cat(ws)
 
 
 def init_params(n_out, seed=0):
@@ -81,8 +91,10 @@ def init_params(n_out, seed=0):
     return {k: v.contiguous() for k, v in p.items()}
 
 
-def train(x, ys, steps=400, lr=1e-3, seed=0, log=print):
-    """Full-batch Adam on the float32 masters; forward/backward on the MFMA kernels."""
+def train(x, ys, w=None, steps=400, lr=1e-3, seed=0, log=print):
+    """Full-batch Adam on the float32 masters; forward/backward on the MFMA kernels.
+    w: per-output loss weights (refiner_weights), so that offsets count by the
+    world-space displacement they cause and colour/opacity by the fan's area."""
     import torch
     n_out = ys.shape[1]
     R = Refiner(n_out)
@@ -93,7 +105,7 @@ def train(x, ys, steps=400, lr=1e-3, seed=0, log=print):
     hist = []
     for t in range(1, steps + 1):
         y = R.forward(x)
-        L, dy = refiner_loss(R, y, ys)
+        L, dy = refiner_loss(R, y, ys, w)
         g = R.backward(x, dy)
         adam_step([dict(param=p[k], grad=g[k], m=m[k], v=v[k], lr=lr) for k in p], t)
         R.set_weights(p)
@@ -103,19 +115,65 @@ def train(x, ys, steps=400, lr=1e-3, seed=0, log=print):
     return R, p, hist
 
 
+def scene_data(seeds, n=12_500, K=8, res=256, perturb=False):
+    """Per training scene: Gaussians on the GPU, cameras, target images, refiner features."""
+    out = []
+    for s in seeds:
+        g = scenes.gaussians(n, s, 0.01, 0.1, flat=True)
+        cams = views(res)
+        tgt = target_images(g, cams, s + 1, perturb=perturb)
+        gg = to_gpu(g)
+        out.append((gg, cams, tgt, refiner_features(gg, K)))
+    return out
+
+
+def train_image(data, K=8, sigma=2.0, steps=1000, lr=1e-3, seed=0, log=print):
+    """Trains the refiner on the fine-tuning objective itself: each step renders
+    the refined fans of one training scene, takes the image MSE against its
+    targets, and brings dL/dimage back through msp_render_backward, the adjoint
+    of msp_refiner_apply and the MFMA backward to the weights (Adam on the
+    float32 masters). The data are the method's own: the plain conversion's
+    inputs and the targets its fine-tuning fits."""
+    import torch
+    n_out = 3 * K + 4
+    R = Refiner(n_out)
+    p = init_params(n_out, seed)
+    m = {k: torch.zeros_like(v) for k, v in p.items()}
+    v = {k: torch.zeros_like(t) for k, t in p.items()}
+    R.set_weights(p)
+    state = RenderState(_lib.Context.get(torch.cuda.current_device()))
+    opts = RenderOptions()
+    hist = []
+    for t in range(1, steps + 1):
+        gg, cams, tgt, x = data[(t - 1) % len(data)]
+        y = R.forward(x)
+        faces = refiner_apply(gg, K, sigma, y)
+        img, st = render(faces, cams, opts, state=state)
+        L, dimg = loss(img, tgt, MSP_LOSS_MSE)
+        gr = render_backward(st, faces, dimg, need=("dpos", "dopacity", "drgb"))
+        dy = refiner_apply_backward(gg, K, sigma, y, gr)
+        gw = R.backward(x, dy)
+        adam_step([dict(param=p[k], grad=gw[k], m=m[k], v=v[k], lr=lr) for k in p], t)
+        R.set_weights(p)
+        if t == 1 or t % 100 == 0 or t == steps:
+            hist.append((t, float(L.item())))
+            log(f"train (image): step {t} scene MSE {hist[-1][1]:.6f}")
+    return R, p, hist
+
+
 def image_mse(faces, cams, tgt) -> float:
     img, _ = render(faces, cams, RenderOptions())
     L, _ = loss(img, tgt, MSP_LOSS_MSE, want_grad=False)
     return float(L.item())
 
 
-def evaluate(R, seeds, n=12_500, K=8, sigma=2.0, res=256):
+def evaluate(R, seeds, n=12_500, K=8, sigma=2.0, res=256, perturb=False):
     """Image MSE against the targets of plain and refiner-initialised fans (no fine-tuning)."""
     out = []
     for s in seeds:
         g = scenes.gaussians(n, s, 0.01, 0.1, flat=True)
         cams = views(res)
-        tgt = target_images(g, cams, s + 1)
+        tgt = target_images(g, cams, s + 1, perturb=perturb)
         gg = to_gpu(g)
         plain = image_mse(convert(gg, K, sigma), cams, tgt)
         y = R.forward(refiner_features(gg, K))
@@ -158,8 +216,11 @@ def main():
     ap.add_argument("--n", type=int, default=12_500)
     ap.add_argument("--pair-steps", type=int, default=500)
     ap.add_argument("--res", type=int, default=256)
-    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--unweighted", action="store_true", help="plain MSE on the outputs instead of refiner_weights")
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--image-steps", type=int, default=1000, help="steps of training on the fine-tuning objective")
+    ap.add_argument("--image-lr", type=float, default=1e-3)
     ap.add_argument("--infer-n", type=int, default=1_000_000)
     ap.add_argument("--ft-n", type=int, default=0, help="Gaussians of the time-to-MSE run (0: skip)")
     ap.add_argument("--ft-views", type=int, default=16)
@@ -172,19 +233,30 @@ def main():
         print(*a, flush=True)
 
     res = {}
+    import statistics as st
     t = time.perf_counter()
-    x, ys = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res, log=log)
+    x, ys, w = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res, log=log)
     res["pairs"] = dict(samples=int(x.shape[0]), faces=int(x.shape[0]) * 8, seconds=time.perf_counter() - t)
     t = time.perf_counter()
-    R, p, hist = train(x, ys, steps=args.train_steps, lr=args.lr, log=log)
+    Rs, _, hist = train(x, ys, None if args.unweighted else w, steps=args.train_steps, lr=args.lr, log=log)
     torch.cuda.synchronize()
-    res["train"] = dict(seconds=time.perf_counter() - t, loss=hist)
-    ev = evaluate(R, range(2000, 2005), n=args.n, res=args.res)
-    import statistics as st
-    gain = [e["plain"] / e["refined"] for e in ev]
-    res["heldout"] = dict(per_seed=ev, plain_mean=st.mean(e["plain"] for e in ev),
-                          refined_mean=st.mean(e["refined"] for e in ev), ratio_mean=st.mean(gain),
-                          ratio_sd=st.pstdev(gain))
+    res["train_on_pairs"] = dict(seconds=time.perf_counter() - t, loss=hist)
+    t = time.perf_counter()
+    data = scene_data(range(1000, 1000 + args.train_seeds), n=args.n, res=args.res)
+    R, p, hist = train_image(data, steps=args.image_steps, lr=args.image_lr, log=log)
+    torch.cuda.synchronize()
+    res["train_on_objective"] = dict(seconds=time.perf_counter() - t, loss=hist)
+    del data
+    for key, pert in (("heldout", False), ("heldout_perturbed_targets", True)):
+        for name, net in (("objective", R), ("pairs", Rs)):
+            ev = evaluate(net, range(2000, 2005), n=args.n, res=args.res, perturb=pert)
+            gain = [e["plain"] / e["refined"] for e in ev]
+            k2 = f"{key}_{name}"
+            res[k2] = dict(per_seed=ev, plain_mean=st.mean(e["plain"] for e in ev),
+                           refined_mean=st.mean(e["refined"] for e in ev), ratio_mean=st.mean(gain),
+                           ratio_sd=st.pstdev(gain))
+            log(f"{k2}: plain {res[k2]['plain_mean']:.6f} refined {res[k2]['refined_mean']:.6f} "
+                f"(plain/refined {res[k2]['ratio_mean']:.3f} +- {res[k2]['ratio_sd']:.3f})")
     # inference throughput on 1M Gaussians (MFMA forward)
     g = scenes.gaussians(args.infer_n, 7, 0.01, 0.1, flat=True)
     xi = refiner_features(to_gpu(g), 8)

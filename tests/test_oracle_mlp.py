@@ -102,3 +102,76 @@ def test_features_layout():
     np.testing.assert_allclose(x[:, 3:6], np.asarray(g.scale, np.float64).T / 0.1)
     assert np.all(x[:, 6] >= 0) and np.allclose(np.linalg.norm(x[:, 6:10], axis=1), 1)
     assert np.all(x[:, 14] == 0.5)
+
+
+def test_loss_weights_measure_the_refined_fan():
+    """The offset part of the weighted error is the squared world-space
+    displacement of the refined fans' boundary vertices (through refined_fan's
+    own geometry), and the opacity/colour weight is the fan's area (summed
+    triangle areas of the conversion) over the K-gon of radius ref."""
+    from oracle import convert as oc
+    from oracle import mlp
+    from paper_2502_07754_amd import scenes
+    K, sigma, ref = 8, 2.0, 0.1
+    g = scenes.gaussians(40, 77, 0.01, 0.1, flat=True)
+    rng = np.random.default_rng(5)
+    y = rng.normal(0, 0.3, (40, 3 * K + 4))
+    t = rng.normal(0, 0.3, (40, 3 * K + 4))
+    y[:, 3 * K:] = 0.0
+    t[:, 3 * K:] = 0.0
+    w = mlp.loss_weights(g.scale, K, sigma, ref)
+    fy = mlp.refined_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, y)
+    ft = mlp.refined_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, t)
+    disp = (fy["pos"] - ft["pos"]).T.reshape(40, K + 1, 3)
+    world = np.sum(disp ** 2, axis=(1, 2)) / ref ** 2
+    weighted = np.sum(w * (y - t) ** 2, axis=1)
+    np.testing.assert_allclose(weighted, world, rtol=1e-10)
+    f = oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma)
+    P = f["pos"].T
+    i0, i1, i2 = f["idx"]
+    area = 0.5 * np.linalg.norm(np.cross(P[i1] - P[i0], P[i2] - P[i0]), axis=1).reshape(40, K).sum(1)
+    np.testing.assert_allclose(w[:, 3 * K], area / (0.5 * K * np.sin(2 * np.pi / K) * ref ** 2), rtol=1e-10)
+
+
+def test_weighted_mse_gradient_and_unit_weights():
+    from oracle import mlp
+    rng = np.random.default_rng(6)
+    y, t, w = rng.normal(size=(7, 5)), rng.normal(size=(7, 5)), rng.uniform(0.1, 2.0, (7, 5))
+    L, g = mlp.weighted_mse(y, t, w)
+    h = 1e-6
+    for i, j in [(0, 0), (3, 2), (6, 4)]:
+        yp = y.copy()
+        yp[i, j] += h
+        ym = y.copy()
+        ym[i, j] -= h
+        fd = (mlp.weighted_mse(yp, t, w)[0] - mlp.weighted_mse(ym, t, w)[0]) / (2 * h)
+        assert abs(fd - g[i, j]) < 1e-8
+    assert mlp.weighted_mse(y, t)[0] == np.mean((y - t) ** 2)
+
+
+def test_refined_fan_backward_matches_finite_differences():
+    """dL/dy of L = <dpos, pos> + <dop, op> + <drgb, rgb> at refined_fan(y),
+    against central differences of refined_fan itself."""
+    from oracle import mlp
+    from paper_2502_07754_amd import scenes
+    K, sigma = 6, 2.0
+    g = scenes.gaussians(5, 81, 0.01, 0.1, flat=True)
+    rng = np.random.default_rng(8)
+    y = rng.normal(0, 0.2, (5, 3 * K + 4))
+    y[:, 3 * K] = rng.uniform(-0.1, 0.1, 5)
+    V = 5 * (K + 1)
+    dpos, dop, drgb = rng.normal(size=(3, V)), rng.normal(size=V), rng.normal(size=(3, V))
+
+    def L(yy):
+        f = mlp.refined_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, yy)
+        return np.sum(dpos * f["pos"]) + np.sum(dop * f["opacity"]) + np.sum(drgb * f["rgb"])
+
+    dy = mlp.refined_fan_backward(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, y, dpos, dop, drgb)
+    h = 1e-6
+    for i in range(5):
+        for j in range(3 * K + 4):
+            yp, ym = y.copy(), y.copy()
+            yp[i, j] += h
+            ym[i, j] -= h
+            fd = (L(yp) - L(ym)) / (2 * h)
+            assert abs(fd - dy[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, dy[i, j])
