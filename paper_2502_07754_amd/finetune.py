@@ -13,8 +13,9 @@ from __future__ import annotations
 import dataclasses
 import math
 
-from . import (MSP_LOSS_MSE, RenderOptions, adam_step, loss as msp_loss, prune as msp_prune, render,
+from . import (MSP_LOSS_MSE, RenderOptions, RenderState, adam_step, loss as msp_loss, prune as msp_prune, render,
                render_backward)
+from . import _lib
 
 
 @dataclasses.dataclass
@@ -45,6 +46,8 @@ class FineTuner:
         self.v = dict(pos=z(self.faces["pos"]), opacity=z(self.faces["opacity"]), rgb=z(self.faces["rgb"]))
         self.t = 0
         self.history = []
+        # tile lists, fragment lists and scratch are reused from step to step
+        self.state = RenderState(_lib.Context.get(self.faces["pos"].device.index or 0))
 
     def lr(self):
         c = self.cfg.lr_color
@@ -52,7 +55,7 @@ class FineTuner:
 
     def step(self):
         """One epoch: render all views, loss, adjoint, Adam, prune on schedule. Returns the loss tensor."""
-        img, st = render(self.faces, self.cams, self.opts)
+        img, st = render(self.faces, self.cams, self.opts, state=self.state)
         L, dimg = msp_loss(img, self.targets, self.cfg.loss_kind, self.cfg.lam)
         g = render_backward(st, self.faces, dimg, need=("dpos", "dopacity", "drgb"))
         self.t += 1
@@ -73,7 +76,7 @@ class FineTuner:
         self.m["pos"], self.v["pos"], self.m["rgb"], self.v["rgb"], self.m["opacity"], self.v["opacity"] = vs
 
     def mse(self) -> float:
-        img, _ = render(self.faces, self.cams, self.opts)
+        img, _ = render(self.faces, self.cams, self.opts, state=self.state)
         L, _ = msp_loss(img, self.targets, MSP_LOSS_MSE, want_grad=False)
         return float(L.item())
 

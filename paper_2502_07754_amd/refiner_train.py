@@ -48,11 +48,19 @@ def to_gpu(g: scenes.Gaussians):
             for k, v in dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=None).items()}
 
 
-def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3, perturb=True):
+def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3, perturb=True, views_per_call=16):
+    """Target views: the multi-ring conversion of the (perturbed) scene, rendered
+    a few views per call (the ring soup of a large scene is big)."""
+    import torch
     tg = scenes.perturbed(g, seed) if perturb else g
     tf = convert_rings(to_gpu(tg), ring_k, rings, 3.0)
-    img, _ = render(tf, cams, RenderOptions())
-    return img[:, :3].contiguous()
+    out = []
+    for v0 in range(0, len(cams), views_per_call):
+        img, st = render(tf, cams[v0:v0 + views_per_call], RenderOptions())
+        out.append(img[:, :3].clone())
+        del img, st
+    del tf
+    return torch.cat(out).contiguous()
 
 
 def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-2, log=print, ref_len=0.1,
@@ -183,7 +191,7 @@ def evaluate(R, seeds, n=12_500, K=8, sigma=2.0, res=256, perturb=False):
 
 
 def time_to_mse(g: scenes.Gaussians, cams, tgt, K=8, sigma=2.0, steps=1000, R=None, target=None, lr_color=1e-2,
-                prune_every=10, opts=None):
+                prune_every=10, opts=None, log=None):
     """Wall-clock seconds of conversion (+ refiner inference) + fine-tuning until the
     training MSE reaches `target` (or `steps` steps when target is None)."""
     import torch
@@ -202,12 +210,29 @@ def time_to_mse(g: scenes.Gaussians, cams, tgt, K=8, sigma=2.0, steps=1000, R=No
         if target is not None or i == steps - 1 or i % 10 == 0:
             lv = float(L.item())          # the MSE of the render this step started from
             curve.append((i, lv))
+            if log is not None and i % 50 == 0:
+                log(f"  step {i}: MSE {lv:.6f} at {time.perf_counter() - t0:.1f} s")
             if target is not None and lv <= target:
                 reached = i
                 break
     torch.cuda.synchronize()
     return dict(seconds=time.perf_counter() - t0, steps=(reached if reached is not None else steps),
                 reached=reached is not None or target is None, final_mse=curve[-1][1], curve=curve[::max(1, len(curve) // 20)])
+
+
+def save_params(p: dict, path: str):
+    import numpy as np
+    np.savez(path, **{k: v.detach().cpu().numpy() for k, v in p.items()})
+
+
+def load_refiner(path: str, K=8):
+    import numpy as np
+    import torch
+    d = np.load(path)
+    p = {k: torch.from_numpy(d[k]).cuda().contiguous() for k in d.files}
+    R = Refiner(3 * K + 4)
+    R.set_weights(p)
+    return R, p
 
 
 def main():
@@ -221,65 +246,93 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--image-steps", type=int, default=1000, help="steps of training on the fine-tuning objective")
     ap.add_argument("--image-lr", type=float, default=1e-3)
+    ap.add_argument("--skip-pairs", action="store_true", help="train only on the objective; no pair comparison")
+    ap.add_argument("--load-weights", default="", help="refiner weights (.npz) instead of training")
+    ap.add_argument("--save-weights", default="")
     ap.add_argument("--infer-n", type=int, default=1_000_000)
     ap.add_argument("--ft-n", type=int, default=0, help="Gaussians of the time-to-MSE run (0: skip)")
     ap.add_argument("--ft-views", type=int, default=16)
     ap.add_argument("--ft-res", type=int, nargs=2, default=(1920, 1080))
     ap.add_argument("--ft-steps", type=int, default=1000)
+    ap.add_argument("--ft-mode", choices=("both", "plain", "refined"), default="both")
+    ap.add_argument("--ft-target", type=float, default=0.0, help="target MSE of a refined-only run")
     args = ap.parse_args()
+    import statistics as st
+
     import torch
 
     def log(*a):
         print(*a, flush=True)
 
     res = {}
-    import statistics as st
-    t = time.perf_counter()
-    x, ys, w = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res, log=log)
-    res["pairs"] = dict(samples=int(x.shape[0]), faces=int(x.shape[0]) * 8, seconds=time.perf_counter() - t)
-    t = time.perf_counter()
-    Rs, _, hist = train(x, ys, None if args.unweighted else w, steps=args.train_steps, lr=args.lr, log=log)
-    torch.cuda.synchronize()
-    res["train_on_pairs"] = dict(seconds=time.perf_counter() - t, loss=hist)
-    t = time.perf_counter()
-    data = scene_data(range(1000, 1000 + args.train_seeds), n=args.n, res=args.res)
-    R, p, hist = train_image(data, steps=args.image_steps, lr=args.image_lr, log=log)
-    torch.cuda.synchronize()
-    res["train_on_objective"] = dict(seconds=time.perf_counter() - t, loss=hist)
-    del data
-    for key, pert in (("heldout", False), ("heldout_perturbed_targets", True)):
-        for name, net in (("objective", R), ("pairs", Rs)):
-            ev = evaluate(net, range(2000, 2005), n=args.n, res=args.res, perturb=pert)
-            gain = [e["plain"] / e["refined"] for e in ev]
-            k2 = f"{key}_{name}"
-            res[k2] = dict(per_seed=ev, plain_mean=st.mean(e["plain"] for e in ev),
-                           refined_mean=st.mean(e["refined"] for e in ev), ratio_mean=st.mean(gain),
-                           ratio_sd=st.pstdev(gain))
-            log(f"{k2}: plain {res[k2]['plain_mean']:.6f} refined {res[k2]['refined_mean']:.6f} "
-                f"(plain/refined {res[k2]['ratio_mean']:.3f} +- {res[k2]['ratio_sd']:.3f})")
-    # inference throughput on 1M Gaussians (MFMA forward)
-    g = scenes.gaussians(args.infer_n, 7, 0.01, 0.1, flat=True)
-    xi = refiner_features(to_gpu(g), 8)
-    R.forward(xi)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    reps = 10
-    for _ in range(reps):
+    if args.load_weights:
+        R, p = load_refiner(args.load_weights)
+    else:
+        if not args.skip_pairs:
+            t = time.perf_counter()
+            x, ys, w = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res,
+                                  log=log)
+            res["pairs"] = dict(samples=int(x.shape[0]), faces=int(x.shape[0]) * 8, seconds=time.perf_counter() - t)
+            t = time.perf_counter()
+            Rs, _, hist = train(x, ys, None if args.unweighted else w, steps=args.train_steps, lr=args.lr, log=log)
+            torch.cuda.synchronize()
+            res["train_on_pairs"] = dict(seconds=time.perf_counter() - t, loss=hist)
+            del x, ys, w
+        t = time.perf_counter()
+        data = scene_data(range(1000, 1000 + args.train_seeds), n=args.n, res=args.res)
+        R, p, hist = train_image(data, steps=args.image_steps, lr=args.image_lr, log=log)
+        torch.cuda.synchronize()
+        res["train_on_objective"] = dict(seconds=time.perf_counter() - t, loss=hist)
+        del data
+        nets = [("objective", R)] + ([] if args.skip_pairs else [("pairs", Rs)])
+        for key, pert in (("heldout", False), ("heldout_perturbed_targets", True)):
+            for name, net in nets:
+                ev = evaluate(net, range(2000, 2005), n=args.n, res=args.res, perturb=pert)
+                gain = [e["plain"] / e["refined"] for e in ev]
+                k2 = f"{key}_{name}"
+                res[k2] = dict(per_seed=ev, plain_mean=st.mean(e["plain"] for e in ev),
+                               refined_mean=st.mean(e["refined"] for e in ev), ratio_mean=st.mean(gain),
+                               ratio_sd=st.pstdev(gain))
+                log(f"{k2}: plain {res[k2]['plain_mean']:.6f} refined {res[k2]['refined_mean']:.6f} "
+                    f"(plain/refined {res[k2]['ratio_mean']:.3f} +- {res[k2]['ratio_sd']:.3f})")
+        if args.save_weights:
+            save_params(p, args.save_weights)
+    if args.infer_n:
+        # inference throughput (MFMA forward)
+        g = scenes.gaussians(args.infer_n, 7, 0.01, 0.1, flat=True)
+        xi = refiner_features(to_gpu(g), 8)
         R.forward(xi)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / reps
-    flop = 2.0 * (16 * 256 + 256 * 256 + 256 * 32) * args.infer_n   # padded operands as executed
-    res["inference"] = dict(n=args.infer_n, ms=dt * 1e3, tflops=flop / dt / 1e12, frac_of_bf16_peak=flop / dt / 2.5e15)
-    log(json.dumps(res["inference"]))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            R.forward(xi)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        flop = 2.0 * (16 * 256 + 256 * 256 + 256 * 32) * args.infer_n   # padded operands as executed
+        res["inference"] = dict(n=args.infer_n, ms=dt * 1e3, tflops=flop / dt / 1e12,
+                                frac_of_bf16_peak=flop / dt / 2.5e15)
+        log(json.dumps(res["inference"]))
+        del xi
     if args.ft_n:
         g = scenes.gaussians(args.ft_n, 0, 0.01, 0.1, flat=True)
         cams = scenes.ring_cameras(args.ft_views, args.ft_res[0], args.ft_res[1])
-        tgt = target_images(g, cams, 1)
-        plain = time_to_mse(g, cams, tgt, steps=args.ft_steps)
-        log(f"plain: {plain['seconds']:.1f} s, final MSE {plain['final_mse']:.6f}")
-        refined = time_to_mse(g, cams, tgt, steps=args.ft_steps, R=R, target=plain["final_mse"])
-        log(f"refined: {refined['seconds']:.1f} s to MSE {plain['final_mse']:.6f} ({refined['steps']} steps)")
-        res["time_to_mse"] = dict(n=args.ft_n, views=args.ft_views, res=list(args.ft_res), plain=plain, refined=refined)
+        t = time.perf_counter()
+        tgt = target_images(g, cams, 1, views_per_call=2)
+        torch.cuda.synchronize()
+        log(f"targets: {args.ft_views} views {args.ft_res[0]}x{args.ft_res[1]} in {time.perf_counter() - t:.1f} s")
+        out = dict(n=args.ft_n, views=args.ft_views, res=list(args.ft_res), steps=args.ft_steps)
+        target = args.ft_target or None
+        if args.ft_mode in ("both", "plain"):
+            plain = time_to_mse(g, cams, tgt, steps=args.ft_steps, log=log)
+            log(f"plain: {plain['seconds']:.1f} s, final MSE {plain['final_mse']:.6f}")
+            out["plain"] = plain
+            target = plain["final_mse"]
+        if args.ft_mode in ("both", "refined"):
+            refined = time_to_mse(g, cams, tgt, steps=args.ft_steps, R=R, target=target, log=log)
+            log(f"refined: {refined['seconds']:.1f} s to MSE {target} ({refined['steps']} steps)")
+            out["refined"] = refined
+        res["time_to_mse"] = out
     print(json.dumps(res))
 
 
