@@ -31,6 +31,28 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
+# HBM bytes per launch (read, written) of the two heaviest kernels at the
+# autotuned configuration (tile 32x16, ordering buffer 16), from rocprofv3
+# --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by the same counters over a
+# 1 GiB device copy (profiles/batched_render_8x1080p_tile32x16_kbuf16.md).
+# They describe the kernel sources they were measured on: with any other
+# source (hash below) or configuration the traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "49cd03834c78207c0c82f2060dd0ca4b48ba05fa5b7aa17ae78a5a77ae325494",
+    "tile": [32, 16], "kbuf": 16,
+    "composite": (22671435384, 6734894208),
+    "bwd_grads": (13962457756, 7665067520),
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2502_07754_amd/csrc/raster.hip", "paper_2502_07754_amd/csrc/common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -101,7 +123,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=500_000, help="Gaussians")
     ap.add_argument("--views", type=int, default=8)
-    ap.add_argument("--tile", type=int, default=0, help="0: autotuned")
+    ap.add_argument("--tile", type=int, default=0, help="tile width (and height unless --tile-h); 0: autotuned")
+    ap.add_argument("--tile-h", type=int, default=0, help="tile height (default: --tile)")
     ap.add_argument("--kbuf", type=int, default=0, help="0: autotuned")
     ap.add_argument("--no-graph", action="store_true", help="eager calls instead of the captured step")
     ap.add_argument("--list-rows", type=int, default=128,
@@ -137,13 +160,14 @@ def main():
     ctx.timing(True)
     faces = msp.convert(gg, K, sigma)
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
-    opts = msp.RenderOptions(tile_w=args.tile, tile_h=args.tile, kbuf=args.kbuf, t_eps=1e-6, color_mode=1,
+    th = args.tile_h or args.tile
+    opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=1,
                              list_rows=args.list_rows)
     if args.tile == 0 or args.kbuf == 0:
         t0 = time.perf_counter()
         tuned = msp.autotune(faces, cams, opts, dimg)
         log(f"autotuned tile {tuned.tile_w}x{tuned.tile_h}, kbuf {tuned.kbuf} in {time.perf_counter() - t0:.1f} s")
-        opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=args.tile or tuned.tile_h,
+        opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=th or tuned.tile_h,
                                  kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=1, list_rows=args.list_rows)
     state = msp.RenderState(ctx)
     if args.no_graph:
@@ -197,9 +221,9 @@ def main():
     frags = st["fragments"]
     entries = st["entries"]
     if dom in ("composite", "bwd_lists"):
-        # per composited fragment: barycentrics, alpha, colour, blend (~40 flop);
-        # per (tile entry, pixel) coverage test (~12 flop) is counted via entries x tile pixels
-        flop = 40.0 * frags + 12.0 * entries * 64
+        # per composited fragment: barycentrics, depth, alpha, colour, blend (~40 flop);
+        # per (face, pixel inside the face's pixel rectangle) one coverage test (3 edge functions, 12 flop)
+        flop = 40.0 * frags + 12.0 * st["footprint_pixels"]
         roof = dict(bound="alu", achieved=flop / (dom_ms * 1e-3) / 1e12, peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", traffic=None)
     elif dom == "bwd_grads":
@@ -213,6 +237,10 @@ def main():
                   "sh_bwd": (192 * 2 + 36 + 12 * args.views) * faces["idx"].shape[1]}.get(dom, 0.0)
         roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                     traffic=None)
+    mt = MEASURED_TRAFFIC
+    if (dom in mt and kernel_sources_sha256() == mt["sources_sha256"] and [opts.tile_w, opts.tile_h] == mt["tile"]
+            and opts.kbuf == mt["kbuf"]):
+        roof["traffic"] = float(sum(mt[dom]))
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
     roof["ms_per_launch"] = dom_ms

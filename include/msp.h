@@ -114,6 +114,7 @@ typedef struct msp_render_stats {
   int64_t max_tile_entries; /* longest tile list */
   int64_t fragments;        /* fragments composited (before early stop) over all views */
   int64_t restarts;         /* ordering-buffer overflows resolved by re-scanning a tile list */
+  int64_t footprint_pixels; /* sum over drawn (view, face) of the pixel rectangle the face's corners span */
 } msp_render_stats;
 
 /* ---- context ---------------------------------------------------------- */

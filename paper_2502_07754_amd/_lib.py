@@ -48,7 +48,8 @@ class AdamGroup(C.Structure):
 
 class RenderStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_views", "width", "height", "tile_w", "tile_h", "entries",
-                                         "max_tile_entries", "fragments", "restarts")]
+                                         "max_tile_entries", "fragments", "restarts",
+                                         "footprint_pixels")]
 
 
 EXPORTS = {

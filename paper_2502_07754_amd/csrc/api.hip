@@ -515,7 +515,7 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
   (void)hipStreamSynchronize(ctx->stream);
   DevBuf* bufs[] = {&st->cams, &st->geo, &st->attr, &st->tile_cnt, &st->tile_off, &st->cursor,
                     &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap,
-                    &st->blk_off, &st->frag_list, &st->col4, &st->dcol};
+                    &st->blk_off, &st->frag_list, &st->col4, &st->dcol, &st->fp_part};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   free_graph(ctx, st);
@@ -558,6 +558,7 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.nfrag = P<int32_t>(st->nfrag);
   a.counters = P<unsigned long long>(st->counters);
   a.ovf = reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5);
+  a.fp_part = P<unsigned long long>(st->fp_part);
 }
 
 static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
@@ -631,8 +632,10 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
       (rc = msp_ensure(ctx, st->geo, 48 * V * F)) || (rc = msp_ensure(ctx, st->attr, 64 * F)) ||
       (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
       (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
-      (rc = msp_ensure(ctx, st->counters, 8 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))))
+      (rc = msp_ensure(ctx, st->counters, 8 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))) ||
+      (rc = msp_ensure(ctx, st->fp_part, 8 * V * ((F + 255) / 256))))
     return (msp_status)rc;
+  st->fp_parts = F > 0 ? V * ((F + 255) / 256) : 0;
   if (st->h_cams_cap < n_views) {
     delete[] st->h_cams;
     st->h_cams = new msp_camera[n_views];
@@ -991,6 +994,12 @@ msp_status msp_state_stats(msp_ctx* ctx, msp_state* st, msp_render_stats* out) {
   out->max_tile_entries = mx;
   out->fragments = (int64_t)c[0];
   out->restarts = (int64_t)c[1];
+  std::vector<unsigned long long> fp((size_t)st->fp_parts);
+  if (st->fp_parts)
+    MSP_HIP(ctx, hipMemcpy(fp.data(), st->fp_part.p, sizeof(unsigned long long) * st->fp_parts, hipMemcpyDeviceToHost));
+  int64_t fps = 0;
+  for (unsigned long long v : fp) fps += (int64_t)v;
+  out->footprint_pixels = fps;
   return MSP_OK;
 }
 

@@ -64,7 +64,8 @@ struct msp_state {
   std::vector<TimerRec> graph_timer;  // stage events captured into the graph (timing on at capture)
 
   DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, keys, tmp, nfrag, counters,
-      scan_part, blk_cap, blk_off, frag_list, col4, dcol;
+      scan_part, blk_cap, blk_off, frag_list, col4, dcol, fp_part;
+  int64_t fp_parts = 0;          // entries of fp_part written by the last render
 };
 
 // ---- error helpers (host) ----
@@ -111,8 +112,10 @@ struct RasterArgs {
   float bg0, bg1, bg2;
   float* img;              // [V][4][H][W]
   int32_t* nfrag;          // [V][H][W]
-  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd list queue, [4] bwd grad queue
+  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd list queue, [4] bwd grad queue,
+                                 // [5] overflow flag
   uint32_t* ovf;           // overflow flag (low word of counters[5]); set: kernels of the step return at once
+  unsigned long long* fp_part;  // [views][setup workgroups] footprint pixels per setup workgroup (statistics)
   // backward
   const float* dimg;
   const int64_t* blk_off;  // [n_blocks + 1] in units of 64-slot rows

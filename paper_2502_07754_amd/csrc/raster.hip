@@ -142,6 +142,7 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
   const msp_camera c = a.cams[view];
   bool ok = false;
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
+  int rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;  // pixel rectangle of a drawn face
   if (f < F) {
     float4 g0 = make_float4(0, 0, 0, 0), g1 = g0;
     float4 g2 = make_float4(0.f, __uint_as_float(1u), __uint_as_float(0u), 0.f);
@@ -165,6 +166,10 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
         fy1 = fminf(fy1, (float)(a.H - 1));
         if (fx0 <= fx1 && fy0 <= fy1) {
           const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
+          rx0 = px0;
+          rx1 = px1;
+          ry0 = py0;
+          ry1 = py1;
           const float zmin = fminf(fminf(p0.zc, p1.zc), p2.zc);
           tx0 = px0 / a.tile_w;
           ty0 = py0 / a.tile_h;
@@ -182,6 +187,21 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
     geo[0] = g0;
     geo[1] = g1;
     geo[2] = g2;
+  }
+  // footprint pixels of the drawn faces per workgroup (statistics: the coverage
+  // tests the pixels ask for); summed on the host when statistics are read
+  {
+    __shared__ unsigned long long fsum[256 / MSP_WAVE];
+    unsigned long long area = 0;
+    if (ok) area = (unsigned long long)(rx1 - rx0 + 1) * (unsigned long long)(ry1 - ry0 + 1);
+    for (int d = 32; d >= 1; d >>= 1) area += __shfl_xor(area, d);
+    if (lane_id() == 0) fsum[threadIdx.x / MSP_WAVE] = area;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int w = 0; w < (int)(blockDim.x / MSP_WAVE); ++w) t += fsum[w];
+      a.fp_part[(int64_t)view * gridDim.x + blockIdx.x] = t;
+    }
   }
   // per-tile counts through the workgroup's tile table
   __shared__ int32_t tkey[kTableSlots];

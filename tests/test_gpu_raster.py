@@ -80,6 +80,8 @@ def test_tile_lists_bit_exact_config1(gpu, tile):
     roff, rkeys = ob.tile_lists(f["pos"], f["idx"], cams[0], *tile)
     assert np.array_equal(off, roff)
     assert np.array_equal(keys, rkeys)
+    _, (px0, px1, py0, py1), _ = ob.face_ranges(f["pos"], f["idx"], cams[0])
+    assert st.stats()["footprint_pixels"] == int(np.sum((px1 - px0 + 1) * (py1 - py0 + 1)))
 
 
 def test_tile_lists_bit_exact_multiview_ragged(gpu):
