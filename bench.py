@@ -131,6 +131,11 @@ def main():
                     help="fragment-list rows per pixel the forward stores for the backward (0: recompute)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scene", choices=("flat", "3d"), default="flat",
+                    help="flat: the batched-render scene; 3d: the same count of 3D Gaussians, scales "
+                         "log-U[0.005, 0.05] on all three axes")
+    ap.add_argument("--fan3", action="store_true",
+                    help="convert with three fans per Gaussian (3D-Gaussian conversion) instead of one")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device-to-device copy of this many GiB (bandwidth and "
                          "HBM-counter calibration) and exit")
@@ -153,12 +158,14 @@ def main():
     W, H = 1920, 1080
     g, cams, p = scenes.config3(n=args.n, views=args.views, width=W, height=H)
     K, sigma = p["K"], p["sigma"]
+    if args.scene == "3d":
+        g = scenes.gaussians(args.n, 0, 0.005, 0.05, flat=False, sh=True)
     dev = torch.device("cuda:0")
     gg = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
           dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=g.sh).items()}
     ctx = _lib.Context.get(0)
     ctx.timing(True)
-    faces = msp.convert(gg, K, sigma)
+    faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT)
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
     opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=1,
@@ -238,8 +245,9 @@ def main():
         roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                     traffic=None)
     mt = MEASURED_TRAFFIC
-    if (dom in mt and kernel_sources_sha256() == mt["sources_sha256"] and [opts.tile_w, opts.tile_h] == mt["tile"]
-            and opts.kbuf == mt["kbuf"]):
+    if (dom in mt and args.scene == "flat" and not args.fan3 and kernel_sources_sha256() == mt["sources_sha256"]
+            and [opts.tile_w, opts.tile_h] == mt["tile"] and opts.kbuf == mt["kbuf"] and args.n == 500_000
+            and args.views == 8):
         roof["traffic"] = float(sum(mt[dom]))
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
@@ -251,15 +259,16 @@ def main():
         "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.n} flat Gaussians, K={K}, sigma={sigma}, SH degree 3, {args.views} views "
-                               f"{W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
+        "config": {"workload": f"{args.n} {'flat' if args.scene == 'flat' else '3D'} Gaussians, "
+                               f"{'three fans' if args.fan3 else 'one fan'} of K={K}, sigma={sigma}, SH degree 3, "
+                               f"{args.views} views {W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
                    "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
                    "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
                    "entries_per_step": entries, "fragments_per_step": frags,
                    "fragments_per_s": frags / dt},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.scene == "flat" and not args.fan3:
         log("timing the oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(g, cams, K, sigma, args.cpu_seconds)
     print(json.dumps(out), flush=True)

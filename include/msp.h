@@ -84,7 +84,7 @@ typedef struct msp_camera {
   int32_t width, height; /* all views of one render share width and height */
 } msp_camera;
 
-enum { MSP_FAN_FLAT = 0 };                       /* conversion modes */
+enum { MSP_FAN_FLAT = 0, MSP_FAN_3D = 1 };       /* conversion modes */
 enum { MSP_COLOR_RGB = 0, MSP_COLOR_SH3 = 1 };   /* colour source of a render */
 
 typedef struct msp_render_opts {
@@ -130,8 +130,10 @@ int msp_version(void);
 
 /* ---- conversion --------------------------------------------------------- */
 
-/* Host-only sizing: n_verts = n (K + 1), n_faces = n K for MSP_FAN_FLAT.
- * EINVAL if K is outside [3, 64], n < 0 or mode is unknown. */
+/* Host-only sizing: n_verts = n (K + 1), n_faces = n K for MSP_FAN_FLAT;
+ * n_verts = n (7 + 3 (K - 4)), n_faces = 3 n K for MSP_FAN_3D (K a multiple
+ * of 4). EINVAL if K is outside [3, 64], n < 0, the mode is unknown or the
+ * counts reach 2^31. */
 msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_t* n_faces);
 
 /* Gaussian -> fan conversion (flat-Gaussian transformation section).
@@ -144,6 +146,14 @@ msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_
  * opacity is the Gaussian's at the centre and opac_mul times it on the
  * boundary. When g->sh is non-NULL each face gets its Gaussian's 48 SH
  * coefficients in out->sh. `out` arrays must be sized by msp_convert_size.
+ * mode MSP_FAN_3D (3D-Gaussian section: Eq. 3d_scaledrot, one fan on each of
+ * the planes of axes (1,2), (1,3), (2,3), sharing the points where the planes
+ * meet): per Gaussian vertex 0 is the mean, vertices 1..6 are m + A_1, m - A_1,
+ * m + A_2, m - A_2, m + A_3, m - A_3 (A_i = sigma s_i r_i), then per plane
+ * (i, j) its boundary points m + cos(t_k) A_i + sin(t_k) A_j for the K - 4
+ * angles off the quarter turns, in angle order; face 3Kg + pK + k is (centre,
+ * point k, point (k+1) mod K) of plane p, where the quarter turns t = -pi,
+ * -pi/2, 0, pi/2 are the shared points -A_i, -A_j, +A_i, +A_j.
  * EINVAL: sigma not finite and > 0, opac_mul not finite, NULL arrays with n > 0,
  * out sizes that differ from msp_convert_size, or out->sh NULL while g->sh is set. */
 msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,

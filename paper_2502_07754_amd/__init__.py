@@ -20,10 +20,12 @@ from ._lib import MspError
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
            "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_weights",
-           "refiner_apply_backward", "refiner_loss"]
+           "refiner_apply_backward", "refiner_loss", "MSP_FAN_FLAT", "MSP_FAN_3D"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
+MSP_FAN_FLAT = 0
+MSP_FAN_3D = 1
 
 
 def load_library():
@@ -51,16 +53,17 @@ def _ctx(t):
     return _lib.Context.get(t.device.index if t.device.index is not None else 0)
 
 
-def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2) -> dict:
+def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2, mode: int = 0) -> dict:
     """Gaussian -> triangle fans (msp_convert). `g` holds GPU float32 tensors
-    mean [3,N], scale [3,N], quat [4,N], opacity [N], rgb [3,N] and optionally sh [48,N]."""
+    mean [3,N], scale [3,N], quat [4,N], opacity [N], rgb [3,N] and optionally sh [48,N].
+    mode MSP_FAN_FLAT (one fan over the two largest axes) or MSP_FAN_3D (three fans)."""
     import torch
     mean = _need(g["mean"], torch.float32, "mean")
     ctx = _ctx(mean)
     ctx.bind_stream()
     n = mean.shape[1]
     nv, nf = C.c_int64(), C.c_int64()
-    ctx.check(ctx.lib.msp_convert_size(n, K, 0, C.byref(nv), C.byref(nf)), "msp_convert_size")
+    ctx.check(ctx.lib.msp_convert_size(n, K, int(mode), C.byref(nv), C.byref(nf)), "msp_convert_size")
     dev = mean.device
     sh = g.get("sh")
     out = dict(pos=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
@@ -75,7 +78,7 @@ def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2) -> dict:
                        _dev_ptr(_need(g["rgb"], torch.float32, "rgb")),
                        None if sh is None else _dev_ptr(_need(sh, torch.float32, "sh")))
     Fc = _faces_struct(out)
-    ctx.check(ctx.lib.msp_convert(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), 0, C.byref(Fc)),
+    ctx.check(ctx.lib.msp_convert(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), int(mode), C.byref(Fc)),
               "msp_convert")
     return out
 

@@ -215,9 +215,16 @@ msp_status msp_set_stream(msp_ctx* ctx, void* hip_stream) {
 const char* msp_last_error(const msp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_t* n_faces) {
-  if (n < 0 || K < 3 || K > 64 || mode != MSP_FAN_FLAT || !n_verts || !n_faces) return MSP_EINVAL;
-  *n_verts = n * (K + 1);
-  *n_faces = n * K;
+  if (n < 0 || K < 3 || K > 64 || !n_verts || !n_faces) return MSP_EINVAL;
+  if (mode == MSP_FAN_FLAT) {
+    *n_verts = n * (K + 1);
+    *n_faces = n * K;
+  } else if (mode == MSP_FAN_3D && K % 4 == 0) {
+    *n_verts = n * (7 + 3 * (K - 4));
+    *n_faces = n * 3 * K;
+  } else {
+    return MSP_EINVAL;
+  }
   if (*n_verts >= (int64_t(1) << 31) || *n_faces >= (int64_t(1) << 31)) return MSP_EINVAL;
   return MSP_OK;
 }
@@ -246,7 +253,10 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
     cs[k] = (float)std::cos(th);
     cs[K + k] = (float)std::sin(th);
   }
-  MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  if (mode == MSP_FAN_3D)
+    MSP_TIMED(ctx, ST_CONVERT, launch_convert_three(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  else
+    MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
   return MSP_OK;
 }
 

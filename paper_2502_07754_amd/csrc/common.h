@@ -85,6 +85,8 @@ hipError_t launch_fill_f32(hipStream_t s, float* p, float v, int64_t n);
 
 hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
                                const float* cos_sin, msp_faces* out);
+hipError_t launch_convert_three(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
+                                const float* cos_sin, msp_faces* out);
 
 // exclusive scan of n uint32 values into n+1 int64 offsets (last = total); scratch sized by scan_scratch_bytes
 size_t scan_scratch_bytes(int64_t n);

@@ -613,11 +613,87 @@ __device__ __forceinline__ bool decode_item(const RasterArgs& a, uint32_t item, 
   return it.bx0 < a.W && it.by0 < a.H;
 }
 
-template <int KB>
-struct KBuf {
+
+// Per-lane ordering buffer in registers: up to KB fragments sorted by key
+// (depth bits, face id), with alpha and (COL) the interpolated colour.
+// Insertion is a compare-select network, popping a shift.
+template <int KB, bool COL>
+struct RegBuf {
   float z[KB];
   uint32_t f[KB];
   float al[KB], cr[KB], cg[KB], cb[KB];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      z[i] = __uint_as_float(0x7f800000u);
+      f[i] = kEmpty;
+    }
+  }
+  __device__ __forceinline__ void init() {
+    clear();
+#pragma unroll
+    for (int i = 0; i < KB; ++i) al[i] = cr[i] = cg[i] = cb[i] = 0.f;
+  }
+  __device__ __forceinline__ bool empty() const { return f[0] == kEmpty; }
+  __device__ __forceinline__ float front_z() const { return z[0]; }
+  __device__ __forceinline__ uint32_t front_f() const { return f[0]; }
+  __device__ __forceinline__ float front_al() const { return al[0]; }
+  __device__ __forceinline__ uint64_t front_key() const { return mkkey(z[0], f[0]); }
+  __device__ __forceinline__ void front_col(float& r, float& g, float& b) const {
+    r = cr[0];
+    g = cg[0];
+    b = cb[0];
+  }
+  __device__ __forceinline__ void pop() {
+#pragma unroll
+    for (int i = 0; i < KB - 1; ++i) {
+      z[i] = z[i + 1];
+      f[i] = f[i + 1];
+      al[i] = al[i + 1];
+      if (COL) {
+        cr[i] = cr[i + 1];
+        cg[i] = cg[i + 1];
+        cb[i] = cb[i + 1];
+      }
+    }
+    z[KB - 1] = __uint_as_float(0x7f800000u);
+    f[KB - 1] = kEmpty;
+  }
+  // inserts (nk, ...) in order; when full, the largest of buffer + new is
+  // dropped and `drop` lowered to it
+  __device__ __forceinline__ void insert(uint64_t nk, float zz, uint32_t fid, float a_, float r, float g, float b,
+                                         uint64_t& drop) {
+    const bool full = f[KB - 1] != kEmpty;
+    const uint64_t lastk = mkkey(z[KB - 1], f[KB - 1]);
+    if (full) drop = nk < lastk ? lastk : nk;
+    if (full && nk > lastk) return;
+    bool cpos[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(z[i], f[i]);
+#pragma unroll
+    for (int i = KB - 1; i >= 1; --i) {
+      const bool up = cpos[i - 1];
+      const bool put = !up && cpos[i];
+      z[i] = up ? z[i - 1] : (put ? zz : z[i]);
+      f[i] = up ? f[i - 1] : (put ? fid : f[i]);
+      al[i] = up ? al[i - 1] : (put ? a_ : al[i]);
+      if (COL) {
+        cr[i] = up ? cr[i - 1] : (put ? r : cr[i]);
+        cg[i] = up ? cg[i - 1] : (put ? g : cg[i]);
+        cb[i] = up ? cb[i - 1] : (put ? b : cb[i]);
+      }
+    }
+    if (cpos[0]) {
+      z[0] = zz;
+      f[0] = fid;
+      al[0] = a_;
+      if (COL) {
+        cr[0] = r;
+        cg[0] = g;
+        cb[0] = b;
+      }
+    }
+  }
 };
 
 // Loads entry `e` of the tile list (key, records), used one chunk ahead of its use.
@@ -637,12 +713,13 @@ __device__ __forceinline__ Prefetch prefetch_entry(const RasterArgs& a, const It
   return p;
 }
 
-// Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1 also
+// Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1
 // records each composited fragment (face id, transmittance before it) into the
-// block's list slab.
-template <int KB, int MODE, bool SHP>
-__device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, int lane, float& T, float& Cr,
-                            float& Cg, float& Cb, int& nf, uint32_t& restarts, uint2* list, int64_t list_rows) {
+// block's list slab. Buf is the ordering buffer.
+template <int KB, int MODE, bool SHP, class Buf>
+__device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Buf& kb, int lane, float& T,
+                            float& Cr, float& Cg, float& Cb, int& nf, uint32_t& restarts, uint2* list,
+                            int64_t list_rows) {
   const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
   const bool valid = px < a.W && py < a.H;
   const int64_t beg = a.tile_off[it.seg];
@@ -652,13 +729,7 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
   const bool sh = a.col4 != nullptr;
   const float eps = a.t_eps;
 
-  KBuf<KB> kb;
-#pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    kb.z[i] = __uint_as_float(0x7f800000u);
-    kb.f[i] = kEmpty;
-    kb.al[i] = kb.cr[i] = kb.cg[i] = kb.cb[i] = 0.f;
-  }
+  kb.init();
   T = 1.f;
   Cr = Cg = Cb = 0.f;
   nf = 0;
@@ -666,48 +737,36 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
   int state = valid ? ACTIVE : DONE;
 
   auto pop_front = [&]() {
+    const uint32_t f0 = kb.front_f();
+    const float al0 = kb.front_al();
     if (list != nullptr) {
-      if (nf < list_rows) list[(int64_t)nf * MSP_WAVE + lane] = make_uint2(kb.f[0], __float_as_uint(T));
+      if (nf < list_rows) list[(int64_t)nf * MSP_WAVE + lane] = make_uint2(f0, __float_as_uint(T));
     }
     if (MODE == 0) {
-      const float w = T * kb.al[0];
+      const float w = T * al0;
       if (SHP) {
         // per-face colour of this view, fetched when the fragment is composited
-        const float4 c = a.col4[(int64_t)it.view * a.n_faces + kb.f[0]];
+        const float4 c = a.col4[(int64_t)it.view * a.n_faces + f0];
         Cr = fmaf(w, c.x, Cr);
         Cg = fmaf(w, c.y, Cg);
         Cb = fmaf(w, c.z, Cb);
       } else {
-        Cr = fmaf(w, kb.cr[0], Cr);
-        Cg = fmaf(w, kb.cg[0], Cg);
-        Cb = fmaf(w, kb.cb[0], Cb);
+        float r, g, b;
+        kb.front_col(r, g, b);
+        Cr = fmaf(w, r, Cr);
+        Cg = fmaf(w, g, Cg);
+        Cb = fmaf(w, b, Cb);
       }
     }
-    T = T * (1.f - kb.al[0]);
-    last = mkkey(kb.z[0], kb.f[0]);
+    T = T * (1.f - al0);
+    last = kb.front_key();
     ++nf;
-#pragma unroll
-    for (int i = 0; i < KB - 1; ++i) {
-      kb.z[i] = kb.z[i + 1];
-      kb.f[i] = kb.f[i + 1];
-      kb.al[i] = kb.al[i + 1];
-      if (!SHP && MODE == 0) {
-        kb.cr[i] = kb.cr[i + 1];
-        kb.cg[i] = kb.cg[i + 1];
-        kb.cb[i] = kb.cb[i + 1];
-      }
-    }
-    kb.z[KB - 1] = __uint_as_float(0x7f800000u);
-    kb.f[KB - 1] = kEmpty;
+    kb.pop();
   };
   // composite every buffered fragment (all keys below the drop threshold are final)
   auto flush_all = [&]() {
-    while (kb.f[0] != kEmpty && T >= eps) pop_front();
-#pragma unroll
-    for (int i = 0; i < KB; ++i) {
-      kb.z[i] = __uint_as_float(0x7f800000u);
-      kb.f[i] = kEmpty;
-    }
+    while (!kb.empty() && T >= eps) pop_front();
+    kb.clear();
   };
 
   while (__any(state != DONE)) {
@@ -793,7 +852,7 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
           cov = 0;
           continue;
         }
-        while (kb.z[0] < W && T >= eps) pop_front();
+        while (kb.front_z() < W && T >= eps) pop_front();
         if (T < eps) {
           state = DONE;
           cov = 0;
@@ -806,36 +865,7 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, in
         if (!(nk > lo && nk < drop)) continue;
         float raw, al, cr, cg, cb;
         frag_attr(S, sh, b0, b1, b2, raw, al, cr, cg, cb);
-        const bool full = kb.f[KB - 1] != kEmpty;
-        const uint64_t lastk = mkkey(kb.z[KB - 1], kb.f[KB - 1]);
-        if (full) drop = nk < lastk ? lastk : nk;  // the largest of buffer + new is dropped
-        if (full && nk > lastk) continue;
-        bool cpos[KB];
-#pragma unroll
-        for (int i = 0; i < KB; ++i) cpos[i] = nk < mkkey(kb.z[i], kb.f[i]);
-#pragma unroll
-        for (int i = KB - 1; i >= 1; --i) {
-          const bool up = cpos[i - 1];
-          const bool put = !up && cpos[i];
-          kb.z[i] = up ? kb.z[i - 1] : (put ? z : kb.z[i]);
-          kb.f[i] = up ? kb.f[i - 1] : (put ? fid : kb.f[i]);
-          kb.al[i] = up ? kb.al[i - 1] : (put ? al : kb.al[i]);
-          if (!SHP && MODE == 0) {
-            kb.cr[i] = up ? kb.cr[i - 1] : (put ? cr : kb.cr[i]);
-            kb.cg[i] = up ? kb.cg[i - 1] : (put ? cg : kb.cg[i]);
-            kb.cb[i] = up ? kb.cb[i - 1] : (put ? cb : kb.cb[i]);
-          }
-        }
-        if (cpos[0]) {
-          kb.z[0] = z;
-          kb.f[0] = fid;
-          kb.al[0] = al;
-          if (!SHP && MODE == 0) {
-            kb.cr[0] = cr;
-            kb.cg[0] = cg;
-            kb.cb[0] = cb;
-          }
-        }
+        kb.insert(nk, z, fid, al, cr, cg, cb, drop);
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -853,6 +883,7 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
+  RegBuf<KB, !SHP> kb;  // with SH the colour comes from the face when a fragment is composited
   uint64_t frags = 0;
   uint32_t restarts = 0;
   if (*a.ovf & 3u) return;
@@ -866,7 +897,7 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
     float T, Cr, Cg, Cb;
     int nf;
     uint2* list = a.store_rows ? a.frag_list + it.blk * a.store_rows * MSP_WAVE : nullptr;
-    trace_block<KB, 0, SHP>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, list, a.store_rows);
+    trace_block<KB, 0, SHP>(a, it, slab, kb, lane, T, Cr, Cg, Cb, nf, restarts, list, a.store_rows);
     if (a.store_rows) {
       // a block whose longest list does not fit is recomputed by the backward pass
       int mx = nf;
@@ -916,6 +947,7 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
+  RegBuf<KB, false> kb;  // lists record face ids and transmittance only
   uint32_t restarts = 0;
   if (*a.ovf & 3u) return;
   for (;;) {
@@ -929,7 +961,8 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
     const int64_t rows = a.blk_off[it.blk + 1] - row0;
     float T, Cr, Cg, Cb;
     int nf;
-    trace_block<KB, 1, false>(a, it, slab, lane, T, Cr, Cg, Cb, nf, restarts, a.frag_list + row0 * MSP_WAVE, rows);
+    trace_block<KB, 1, false>(a, it, slab, kb, lane, T, Cr, Cg, Cb, nf, restarts, a.frag_list + row0 * MSP_WAVE,
+                              rows);
   }
 }
 

@@ -37,8 +37,13 @@ def test_version_and_sizing(libmsp_path):
     assert lib.msp_convert_size(500_000, 16, 0, C.byref(nv), C.byref(nf)) == 0
     assert (nv.value, nf.value) == (8_500_000, 8_000_000)
     assert lib.msp_convert_size(0, 8, 0, C.byref(nv), C.byref(nf)) == 0 and nf.value == 0
-    for n, K, mode in [(-1, 8, 0), (10, 2, 0), (10, 65, 0), (10, 8, 7), (300_000_000, 8, 0)]:
+    for n, K, mode in [(-1, 8, 0), (10, 2, 0), (10, 65, 0), (10, 8, 7), (300_000_000, 8, 0), (10, 6, 1)]:
         assert lib.msp_convert_size(n, K, mode, C.byref(nv), C.byref(nf)) == -1
+    # three fans: centre + 6 shared axis points + 3 (K - 4) others; 3K faces (19 vertices for K = 8)
+    assert lib.msp_convert_size(100, 8, 1, C.byref(nv), C.byref(nf)) == 0
+    assert (nv.value, nf.value) == (1900, 2400)
+    assert lib.msp_convert_size(10, 4, 1, C.byref(nv), C.byref(nf)) == 0
+    assert (nv.value, nf.value) == (70, 120)
 
 
 def test_null_context_is_rejected(libmsp_path):

@@ -60,6 +60,39 @@ def test_convert_sh_and_empty(gpu):
     assert out["pos"].shape == (3, 0) and out["idx"].shape == (3, 0)
 
 
+@pytest.mark.parametrize("n,K", [(1, 4), (257, 8), (1000, 16)])
+def test_convert_three_fans_parity(gpu, n, K):
+    """3D-Gaussian conversion (three fans sharing their axis points) against the oracle."""
+    import torch
+    _say("convert three fans", n, K)
+    g = scenes.gaussians(n, 19, 0.005, 0.05, flat=False, sh=True)
+    out = gpu.convert(gaussians_gpu(g), K, 2.0, mode=gpu.MSP_FAN_3D)
+    torch.cuda.synchronize()
+    ref = oc.convert_three_fans(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, 2.0)
+    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    assert np.array_equal(out["gid"].cpu().numpy(), ref["gid"])
+    per = 7 + 3 * (K - 4)
+    mag = np.abs(np.asarray(g.mean, np.float64)) + 2.0 * np.max(np.asarray(g.scale, np.float64), axis=0)
+    ulp = np.spacing(np.repeat(mag, per, axis=1).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(out["pos"].cpu().numpy().astype(np.float64) - ref["pos"]) <= 4 * ulp)
+    np.testing.assert_allclose(out["opacity"].cpu().numpy(), ref["opacity"], rtol=1e-6)
+    assert np.array_equal(out["rgb"].cpu().numpy(), ref["rgb"].astype(np.float32))
+    sh = np.asarray(g.sh, np.float32)
+    assert np.array_equal(out["sh"].cpu().numpy(), np.repeat(sh, 3 * K, axis=1))
+
+
+def test_three_fan_image_parity(gpu):
+    """A small 3D scene converted with three fans renders like the oracle."""
+    g = scenes.gaussians(150, 23, 0.05, 0.2, flat=False)
+    f = faces_f32(oc.convert_three_fans(g.mean, g.scale, g.quat, g.opacity, g.rgb, 8, 2.0))
+    cam = scenes.ring_cameras(1, 48, 40)[0]
+    img, _ = gpu.render(to_gpu(f), [cam], gpu.RenderOptions(t_eps=0.0))
+    px = [(i, j) for j in range(40) for i in range(48)]
+    unexplained, flagged, covered, worst = _check_image(img[0].cpu().numpy().astype(np.float64), f, cam, px)
+    print("three fans:", worst, flagged, covered, flush=True)
+    assert not unexplained and flagged <= 0.02 * covered
+
+
 def test_convert_rejects_bad_sigma(gpu):
     g = scenes.gaussians(10, 3, 0.01, 0.1, flat=True)
     for s in (0.0, -1.0, float("nan"), float("inf")):
