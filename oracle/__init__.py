@@ -20,4 +20,6 @@ Modules:
   sh        real spherical harmonics up to degree 3
   finetune  loss, Adam step and pruning (fine-tuning section)
   mlp       refiner MLP with bfloat16 rounding points
+  prior     mesh-prior mode: secondary triangles as convex combinations of a
+            geometry mesh face's corners (mesh-prior section)
 """

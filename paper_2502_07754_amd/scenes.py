@@ -165,3 +165,55 @@ def config5(seed: int = 0, n: int = 3_000_000, views: int = 16, width: int = 192
     """3M flat Gaussians, K=8, sixteen 1920x1080 ring views."""
     g = gaussians(n, seed, 0.01, 0.1, flat=True)
     return g, ring_cameras(views, width, height), dict(K=8, sigma=2.0)
+
+
+# ---------------------------------------------------------------------------
+# A geometry mesh for the mesh-prior mode: stands in for a mesh estimated by an
+# external surface-reconstruction tool.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Mesh:
+    pos: np.ndarray   # [3][Vm] f32
+    idx: np.ndarray   # [3][Fm] i32, counter-clockwise seen from outside
+    rgb: np.ndarray   # [3][Vm] f32 in [0, 1]
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.idx.shape[1])
+
+
+def icosphere(level: int, seed: int, radius: float = 1.0, bump: float = 0.1) -> Mesh:
+    """Icosahedron split `level` times into four (edge midpoints pushed to the
+    sphere): 20 4^level faces, 10 4^level + 2 vertices. Each vertex is then
+    moved radially by bump * radius * sin(3 u . p + phase) and coloured
+    0.5 + 0.5 sin(4 w_c . p + phase_c), with u, w_c unit vectors and phases
+    drawn from default_rng(seed)."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    p = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=np.float64)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4], [11, 10, 2],
+                  [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5],
+                  [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    for _ in range(level):
+        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
+        key = np.sort(e, axis=1)
+        uniq, inv = np.unique(key[:, 0] * (len(p) + 1) + key[:, 1], return_inverse=True)
+        a, b = uniq // (len(p) + 1), uniq % (len(p) + 1)
+        mid = p[a] + p[b]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        m = len(p) + inv.reshape(3, -1)                        # midpoints of edges (0,1), (1,2), (2,0)
+        p = np.concatenate([p, mid])
+        f = np.concatenate([np.stack([f[:, 0], m[0], m[2]], 1), np.stack([f[:, 1], m[1], m[0]], 1),
+                            np.stack([f[:, 2], m[2], m[1]], 1), np.stack([m[0], m[1], m[2]], 1)])
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    w = rng.normal(size=(3, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    ph = rng.uniform(0, 2 * math.pi, size=4)
+    r = radius * (1.0 + bump * np.sin(3.0 * p @ u + ph[0]))
+    pos = p * r[:, None]
+    rgb = 0.5 + 0.5 * np.sin(4.0 * p @ w.T + ph[1:])
+    return Mesh(pos=_f32(pos.T), idx=np.ascontiguousarray(f.T.astype(np.int32)), rgb=_f32(rgb.T))
