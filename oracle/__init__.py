@@ -20,6 +20,8 @@ Modules:
   sh        real spherical harmonics up to degree 3
   finetune  loss, Adam step and pruning (fine-tuning section)
   mlp       refiner MLP with bfloat16 rounding points
+  rays      transmittance and closest hit of secondary rays through the soup
+            (the ray-tracing use named in the abstract and introduction)
   prior     mesh-prior mode: secondary triangles as convex combinations of a
             geometry mesh face's corners (mesh-prior section)
 """
