@@ -116,6 +116,89 @@ def copy_bandwidth(gib: float, reps: int):
                       "GB_per_s": nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def bench_rays(args):
+    """Secondary rays through the faces of the batched-render scene: one step is
+    a transmittance query over R shadow segments (to a point light) and a
+    closest-hit query over R incoherent rays, both against one hierarchy."""
+    import numpy as np
+    import torch
+
+    import paper_2502_07754_amd as msp
+    from paper_2502_07754_amd import scenes
+
+    dev = torch.device("cuda:0")
+    g, _, p = scenes.config3(n=args.n, views=1, width=64, height=64)
+    gg = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
+          dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb).items()}
+    faces = msp.convert(gg, p["K"], p["sigma"])
+    R = args.rays
+    shadow = [torch.from_numpy(a).to(dev) for a in scenes.shadow_rays(R, 0)]
+    scatter = [torch.from_numpy(a).to(dev) for a in scenes.scatter_rays(R, 1)]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    b0, b1 = ev(), ev()
+    b0.record()
+    bvh = msp.Bvh(faces)
+    b1.record()
+    torch.cuda.synchronize()
+    build_ms = b0.elapsed_time(b1)
+    log(f"hierarchy over {faces['idx'].shape[1]} faces built in {build_ms:.2f} ms")
+
+    def step(times=None):
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        T = bvh.transmittance(*shadow, t_eps=1e-6)
+        e[1].record()
+        hit = bvh.closest(*scatter, alpha_min=0.0)
+        e[2].record()
+        if times is not None:
+            times.append(e)
+        return T, hit
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st0 = bvh.status()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(times)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st1 = bvh.status()
+    ms_T = sum(e[0].elapsed_time(e[1]) for e in times) / args.steps
+    ms_C = sum(e[1].elapsed_time(e[2]) for e in times) / args.steps
+    T, hit = step()
+    torch.cuda.synchronize()
+    occl = float((T < 1).float().mean())
+    hits = float((hit[1] >= 0).float().mean())
+    visits = (st1["node_visits"] - st0["node_visits"]) / args.steps
+    leaf = (st1["leaf_tests"] - st0["leaf_tests"]) / args.steps
+    log(f"transmittance {ms_T:.3f} ms, closest {ms_C:.3f} ms per query; occluded {occl:.3f}, hit {hits:.3f}; "
+        f"per ray {visits / (2 * R):.1f} node visits, {leaf / (2 * R):.1f} leaf tests")
+    # algorithmic bytes of the dominant query: 64-byte node and leaf records per visit, ray in/out
+    dom, dom_ms = ("trace_closest", ms_C) if ms_C >= ms_T else ("trace_transmittance", ms_T)
+    nbytes = 64.0 * (visits + leaf) / 2 + R * (32 + (16 if dom == "trace_closest" else 4))
+    roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["ms_per_launch"] = dom_ms
+    roof["timing"] = "hip events on the query stream over the timed steps"
+    out = {
+        "metric": "Mrays/s (shadow transmittance + closest hit) through the converted soup",
+        "value": 2 * R / dt / 1e6, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.n} flat Gaussians, one fan of K={p['K']}, {faces['idx'].shape[1]} faces; "
+                               f"{R} shadow segments to a point light and {R} isotropic rays per step",
+                   "rays_per_query": R, "build_ms": build_ms, "transmittance_ms": ms_T, "closest_ms": ms_C,
+                   "occluded_fraction": occl, "hit_fraction": hits,
+                   "node_visits_per_ray": visits / (2 * R), "leaf_tests_per_ray": leaf / (2 * R)},
+        "roofline": roof,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,9 +214,16 @@ def main():
                     help="fragment-list rows per pixel the forward stores for the backward (0: recompute)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scene", choices=("flat", "3d"), default="flat",
+    ap.add_argument("--scene", choices=("flat", "3d", "prior", "rays"), default="flat",
                     help="flat: the batched-render scene; 3d: the same count of 3D Gaussians, scales "
-                         "log-U[0.005, 0.05] on all three axes")
+                         "log-U[0.005, 0.05] on all three axes; prior: mesh-prior mode, secondary triangles "
+                         "on an icosphere geometry mesh (positions from their logits and the logits' "
+                         "adjoint inside every step); rays: secondary rays through the batched-render "
+                         "scene's faces (hierarchy build, shadow transmittance and closest hit)")
+    ap.add_argument("--rays", type=int, default=4 * 1920 * 1080,
+                    help="rays per query for --scene rays (shadow segments and as many incoherent rays)")
+    ap.add_argument("--prior-level", type=int, default=7, help="icosphere subdivision level (20 4^level faces)")
+    ap.add_argument("--prior-n", type=int, default=2, help="secondary triangles per mesh face: n^2")
     ap.add_argument("--fan3", action="store_true",
                     help="convert with three fans per Gaussian (3D-Gaussian conversion) instead of one")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -152,6 +242,10 @@ def main():
         copy_bandwidth(args.copy_gib, max(1, args.steps))
         return
 
+    if args.scene == "rays":
+        bench_rays(args)
+        return
+
     import paper_2502_07754_amd as msp
     from paper_2502_07754_amd import _lib, scenes
 
@@ -165,17 +259,26 @@ def main():
           dict(mean=g.mean, scale=g.scale, quat=g.quat, opacity=g.opacity, rgb=g.rgb, sh=g.sh).items()}
     ctx = _lib.Context.get(0)
     ctx.timing(True)
-    faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT)
+    mesh = None
+    if args.scene == "prior":
+        m = scenes.icosphere(args.prior_level, 0)
+        mesh = {k: torch.from_numpy(v).to(dev) for k, v in dict(pos=m.pos, idx=m.idx, rgb=m.rgb).items()}
+        faces, logits = msp.prior_init(mesh, args.prior_n, shrink=0.05, opacity0=0.5)
+        dlogits = torch.empty_like(logits)
+        cm = msp.MSP_COLOR_RGB
+    else:
+        faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT)
+        cm = msp.MSP_COLOR_SH3
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
-    opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=1,
+    opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=cm,
                              list_rows=args.list_rows)
     if args.tile == 0 or args.kbuf == 0:
         t0 = time.perf_counter()
         tuned = msp.autotune(faces, cams, opts, dimg)
         log(f"autotuned tile {tuned.tile_w}x{tuned.tile_h}, kbuf {tuned.kbuf} in {time.perf_counter() - t0:.1f} s")
         opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=th or tuned.tile_h,
-                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=1, list_rows=args.list_rows)
+                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=cm, list_rows=args.list_rows)
     state = msp.RenderState(ctx)
     if args.no_graph:
         def step():
@@ -189,6 +292,15 @@ def main():
 
         def step():
             return gstep()
+
+    if mesh is not None:
+        render_step = step
+
+        def step():
+            msp.prior_vertices(mesh, args.prior_n, logits, out=faces["pos"])
+            img, grads = render_step()
+            msp.prior_backward(mesh, args.prior_n, logits, grads["dpos"], out=dlogits)
+            return img, grads
 
     for _ in range(args.warmup):
         step()
@@ -254,14 +366,20 @@ def main():
     roof["ms_per_launch"] = dom_ms
     roof["timing"] = timing_src
 
+    if mesh is not None:
+        workload = (f"mesh prior: icosphere level {args.prior_level} ({mesh['idx'].shape[1]} faces), "
+                    f"{args.prior_n ** 2} secondary triangles per face, RGB, {args.views} views {W}x{H}, "
+                    f"secondary positions + fwd + bwd + logit adjoint")
+    else:
+        workload = (f"{args.n} {'flat' if args.scene == 'flat' else '3D'} Gaussians, "
+                    f"{'three fans' if args.fan3 else 'one fan'} of K={K}, sigma={sigma}, SH degree 3, "
+                    f"{args.views} views {W}x{H}, fwd+bwd")
     out = {
         "metric": "Mpix/s fwd+bwd at 1080p, 500k Gaussians K=16; fine-tune s to target MSE",
         "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.n} {'flat' if args.scene == 'flat' else '3D'} Gaussians, "
-                               f"{'three fans' if args.fan3 else 'one fan'} of K={K}, sigma={sigma}, SH degree 3, "
-                               f"{args.views} views {W}x{H}, fwd+bwd", "views": args.views, "width": W, "height": H,
+        "config": {"workload": workload, "views": args.views, "width": W, "height": H,
                    "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
                    "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
                    "entries_per_step": entries, "fragments_per_step": frags,

@@ -245,6 +245,101 @@ msp_status msp_prune(msp_ctx* ctx, msp_faces* f, float thresh, float* const* vst
 msp_status msp_rings_size(int64_t n, int K, int rings, int64_t* n_verts, int64_t* n_faces);
 msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int rings, float sigma_max, msp_faces* out);
 
+/* ---- mesh prior ---------------------------------------------------------- */
+
+/* Mesh-prior mode (section "MeshSplats with Mesh Prior"). A fixed geometry
+ * mesh (from an external reconstruction tool) carries T = n^2 secondary,
+ * disjoint triangles per face; every secondary vertex is the convex
+ * combination v = a_1 m_1 + a_2 m_2 + a_3 m_3 of its mesh face's corners with
+ * a = softmax(theta) over three logits, so it stays on that face while the
+ * logits, colours and opacities are trained. Layout: secondary face
+ * f = mesh_face T + t owns vertices 3f, 3f + 1, 3f + 2; logits are [3][n_verts]
+ * with row j the logit of mesh corner j. Mesh indices outside [0, n_verts)
+ * give NaN positions (NaN colours at init) and zero logit gradients for that
+ * face's secondary vertices; nothing is read out of bounds. */
+typedef struct msp_mesh {
+  int64_t n_verts, n_faces;
+  const float* pos;    /* [3][n_verts] */
+  const int32_t* idx;  /* [3][n_faces] */
+  const float* rgb;    /* [3][n_verts] vertex colours, or NULL */
+} msp_mesh;
+
+/* Host-only sizing: n_verts = 3 n^2 n_mesh_faces, n_faces = n^2 n_mesh_faces.
+ * EINVAL if n is outside [1, 16], n_mesh_faces < 0 or a count reaches 2^31. */
+msp_status msp_prior_size(int64_t n_mesh_faces, int n, int64_t* n_verts, int64_t* n_faces);
+
+/* Initial secondary triangles: sub-triangle t of the regular subdivision with
+ * n segments per edge (grid point (a, b) weighs the corners ((n-a-b)/n, a/n,
+ * b/n); row a = 0..n-1 holds, for b = 0, 1, ..., the upward triangle ((a,b),
+ * (a+1,b), (a,b+1)) followed, while a + b <= n - 2, by the downward one
+ * ((a+1,b), (a+1,b+1), (a,b+1))), each corner's weights moved `shrink` of the
+ * way to its sub-triangle's centroid so that the triangles are disjoint and
+ * every weight is positive; theta = log(weights). Writes logits [3][V],
+ * out->idx, out->gid (mesh face of each secondary face, if not NULL),
+ * out->opacity = opacity0, out->rgb = the mesh vertex colours mixed with the
+ * initial weights (or rgb0, HOST [3], when m->rgb is NULL) and out->pos (as
+ * msp_prior_vertices). out->sh must be NULL. EINVAL: sizes that differ from
+ * msp_prior_size, shrink outside (0, 1), opacity0 outside [0, 1], NULL arrays. */
+msp_status msp_prior_init(msp_ctx* ctx, const msp_mesh* m, int n, float shrink, float opacity0, const float* rgb0,
+                          float* logits, msp_faces* out);
+/* Secondary vertex positions pos [3][V] from logits [3][V] (per vertex a
+ * max-shifted softmax in float32). EINVAL: n outside [1, 16], NULL arrays. */
+msp_status msp_prior_vertices(msp_ctx* ctx, const msp_mesh* m, int n, const float* logits, float* pos);
+/* Adjoint of msp_prior_vertices for the fixed mesh: with g_j = dpos . m_j,
+ * dlogits_j = a_j (g_j - sum_k a_k g_k). dpos [3][V] (e.g. from
+ * msp_render_backward), dlogits [3][V] overwritten. */
+msp_status msp_prior_backward(msp_ctx* ctx, const msp_mesh* m, int n, const float* logits, const float* dpos,
+                              float* dlogits);
+
+/* ---- secondary rays ------------------------------------------------------ */
+
+/* Ray tracing of the face soup, the use of the converted scene that the
+ * abstract and introduction name (shadow and other secondary rays). A ray is
+ * x(t) = origin + t dir for t in the open interval (tmin, tmax); it hits a
+ * face when the Moller-Trumbore solution has u >= 0, v >= 0, u + v <= 1
+ * (closed triangle) and a non-zero determinant (a ray in the face's plane
+ * misses); faces are double-sided; the opacity at a hit is
+ * alpha = clamp((1-u-v) o0 + u o1 + v o2, 0, 1), the renderer's interpolation
+ * at that point. */
+typedef struct msp_rays {
+  int64_t n;
+  const float* origin;  /* [3][n] */
+  const float* dir;     /* [3][n]; any non-zero length (t is in units of |dir|) */
+  const float* tmin;    /* [n] */
+  const float* tmax;    /* [n], may be +inf */
+} msp_rays;
+
+typedef struct msp_bvh msp_bvh;  /* library-owned bounding-volume hierarchy over a face soup */
+
+/* Builds a hierarchy over the faces (Morton order of the face centroids,
+ * hierarchy of Karras 2012, boxes bottom-up), entirely on the stream. The
+ * hierarchy keeps its own copy of each face's corners and opacities taken at
+ * build time; rebuild after the faces change. Faces with indices outside
+ * [0, n_verts) are never hit. EINVAL: NULL arguments, NULL arrays with
+ * n_faces > 0. ENOMEM: device allocation failed. */
+msp_status msp_bvh_build(msp_ctx* ctx, const msp_faces* f, msp_bvh** out);
+msp_status msp_bvh_free(msp_ctx* ctx, msp_bvh* b);
+/* Copies the hierarchy into caller DEVICE buffers (any may be NULL): nodes
+ * [n-1][16] floats (child 0 box lo xyz, hi xyz, child 1 box lo xyz, hi xyz,
+ * child references as int32 bits: >= 0 internal node, < 0 leaf ~j), leaves
+ * [n][16] (v0 xyz, o0, e1 xyz, o1, e2 xyz, o2, face id as int32 bits, 3 unused),
+ * root_box [6] (lo, hi). n = n_leaves (= n_faces). Asynchronous. */
+msp_status msp_bvh_export(msp_ctx* ctx, const msp_bvh* b, float* nodes, float* leaves, float* root_box);
+/* Synchronises; n_leaves, whether any query so far exceeded the 64-entry
+ * traversal stack (those rays returned NaN; the hierarchy's depth bound makes
+ * this unreachable), and the internal-node visits and leaf tests of all
+ * queries since the build. Any output pointer may be NULL. */
+msp_status msp_bvh_status(msp_ctx* ctx, const msp_bvh* b, int64_t* n_leaves, int32_t* overflowed,
+                          int64_t* node_visits, int64_t* leaf_tests);
+/* T [n]: product of (1 - alpha) over every hit in the interval (order-free).
+ * A ray stops once T < t_eps (t_eps = 0: every hit counts). */
+msp_status msp_trace_transmittance(msp_ctx* ctx, const msp_bvh* b, const msp_rays* r, float t_eps, float* T);
+/* Closest hit with alpha >= alpha_min, ties to the smaller face id: t [n]
+ * (+inf when none), face [n] (-1 when none), u, v [n] (barycentric weights of
+ * the face's second and third corners; may be NULL). */
+msp_status msp_trace_closest(msp_ctx* ctx, const msp_bvh* b, const msp_rays* r, float alpha_min, float* t,
+                             int32_t* face, float* u, float* v);
+
 /* ---- refiner: a small MLP that predicts better initial fans ------------- */
 
 /* The refiner is not in the paper: it maps each Gaussian to corrections of its

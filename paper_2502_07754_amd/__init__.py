@@ -20,7 +20,8 @@ from ._lib import MspError
 __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState", "MeshRender", "MspError",
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
            "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_weights",
-           "refiner_apply_backward", "refiner_loss", "MSP_FAN_FLAT", "MSP_FAN_3D"]
+           "refiner_apply_backward", "refiner_loss", "MSP_FAN_FLAT", "MSP_FAN_3D", "prior_init", "prior_vertices",
+           "prior_backward", "Bvh"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -319,6 +320,8 @@ def adam_step(groups: list, step: int, beta1=0.9, beta2=0.999, eps=1e-8):
     for i, g in enumerate(groups):
         for k in ("param", "grad", "m", "v"):
             _need(g[k], torch.float32, k)
+            if g[k].numel() != g["param"].numel():
+                raise ValueError(f"adam group {i}: {k} has {g[k].numel()} elements, param {g['param'].numel()}")
         cl = g.get("clamp")
         arr[i] = _lib.AdamGroup(_dev_ptr(g["param"]), _dev_ptr(g["grad"]), _dev_ptr(g["m"]), _dev_ptr(g["v"]),
                                 g["param"].numel(), float(g["lr"]), float(cl[0]) if cl else 0.0,
@@ -382,6 +385,163 @@ def convert_rings(g: dict, K: int, rings: int, sigma_max: float = 3.0) -> dict:
     ctx.check(ctx.lib.msp_convert_rings(ctx.h, C.byref(G), K, rings, float(sigma_max), C.byref(Fc)),
               "msp_convert_rings")
     return out
+
+
+def _mesh_struct(mesh: dict) -> _lib.Mesh:
+    import torch
+    pos = _need(mesh["pos"], torch.float32, "mesh pos")
+    idx = _need(mesh["idx"], torch.int32, "mesh idx")
+    rgb = mesh.get("rgb")
+    return _lib.Mesh(pos.shape[1], idx.shape[1], _dev_ptr(pos), _dev_ptr(idx),
+                     None if rgb is None else _dev_ptr(_need(rgb, torch.float32, "mesh rgb")))
+
+
+def prior_init(mesh: dict, n: int, shrink: float = 0.05, opacity0: float = 0.5, rgb0=(0.5, 0.5, 0.5)):
+    """msp_prior_init: n^2 secondary triangles per face of the geometry mesh
+    (dict of GPU tensors pos [3][Vm], idx [3][Fm] int32, optional rgb [3][Vm]).
+    Returns (faces, logits [3][V])."""
+    import torch
+    M = _mesh_struct(mesh)
+    ctx = _ctx(mesh["pos"])
+    ctx.bind_stream()
+    nv, nf = C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.msp_prior_size(M.n_faces, n, C.byref(nv), C.byref(nf)), "msp_prior_size")
+    dev = mesh["pos"].device
+    out = dict(pos=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               opacity=torch.empty((nv.value,), dtype=torch.float32, device=dev),
+               rgb=torch.empty((3, nv.value), dtype=torch.float32, device=dev),
+               idx=torch.empty((3, nf.value), dtype=torch.int32, device=dev),
+               gid=torch.empty((nf.value,), dtype=torch.int32, device=dev), sh=None)
+    logits = torch.empty((3, nv.value), dtype=torch.float32, device=dev)
+    c0 = (C.c_float * 3)(*[float(x) for x in rgb0])
+    Fc = _faces_struct(out)
+    ctx.check(ctx.lib.msp_prior_init(ctx.h, C.byref(M), n, float(shrink), float(opacity0), c0, _dev_ptr(logits),
+                                     C.byref(Fc)), "msp_prior_init")
+    return out, logits
+
+
+def prior_vertices(mesh: dict, n: int, logits, out=None):
+    """msp_prior_vertices: secondary vertex positions [3][V] from the logits."""
+    import torch
+    M = _mesh_struct(mesh)
+    logits = _need(logits, torch.float32, "logits")
+    if tuple(logits.shape) != (3, 3 * n * n * M.n_faces):
+        raise ValueError(f"logits must be [3][3 n^2 n_mesh_faces] = [3][{3 * n * n * M.n_faces}]")
+    if out is None:
+        out = torch.empty_like(logits)
+    _need(out, torch.float32, "pos")
+    if out.shape != logits.shape:
+        raise ValueError("pos must have the logits' shape [3][V]")
+    ctx = _ctx(logits)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.msp_prior_vertices(ctx.h, C.byref(M), n, _dev_ptr(logits), _dev_ptr(out)), "msp_prior_vertices")
+    return out
+
+
+def prior_backward(mesh: dict, n: int, logits, dpos, out=None):
+    """msp_prior_backward: dL/dlogits [3][V] from dL/dpos [3][V]."""
+    import torch
+    M = _mesh_struct(mesh)
+    logits = _need(logits, torch.float32, "logits")
+    if tuple(logits.shape) != (3, 3 * n * n * M.n_faces):
+        raise ValueError(f"logits must be [3][3 n^2 n_mesh_faces] = [3][{3 * n * n * M.n_faces}]")
+    dpos = _need(dpos, torch.float32, "dpos")
+    if dpos.shape != logits.shape:
+        raise ValueError("dpos must have the logits' shape [3][V]")
+    if out is None:
+        out = torch.empty_like(logits)
+    _need(out, torch.float32, "dlogits")
+    if out.shape != logits.shape:
+        raise ValueError("dlogits must have the logits' shape [3][V]")
+    ctx = _ctx(logits)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.msp_prior_backward(ctx.h, C.byref(M), n, _dev_ptr(logits), _dev_ptr(dpos), _dev_ptr(out)),
+              "msp_prior_backward")
+    return out
+
+
+class Bvh:
+    """msp_bvh_build and the ray queries (secondary rays through the soup).
+
+    The hierarchy holds a copy of the faces' corners and opacities taken when
+    it is built; rebuild it after the faces change."""
+
+    def __init__(self, faces: dict):
+        import torch
+        pos = _need(faces["pos"], torch.float32, "pos")
+        _need(faces["opacity"], torch.float32, "opacity")
+        _need(faces["idx"], torch.int32, "idx")
+        self.ctx = _ctx(pos)
+        self.ctx.bind_stream()
+        self.n_leaves = int(faces["idx"].shape[1])
+        self.device = pos.device
+        F = _faces_struct(faces)
+        h = C.c_void_p()
+        self.ctx.check(self.ctx.lib.msp_bvh_build(self.ctx.h, C.byref(F), C.byref(h)), "msp_bvh_build")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                self.ctx.lib.msp_bvh_free(self.ctx.h, h)
+            except Exception:
+                pass
+            self.h = None
+
+    @staticmethod
+    def _rays(origin, direction, tmin, tmax):
+        import torch
+        o = _need(origin, torch.float32, "origin")
+        d = _need(direction, torch.float32, "dir")
+        n = o.shape[1]
+        if o.dim() != 2 or o.shape[0] != 3 or tuple(d.shape) != (3, n):
+            raise ValueError("origin and dir must be [3][n]")
+        t0 = _need(tmin, torch.float32, "tmin")
+        t1 = _need(tmax, torch.float32, "tmax")
+        if t0.numel() != n or t1.numel() != n:
+            raise ValueError("tmin and tmax must have n entries")
+        return _lib.Rays(n, _dev_ptr(o), _dev_ptr(d), _dev_ptr(t0), _dev_ptr(t1)), n
+
+    def transmittance(self, origin, direction, tmin, tmax, t_eps: float = 0.0):
+        """msp_trace_transmittance: T [n]."""
+        import torch
+        R, n = self._rays(origin, direction, tmin, tmax)
+        T = torch.empty((n,), dtype=torch.float32, device=self.device)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_trace_transmittance(self.ctx.h, self.h, C.byref(R), float(t_eps),
+                                                            _dev_ptr(T)), "msp_trace_transmittance")
+        return T
+
+    def closest(self, origin, direction, tmin, tmax, alpha_min: float = 0.0):
+        """msp_trace_closest: (t, face, u, v), each [n]."""
+        import torch
+        R, n = self._rays(origin, direction, tmin, tmax)
+        e = lambda dt: torch.empty((n,), dtype=dt, device=self.device)
+        t, f, u, v = e(torch.float32), e(torch.int32), e(torch.float32), e(torch.float32)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_trace_closest(self.ctx.h, self.h, C.byref(R), float(alpha_min), _dev_ptr(t),
+                                                      _dev_ptr(f), _dev_ptr(u), _dev_ptr(v)), "msp_trace_closest")
+        return t, f, u, v
+
+    def export(self):
+        """(nodes [n-1][16], leaves [n][16], root_box [6]) as float32 GPU tensors."""
+        import torch
+        n = self.n_leaves
+        nodes = torch.empty((max(n - 1, 0), 16), dtype=torch.float32, device=self.device)
+        leaves = torch.empty((n, 16), dtype=torch.float32, device=self.device)
+        box = torch.empty((6,), dtype=torch.float32, device=self.device)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.msp_bvh_export(self.ctx.h, self.h, _dev_ptr(nodes) if n > 1 else None,
+                                                   _dev_ptr(leaves) if n > 0 else None, _dev_ptr(box)),
+                       "msp_bvh_export")
+        return nodes, leaves, box
+
+    def status(self) -> dict:
+        nl, ov, nn, nt = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
+        self.ctx.check(self.ctx.lib.msp_bvh_status(self.ctx.h, self.h, C.byref(nl), C.byref(ov), C.byref(nn),
+                                                   C.byref(nt)), "msp_bvh_status")
+        return dict(n_leaves=nl.value, overflowed=bool(ov.value), node_visits=nn.value, leaf_tests=nt.value)
 
 
 def _gauss_struct(g: dict) -> _lib.Gaussians:

@@ -27,6 +27,16 @@ class Faces(C.Structure):
                 ("rgb", C.c_void_p), ("sh", C.c_void_p), ("idx", C.c_void_p), ("gid", C.c_void_p)]
 
 
+class Mesh(C.Structure):
+    _fields_ = [("n_verts", C.c_int64), ("n_faces", C.c_int64), ("pos", C.c_void_p), ("idx", C.c_void_p),
+                ("rgb", C.c_void_p)]
+
+
+class Rays(C.Structure):
+    _fields_ = [("n", C.c_int64), ("origin", C.c_void_p), ("dir", C.c_void_p), ("tmin", C.c_void_p),
+                ("tmax", C.c_void_p)]
+
+
 class Camera(C.Structure):
     _fields_ = [("world_to_cam", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
                 ("cy", C.c_float), ("znear", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
@@ -85,6 +95,19 @@ EXPORTS = {
     "msp_rings_size": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "msp_convert_rings": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_int, C.c_float,
                                     C.POINTER(Faces)]),
+    "msp_prior_size": (C.c_int, [C.c_int64, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "msp_prior_init": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p,
+                                 C.POINTER(Faces)]),
+    "msp_prior_vertices": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p]),
+    "msp_prior_backward": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "msp_bvh_build": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(C.c_void_p)]),
+    "msp_bvh_free": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "msp_bvh_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "msp_bvh_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "msp_trace_transmittance": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Rays), C.c_float, C.c_void_p]),
+    "msp_trace_closest": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Rays), C.c_float, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
     "msp_refiner_create": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "msp_refiner_free": (C.c_int, [C.c_void_p, C.c_void_p]),
     "msp_refiner_set_weights": (C.c_int, [C.c_void_p, C.c_void_p] + [C.c_void_p] * 6),

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmsp.so")
 
-SOURCES = ["convert.hip", "scan.hip", "sh.hip", "raster.hip", "finetune.hip", "refiner.hip", "api.hip"]
+SOURCES = ["convert.hip", "scan.hip", "sh.hip", "raster.hip", "finetune.hip", "refiner.hip", "prior.hip", "trace.hip", "api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/msp.h: argument checking,
 // library-owned scratch, and the order of kernel launches on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -372,6 +373,178 @@ msp_status msp_convert_rings(msp_ctx* ctx, const msp_gaussians* g, int K, int ri
     return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert_rings: null array");
   DeviceGuard dg(ctx->device);
   MSP_TIMED(ctx, ST_CONVERT, launch_convert_rings(ctx->stream, g, K, rings, sigma_max, out));
+  return MSP_OK;
+}
+
+msp_status msp_prior_size(int64_t n_mesh_faces, int n, int64_t* n_verts, int64_t* n_faces) {
+  if (n_mesh_faces < 0 || n < 1 || n > 16 || !n_verts || !n_faces) return MSP_EINVAL;
+  const int64_t T = (int64_t)n * n;
+  if (n_mesh_faces > (int64_t(1) << 31) / (3 * T)) return MSP_EINVAL;
+  *n_faces = n_mesh_faces * T;
+  *n_verts = 3 * *n_faces;
+  if (*n_verts >= (int64_t(1) << 31)) return MSP_EINVAL;
+  return MSP_OK;
+}
+
+static bool prior_mesh_ok(const msp_mesh* m) {
+  return m && m->n_verts >= 0 && m->n_faces >= 0 && m->n_verts < (int64_t(1) << 31) &&
+         (m->n_faces == 0 || (m->pos && m->idx));
+}
+
+msp_status msp_prior_init(msp_ctx* ctx, const msp_mesh* m, int n, float shrink, float opacity0, const float* rgb0,
+                          float* logits, msp_faces* out) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!prior_mesh_ok(m) || !out || msp_prior_size(m->n_faces, n, &V, &F) != MSP_OK)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_init: bad mesh or n");
+  if (!(shrink > 0.f && shrink < 1.f) || !(opacity0 >= 0.f && opacity0 <= 1.f))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_init: shrink must be in (0, 1), opacity0 in [0, 1]");
+  if (out->n_verts != V || out->n_faces != F)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_init: output sizes differ from msp_prior_size");
+  if (out->sh) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_init: secondary triangles carry no SH");
+  if (F > 0 && (!logits || !out->pos || !out->opacity || !out->rgb || !out->idx || (!m->rgb && !rgb0)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_init: null array");
+  float c0[3] = {0.f, 0.f, 0.f};
+  if (rgb0) std::copy(rgb0, rgb0 + 3, c0);
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_CONVERT, launch_prior_init(ctx->stream, m, n, shrink, opacity0, c0, logits, out));
+  MSP_TIMED(ctx, ST_CONVERT, launch_prior_vertices(ctx->stream, m, n, logits, out->pos));
+  return MSP_OK;
+}
+
+msp_status msp_prior_vertices(msp_ctx* ctx, const msp_mesh* m, int n, const float* logits, float* pos) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!prior_mesh_ok(m) || msp_prior_size(m->n_faces, n, &V, &F) != MSP_OK)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_vertices: bad mesh or n");
+  if (V > 0 && (!logits || !pos)) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_vertices: null array");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_CONVERT, launch_prior_vertices(ctx->stream, m, n, logits, pos));
+  return MSP_OK;
+}
+
+msp_status msp_prior_backward(msp_ctx* ctx, const msp_mesh* m, int n, const float* logits, const float* dpos,
+                              float* dlogits) {
+  if (!ctx) return MSP_EINVAL;
+  int64_t V, F;
+  if (!prior_mesh_ok(m) || msp_prior_size(m->n_faces, n, &V, &F) != MSP_OK)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_backward: bad mesh or n");
+  if (V > 0 && (!logits || !dpos || !dlogits))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_prior_backward: null array");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_prior_backward(ctx->stream, m, n, logits, dpos, dlogits));
+  return MSP_OK;
+}
+
+static void bvh_release(msp_bvh* b) {
+  DevBuf* bufs[] = {&b->part, &b->boxes, &b->keys0, &b->keys1, &b->vals0, &b->vals1, &b->counts, &b->offs,
+                    &b->scan, &b->nodes, &b->leaves, &b->parent, &b->lparent, &b->flags, &b->err};
+  for (DevBuf* d : bufs) {
+    if (d->p) (void)hipFree(d->p);
+    d->p = nullptr;
+    d->bytes = 0;
+  }
+}
+
+msp_status msp_bvh_build(msp_ctx* ctx, const msp_faces* f, msp_bvh** out) {
+  if (!ctx) return MSP_EINVAL;
+  if (!f || !out || f->n_faces < 0 || f->n_verts < 0 || f->n_faces >= (int64_t(1) << 31))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_bvh_build: bad argument");
+  if (f->n_faces > 0 && (!f->pos || !f->opacity || !f->idx))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_bvh_build: null array");
+  DeviceGuard dg(ctx->device);
+  msp_bvh* b = new msp_bvh();
+  const int64_t F = f->n_faces;
+  const int64_t n = F > 0 ? F : 1;
+  const int64_t tiles = (n + 2047) / 2048;
+  int rc;
+  if ((rc = msp_ensure(ctx, b->part, 6 * 1024 * sizeof(float))) || (rc = msp_ensure(ctx, b->boxes, 16 * sizeof(float))) ||
+      (rc = msp_ensure(ctx, b->keys0, n * 4)) || (rc = msp_ensure(ctx, b->keys1, n * 4)) ||
+      (rc = msp_ensure(ctx, b->vals0, n * 4)) || (rc = msp_ensure(ctx, b->vals1, n * 4)) ||
+      (rc = msp_ensure(ctx, b->counts, 256 * tiles * 4)) || (rc = msp_ensure(ctx, b->offs, (256 * tiles + 1) * 8)) ||
+      (rc = msp_ensure(ctx, b->scan, scan_scratch_bytes(256 * tiles))) || (rc = msp_ensure(ctx, b->nodes, n * 64)) ||
+      (rc = msp_ensure(ctx, b->leaves, n * 64)) || (rc = msp_ensure(ctx, b->parent, n * 4)) ||
+      (rc = msp_ensure(ctx, b->lparent, n * 4)) || (rc = msp_ensure(ctx, b->flags, n * 4)) ||
+      (rc = msp_ensure(ctx, b->err, 256))) {
+    bvh_release(b);
+    delete b;
+    return (msp_status)rc;
+  }
+  b->n_leaves = F;
+  const BvhBufs v = b->view();
+  hipError_t e = launch_fill_u32(ctx->stream, v.err, 0u, 8);
+  if (e == hipSuccess) e = launch_bvh_build(ctx->stream, f, v);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(ctx->stream);
+    bvh_release(b);
+    delete b;
+    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("msp_bvh_build: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return MSP_OK;
+}
+
+msp_status msp_bvh_free(msp_ctx* ctx, msp_bvh* b) {
+  if (!ctx || !b) return MSP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  bvh_release(b);
+  delete b;
+  return MSP_OK;
+}
+
+msp_status msp_bvh_export(msp_ctx* ctx, const msp_bvh* b, float* nodes, float* leaves, float* root_box) {
+  if (!ctx) return MSP_EINVAL;
+  if (!b) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_bvh_export: null hierarchy");
+  DeviceGuard dg(ctx->device);
+  const BvhBufs v = b->view();
+  const int64_t n = b->n_leaves;
+  if (nodes && n > 1) MSP_HIP(ctx, hipMemcpyAsync(nodes, v.nodes, (n - 1) * 64, hipMemcpyDeviceToDevice, ctx->stream));
+  if (leaves && n > 0) MSP_HIP(ctx, hipMemcpyAsync(leaves, v.leaves, n * 64, hipMemcpyDeviceToDevice, ctx->stream));
+  if (root_box) MSP_HIP(ctx, hipMemcpyAsync(root_box, v.root_box, 24, hipMemcpyDeviceToDevice, ctx->stream));
+  return MSP_OK;
+}
+
+msp_status msp_bvh_status(msp_ctx* ctx, const msp_bvh* b, int64_t* n_leaves, int32_t* overflowed,
+                          int64_t* node_visits, int64_t* leaf_tests) {
+  if (!ctx) return MSP_EINVAL;
+  if (!b) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_bvh_status: null hierarchy");
+  DeviceGuard dg(ctx->device);
+  uint32_t w[6] = {0, 0, 0, 0, 0, 0};
+  MSP_HIP(ctx, hipMemcpyAsync(w, b->err.p, sizeof(w), hipMemcpyDeviceToHost, ctx->stream));
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (n_leaves) *n_leaves = b->n_leaves;
+  if (overflowed) *overflowed = w[0] ? 1 : 0;
+  uint64_t nn, nl;
+  std::memcpy(&nn, w + 2, 8);
+  std::memcpy(&nl, w + 4, 8);
+  if (node_visits) *node_visits = (int64_t)nn;
+  if (leaf_tests) *leaf_tests = (int64_t)nl;
+  return MSP_OK;
+}
+
+static bool rays_ok(const msp_rays* r) {
+  return r && r->n >= 0 && (r->n == 0 || (r->origin && r->dir && r->tmin && r->tmax));
+}
+
+msp_status msp_trace_transmittance(msp_ctx* ctx, const msp_bvh* b, const msp_rays* r, float t_eps, float* T) {
+  if (!ctx) return MSP_EINVAL;
+  if (!b || !rays_ok(r) || (r->n > 0 && !T) || !(t_eps >= 0.f))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_trace_transmittance: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_trace_transmittance(ctx->stream, b->view(), b->n_leaves, r, t_eps, T,
+                                                      (uint32_t*)b->err.p));
+  return MSP_OK;
+}
+
+msp_status msp_trace_closest(msp_ctx* ctx, const msp_bvh* b, const msp_rays* r, float alpha_min, float* t,
+                             int32_t* face, float* u, float* v) {
+  if (!ctx) return MSP_EINVAL;
+  if (!b || !rays_ok(r) || (r->n > 0 && (!t || !face)) || !std::isfinite(alpha_min))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_trace_closest: bad argument");
+  DeviceGuard dg(ctx->device);
+  MSP_TIMED(ctx, ST_OTHER, launch_trace_closest(ctx->stream, b->view(), b->n_leaves, r, alpha_min, t, face, u, v,
+                                                (uint32_t*)b->err.p));
   return MSP_OK;
 }
 

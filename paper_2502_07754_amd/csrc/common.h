@@ -68,6 +68,49 @@ struct msp_state {
   int64_t fp_parts = 0;          // entries of fp_part written by the last render
 };
 
+// device views of a bounding-volume hierarchy's buffers (trace.hip)
+struct BvhBufs {
+  float* part = nullptr;       // [blocks][6] partial centroid boxes
+  float* scene_box = nullptr;  // [6] centroid box (lo, hi)
+  float* root_box = nullptr;   // [6] box of all faces
+  uint32_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* counts = nullptr;  // [256][tiles] digit counts
+  int64_t* offs = nullptr;     // [256 tiles + 1] their exclusive scan
+  void* scan = nullptr;
+  float* nodes = nullptr;      // [n - 1][16]
+  float* leaves = nullptr;     // [n][16]
+  int32_t* parent = nullptr;   // [n - 1]
+  int32_t* lparent = nullptr;  // [n]
+  uint32_t* flags = nullptr;   // [n - 1] arrival counts of the bottom-up pass
+  uint32_t* err = nullptr;     // [1] traversal-stack overflow seen by a query
+};
+
+struct msp_bvh {
+  int64_t n_leaves = 0;
+  DevBuf part, boxes, keys0, keys1, vals0, vals1, counts, offs, scan, nodes, leaves, parent, lparent, flags, err;
+  BvhBufs view() const {
+    BvhBufs b;
+    b.part = (float*)part.p;
+    b.scene_box = (float*)boxes.p;
+    b.root_box = (float*)boxes.p + 8;
+    b.keys[0] = (uint32_t*)keys0.p;
+    b.keys[1] = (uint32_t*)keys1.p;
+    b.vals[0] = (uint32_t*)vals0.p;
+    b.vals[1] = (uint32_t*)vals1.p;
+    b.counts = (uint32_t*)counts.p;
+    b.offs = (int64_t*)offs.p;
+    b.scan = scan.p;
+    b.nodes = (float*)nodes.p;
+    b.leaves = (float*)leaves.p;
+    b.parent = (int32_t*)parent.p;
+    b.lparent = (int32_t*)lparent.p;
+    b.flags = (uint32_t*)flags.p;
+    b.err = (uint32_t*)err.p;
+    return b;
+  }
+};
+
 // ---- error helpers (host) ----
 int msp_fail(msp_ctx* ctx, int code, const std::string& msg);
 #define MSP_HIP(ctx, call)                                                            \
@@ -165,6 +208,16 @@ hipError_t launch_vec_mse(hipStream_t s, const float* y, const float* t, const f
 int refiner_alloc(msp_ctx* ctx, msp_refiner* r);
 int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N);
 void refiner_free_bufs(msp_refiner* r);
+hipError_t launch_prior_init(hipStream_t s, const msp_mesh* m, int n, float shrink, float op0, const float rgb0[3],
+                             float* logits, msp_faces* out);
+hipError_t launch_prior_vertices(hipStream_t s, const msp_mesh* m, int n, const float* logits, float* pos);
+hipError_t launch_prior_backward(hipStream_t s, const msp_mesh* m, int n, const float* logits, const float* dpos,
+                                 float* dlogits);
+hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b);
+hipError_t launch_trace_transmittance(hipStream_t s, const BvhBufs& b, int64_t n_leaves, const msp_rays* r,
+                                      float t_eps, float* T, uint32_t* err);
+hipError_t launch_trace_closest(hipStream_t s, const BvhBufs& b, int64_t n_leaves, const msp_rays* r, float alpha_min,
+                                float* t, int32_t* face, float* u, float* v, uint32_t* err);
 hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, const float* b1, const float* W2,
                                const float* b2, const float* W3, const float* b3);
 hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu);

@@ -13,8 +13,8 @@ from __future__ import annotations
 import dataclasses
 import math
 
-from . import (MSP_LOSS_MSE, RenderOptions, RenderState, adam_step, loss as msp_loss, prune as msp_prune, render,
-               render_backward)
+from . import (MSP_LOSS_MSE, RenderOptions, RenderState, adam_step, loss as msp_loss, prior_backward, prior_init,
+               prior_vertices, prune as msp_prune, render, render_backward)
 from . import _lib
 
 
@@ -103,3 +103,68 @@ class FineTuner:
             self.m[k] = torch.from_numpy(d[f"m_{k}"]).to(dev)
             self.v[k] = torch.from_numpy(d[f"v_{k}"]).to(dev)
         self.t = int(d["t"])
+
+
+@dataclasses.dataclass
+class PriorTuneConfig:
+    lr_color: float = 1e-2
+    lr_logits: float = math.exp(-3.0) * 1e-2   # the paper's position rate, exp(-3) lr_color
+    loss_kind: int = MSP_LOSS_MSE
+    lam: float = 0.6
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+
+class PriorTuner:
+    """Mesh-prior fine-tuning (mesh-prior section): secondary triangles on a
+    fixed geometry mesh, n^2 per mesh face, whose vertices are softmax-weighted
+    convex combinations of the face's corners. Each step sets the vertex
+    positions from the logits, renders all views, takes the loss, runs the
+    render adjoint, carries the position gradient to the logits, and applies
+    Adam to logits (lr_logits, by default the paper's position rate
+    exp(-3) lr_color), colours and opacities (lr_color; opacities
+    projected to [0, 1]). The number of triangles per mesh face stays fixed,
+    so there is no pruning."""
+
+    def __init__(self, mesh: dict, n: int, cams, targets, cfg: PriorTuneConfig | None = None,
+                 opts: RenderOptions | None = None, shrink: float = 0.05, opacity0: float = 0.5, init=None):
+        import torch
+        self.cfg = cfg or PriorTuneConfig()
+        self.opts = opts or RenderOptions()
+        self.mesh, self.n, self.cams, self.targets = mesh, n, cams, targets
+        if init is None:
+            self.faces, self.logits = prior_init(mesh, n, shrink, opacity0)
+        else:
+            self.faces, self.logits = ({k: (None if v is None else v.clone()) for k, v in init[0].items()},
+                                       init[1].clone())
+        self.dlogits = torch.empty_like(self.logits)
+        z = torch.zeros_like
+        self.m = dict(logits=z(self.logits), opacity=z(self.faces["opacity"]), rgb=z(self.faces["rgb"]))
+        self.v = dict(logits=z(self.logits), opacity=z(self.faces["opacity"]), rgb=z(self.faces["rgb"]))
+        self.t = 0
+        self.history = []
+        self.state = RenderState(_lib.Context.get(self.logits.device.index or 0))
+
+    def step(self):
+        """One epoch over all views. Returns the loss tensor."""
+        c = self.cfg
+        prior_vertices(self.mesh, self.n, self.logits, out=self.faces["pos"])
+        img, st = render(self.faces, self.cams, self.opts, state=self.state)
+        L, dimg = msp_loss(img, self.targets, c.loss_kind, c.lam)
+        g = render_backward(st, self.faces, dimg, need=("dpos", "dopacity", "drgb"))
+        prior_backward(self.mesh, self.n, self.logits, g["dpos"], out=self.dlogits)
+        self.t += 1
+        groups = [dict(param=self.logits, grad=self.dlogits, m=self.m["logits"], v=self.v["logits"], lr=c.lr_logits),
+                  dict(param=self.faces["rgb"], grad=g["drgb"], m=self.m["rgb"], v=self.v["rgb"], lr=c.lr_color),
+                  dict(param=self.faces["opacity"], grad=g["dopacity"], m=self.m["opacity"], v=self.v["opacity"],
+                       lr=c.lr_color, clamp=(0.0, 1.0))]
+        adam_step(groups, self.t, c.beta1, c.beta2, c.eps)
+        self.history.append(L)
+        return L
+
+    def mse(self) -> float:
+        prior_vertices(self.mesh, self.n, self.logits, out=self.faces["pos"])
+        img, _ = render(self.faces, self.cams, self.opts, state=self.state)
+        L, _ = msp_loss(img, self.targets, MSP_LOSS_MSE, want_grad=False)
+        return float(L.item())

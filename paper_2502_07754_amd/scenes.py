@@ -217,3 +217,24 @@ def icosphere(level: int, seed: int, radius: float = 1.0, bump: float = 0.1) -> 
     pos = p * r[:, None]
     rgb = 0.5 + 0.5 * np.sin(4.0 * p @ w.T + ph[1:])
     return Mesh(pos=_f32(pos.T), idx=np.ascontiguousarray(f.T.astype(np.int32)), rgb=_f32(rgb.T))
+
+
+# ---------------------------------------------------------------------------
+# Secondary rays (structure-of-arrays float32: origin [3][n], dir [3][n], t0 [n], t1 [n]).
+# ---------------------------------------------------------------------------
+
+def shadow_rays(n: int, seed: int, light=(0.0, 4.0, 0.0)):
+    """Segments from points drawn U(-1, 1)^3 (the scene's extent) to a point
+    light: dir = light - origin, t in (1e-4, 1)."""
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-1.0, 1.0, size=(3, n))
+    d = np.asarray(light, np.float64).reshape(3, 1) - o
+    return _f32(o), _f32(d), np.full(n, 1e-4, np.float32), np.ones(n, np.float32)
+
+
+def scatter_rays(n: int, seed: int):
+    """Incoherent rays: origins U(-1, 1)^3, directions N(0, 1)^3 (isotropic), t in (1e-4, inf)."""
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-1.0, 1.0, size=(3, n))
+    d = rng.normal(size=(3, n))
+    return _f32(o), _f32(d), np.full(n, 1e-4, np.float32), np.full(n, np.inf, np.float32)

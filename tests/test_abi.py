@@ -46,6 +46,17 @@ def test_version_and_sizing(libmsp_path):
     assert (nv.value, nf.value) == (70, 120)
 
 
+def test_prior_sizing(libmsp_path):
+    lib = _lib.load()
+    nv, nf = C.c_int64(), C.c_int64()
+    assert lib.msp_prior_size(327_680, 2, C.byref(nv), C.byref(nf)) == 0
+    assert (nv.value, nf.value) == (3 * 4 * 327_680, 4 * 327_680)
+    assert lib.msp_prior_size(0, 1, C.byref(nv), C.byref(nf)) == 0 and nv.value == 0
+    for Fm, n in [(-1, 1), (10, 0), (10, 17), (200_000_000, 2)]:
+        assert lib.msp_prior_size(Fm, n, C.byref(nv), C.byref(nf)) == -1
+    assert lib.msp_prior_init(None, None, 1, 0.05, 0.5, None, None, None) == -1
+
+
 def test_null_context_is_rejected(libmsp_path):
     lib = _lib.load()
     assert lib.msp_destroy(None) == -1
@@ -59,7 +70,8 @@ def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of every ABI struct, compiled with gcc against msp.h, equal the ctypes layouts."""
     structs = {"msp_gaussians": _lib.Gaussians, "msp_faces": _lib.Faces, "msp_camera": _lib.Camera,
                "msp_render_opts": _lib.RenderOpts, "msp_face_grads": _lib.FaceGrads,
-               "msp_render_stats": _lib.RenderStats}
+               "msp_render_stats": _lib.RenderStats, "msp_mesh": _lib.Mesh, "msp_adam_group": _lib.AdamGroup,
+               "msp_rays": _lib.Rays}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "msp.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
