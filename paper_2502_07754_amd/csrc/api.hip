@@ -815,7 +815,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
       (rc = msp_ensure(ctx, st->geo, 48 * V * F)) || (rc = msp_ensure(ctx, st->attr, 64 * F)) ||
       (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
       (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
-      (rc = msp_ensure(ctx, st->counters, 8 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))) ||
+      (rc = msp_ensure(ctx, st->counters, 32 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))) ||
       (rc = msp_ensure(ctx, st->fp_part, 8 * V * ((F + 255) / 256))))
     return (msp_status)rc;
   st->fp_parts = F > 0 ? V * ((F + 255) / 256) : 0;
@@ -828,7 +828,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   hipStream_t s = ctx->stream;
   if (!graph) MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->tile_cnt), 0u, NT));
-  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 16));
+  MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 64));
 
   if (opts->color_mode == MSP_COLOR_SH3) {
     if ((rc = msp_ensure(ctx, st->col4, 16 * V * F))) return (msp_status)rc;
@@ -924,7 +924,7 @@ static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f,
       MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
       a.dcol = P<float>(st->dcol);
     }
-    MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 4));
+    MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 16), 0u, 32));
     MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
     if (shm && grads->dsh)
       MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
@@ -955,8 +955,8 @@ static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f,
     MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
     a.dcol = P<float>(st->dcol);
   }
-  // reset the backward work queues (counters 3 and 4)
-  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 3), 0u, 4));
+  // reset the backward work queues (counters 16..31)
+  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 16), 0u, 32));
   MSP_TIMED(ctx, ST_BWD_LISTS, launch_bwd_lists(s, a, st->kbuf, ctx->n_cu));
   MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
   if (shm && grads->dsh)

@@ -157,8 +157,8 @@ struct RasterArgs {
   float bg0, bg1, bg2;
   float* img;              // [V][4][H][W]
   int32_t* nfrag;          // [V][H][W]
-  unsigned long long* counters;  // [0] fragments, [1] restarts, [2] fwd queue, [3] bwd list queue, [4] bwd grad queue,
-                                 // [5] overflow flag
+  unsigned long long* counters;  // [0] fragments, [1] restarts, [5] overflow flag, [8..15] composite queues,
+                                 // [16..23] backward list queues, [24..31] backward gradient queues
   uint32_t* ovf;           // overflow flag (low word of counters[5]); set: kernels of the step return at once
   unsigned long long* fp_part;  // [views][setup workgroups] footprint pixels per setup workgroup (statistics)
   // backward

@@ -614,6 +614,32 @@ __device__ __forceinline__ bool decode_item(const RasterArgs& a, uint32_t item, 
 }
 
 
+// XCD-aware work queues. The chip runs workgroups on eight XCDs, each with its
+// own L2, and hands consecutive workgroups to the XCDs in turn. Work is split
+// into eight queues by a spatial group g (queue g mod 8); a workgroup starts
+// at queue blockIdx.x mod 8, so the items of one group (the blocks of one
+// tile, which read the same tile list and face records) run on one XCD and
+// share its L2. A workgroup whose queue is empty moves on to the next one, so
+// the load stays balanced; placement affects speed only, never results.
+// q8: eight counters; per_group items per group, n_groups groups; returns the
+// item index group * per_group + k (k < per_group) or false when all are done.
+__device__ __forceinline__ bool take_item(unsigned long long* q8, int64_t n_groups, uint32_t per_group, uint32_t home,
+                                          uint32_t& qi, int lane, uint32_t& item) {
+  while (qi < 8) {
+    const uint32_t q = (home + qi) & 7u;
+    const int64_t nq = (int64_t)q < n_groups ? ((n_groups - q + 7) / 8) * per_group : 0;
+    uint32_t k = 0;
+    if (lane == 0) k = (uint32_t)atomicAdd(&q8[q], 1ull);
+    k = __shfl(k, 0);
+    if ((int64_t)k < nq) {
+      item = (uint32_t)(((int64_t)q + 8 * (int64_t)(k / per_group)) * per_group + k % per_group);
+      return true;
+    }
+    ++qi;
+  }
+  return false;
+}
+
 // Per-lane ordering buffer in registers: up to KB fragments sorted by key
 // (depth bits, face id), with alpha and (COL) the interpolated colour.
 // Insertion is a compare-select network, popping a shift.
@@ -887,10 +913,11 @@ __global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_item
   uint64_t frags = 0;
   uint32_t restarts = 0;
   if (*a.ovf & 3u) return;
+  const uint32_t bpt = (uint32_t)((a.tile_w / 8) * (a.tile_h / 8));
+  uint32_t qi = 0;
   for (;;) {
     uint32_t item = 0;
-    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[2], 1ull);
-    item = __shfl(item, 0);
+    if (!take_item(a.counters + 8, a.n_tiles * a.n_views, bpt, blockIdx.x & 7u, qi, lane, item)) break;
     if (item >= n_items) break;
     Item it;
     if (!decode_item(a, item, it)) continue;
@@ -950,10 +977,11 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
   RegBuf<KB, false> kb;  // lists record face ids and transmittance only
   uint32_t restarts = 0;
   if (*a.ovf & 3u) return;
+  const uint32_t bpt = (uint32_t)((a.tile_w / 8) * (a.tile_h / 8));
+  uint32_t qi = 0;
   for (;;) {
     uint32_t item = 0;
-    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[3], 1ull);
-    item = __shfl(item, 0);
+    if (!take_item(a.counters + 16, a.n_tiles * a.n_views, bpt, blockIdx.x & 7u, qi, lane, item)) break;
     if (item >= n_items) break;
     Item it;
     if (!decode_item(a, item, it)) continue;
@@ -1174,15 +1202,19 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   if (*a.ovf & (a.store_rows ? 7u : 3u)) return;
   const int nbx = (a.W + 7) / 8, nby = (a.H + 7) / 8;
   const int nrx = (nbx + 1) / 2, nry = (nby + 1) / 2;
+  // queue groups: 4x4 regions (64x64 pixels) of one view, whose regions share face records
+  const int nsx = (nrx + 3) / 4, nsy = (nry + 3) / 4;
+  const int64_t n_groups = (int64_t)nsx * nsy * a.n_views;
+  uint32_t qi = 0;
   for (;;) {
     // work item: a 2x2 group of 8x8 blocks of one view; the tables persist over the group
     uint32_t item = 0;
-    if (lane == 0) item = (uint32_t)atomicAdd(&a.counters[4], 1ull);
-    item = __shfl(item, 0);
-    if (item >= n_items) break;
-    const int view = (int)(item / ((uint32_t)nrx * nry));
-    const int rr = (int)(item - (uint32_t)view * nrx * nry);
-    const int rx = rr % nrx, ry = rr / nrx;
+    if (!take_item(a.counters + 24, n_groups, 16u, blockIdx.x & 7u, qi, lane, item)) break;
+    const uint32_t grp = item / 16u, sub16 = item % 16u;
+    const int view = (int)(grp / ((uint32_t)nsx * nsy));
+    const int gr = (int)(grp - (uint32_t)view * nsx * nsy);
+    const int rx = (gr % nsx) * 4 + (int)(sub16 & 3u), ry = (gr / nsx) * 4 + (int)(sub16 >> 2);
+    if (view >= a.n_views || rx >= nrx || ry >= nry) continue;
     const msp_camera c = a.cams[view];
     // world-to-camera rotation in registers: the flushes' global atomics could
     // otherwise alias it and force a reload (and a wait) after every atomic
