@@ -4,7 +4,9 @@
 Workload (the batched-render configuration): 500,000 flat Gaussians (means
 U[-1,1]^3, two scales log-U[0.01, 0.1], third 0, uniform rotations, opacity
 sigmoid(N(0,1)), colours from degree-3 SH with coefficients N(0, 0.1^2)),
-converted to K = 16 fans at sigma = 2 (8,000,000 triangles), rendered from
+converted to K = 16 fans at sigma = 2 (8,000,000 triangles; the faces are laid
+out along the Morton curve of the Gaussian means, msp_spatial_order, unless
+--input-order), rendered from
 eight 1920x1080 views on a ring of radius 3, forward and backward with a fixed
 upstream gradient dL/dimage = 1e-3 N(0, 1) (seed 3).
 
@@ -226,6 +228,8 @@ def main():
     ap.add_argument("--prior-n", type=int, default=2, help="secondary triangles per mesh face: n^2")
     ap.add_argument("--fan3", action="store_true",
                     help="convert with three fans per Gaussian (3D-Gaussian conversion) instead of one")
+    ap.add_argument("--input-order", action="store_true",
+                    help="convert the Gaussians in their drawn order instead of the spatial (Morton) order")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device-to-device copy of this many GiB (bandwidth and "
                          "HBM-counter calibration) and exit")
@@ -267,7 +271,9 @@ def main():
         dlogits = torch.empty_like(logits)
         cm = msp.MSP_COLOR_RGB
     else:
-        faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT)
+        # the same scene with its faces laid out along the Morton curve of the Gaussian means
+        order = None if args.input_order else msp.spatial_order(gg)
+        faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT, order=order)
         cm = msp.MSP_COLOR_SH3
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
@@ -382,6 +388,7 @@ def main():
         "config": {"workload": workload, "views": args.views, "width": W, "height": H,
                    "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
                    "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
+                   "face_order": "input" if (args.input_order or mesh is not None) else "morton",
                    "entries_per_step": entries, "fragments_per_step": frags,
                    "fragments_per_s": frags / dt},
         "roofline": roof,

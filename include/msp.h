@@ -159,6 +159,23 @@ msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_
 msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul,
                        int mode, msp_faces* out);
 
+/* A spatially coherent order of the Gaussians: order [n] (DEVICE int32) lists
+ * them by the 30-bit Morton code of their means within the means' bounding
+ * box (stable, so equal codes keep index order). Not in the paper: a layout
+ * choice. Faces converted in this order (msp_convert_ordered) keep the faces
+ * of nearby Gaussians at nearby ids, so binning writes its tile-list keys in
+ * runs and neighbouring faces share cache lines. Synchronises. EINVAL: NULL
+ * arguments with n > 0, n >= 2^31. */
+msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* order);
+/* msp_convert with the output blocks permuted: the faces and vertices of
+ * output block i (the i-th group of K faces and K + 1 vertices, or 3K faces
+ * and 7 + 3 (K - 4) vertices for MSP_FAN_3D) are those of Gaussian order[i],
+ * and out->gid holds order[i] (so gid still names the source Gaussian).
+ * order == NULL is msp_convert. An order entry outside [0, n) gives that
+ * block NaN positions, zero opacity and colour and gid -1. */
+msp_status msp_convert_ordered(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, int mode,
+                               const int32_t* order, msp_faces* out);
+
 /* ---- rendering ---------------------------------------------------------- */
 
 msp_status msp_state_create(msp_ctx* ctx, msp_state** out);

@@ -21,7 +21,7 @@ __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
            "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_weights",
            "refiner_apply_backward", "refiner_loss", "MSP_FAN_FLAT", "MSP_FAN_3D", "prior_init", "prior_vertices",
-           "prior_backward", "Bvh"]
+           "prior_backward", "Bvh", "spatial_order"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -54,10 +54,26 @@ def _ctx(t):
     return _lib.Context.get(t.device.index if t.device.index is not None else 0)
 
 
-def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2, mode: int = 0) -> dict:
+def spatial_order(g: dict):
+    """msp_spatial_order: int32 [N] order of the Gaussians along the Morton curve of their means."""
+    import torch
+    mean = _need(g["mean"], torch.float32, "mean")
+    if mean.dim() != 2 or mean.shape[0] != 3:
+        raise ValueError("mean must be [3][N]")
+    ctx = _ctx(mean)
+    ctx.bind_stream()
+    order = torch.empty((mean.shape[1],), dtype=torch.int32, device=mean.device)
+    G = _lib.Gaussians(mean.shape[1], _dev_ptr(mean), None, None, None, None, None)
+    ctx.check(ctx.lib.msp_spatial_order(ctx.h, C.byref(G), _dev_ptr(order)), "msp_spatial_order")
+    return order
+
+
+def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2, mode: int = 0, order=None) -> dict:
     """Gaussian -> triangle fans (msp_convert). `g` holds GPU float32 tensors
     mean [3,N], scale [3,N], quat [4,N], opacity [N], rgb [3,N] and optionally sh [48,N].
-    mode MSP_FAN_FLAT (one fan over the two largest axes) or MSP_FAN_3D (three fans)."""
+    mode MSP_FAN_FLAT (one fan over the two largest axes) or MSP_FAN_3D (three fans).
+    With `order` (int32 [N], e.g. from spatial_order) output block i is converted
+    from Gaussian order[i] and gid records it (msp_convert_ordered)."""
     import torch
     mean = _need(g["mean"], torch.float32, "mean")
     ctx = _ctx(mean)
@@ -79,8 +95,15 @@ def convert(g: dict, K: int, sigma: float, opac_mul: float = 0.2, mode: int = 0)
                        _dev_ptr(_need(g["rgb"], torch.float32, "rgb")),
                        None if sh is None else _dev_ptr(_need(sh, torch.float32, "sh")))
     Fc = _faces_struct(out)
-    ctx.check(ctx.lib.msp_convert(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), int(mode), C.byref(Fc)),
-              "msp_convert")
+    if order is None:
+        ctx.check(ctx.lib.msp_convert(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), int(mode), C.byref(Fc)),
+                  "msp_convert")
+    else:
+        _need(order, torch.int32, "order")
+        if order.numel() != n:
+            raise ValueError(f"order must have {n} entries")
+        ctx.check(ctx.lib.msp_convert_ordered(ctx.h, C.byref(G), K, float(sigma), float(opac_mul), int(mode),
+                                              _dev_ptr(order), C.byref(Fc)), "msp_convert_ordered")
     return out
 
 

@@ -100,6 +100,9 @@ EXPORTS = {
                                  C.POINTER(Faces)]),
     "msp_prior_vertices": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p]),
     "msp_prior_backward": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "msp_spatial_order": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_void_p]),
+    "msp_convert_ordered": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float, C.c_int,
+                                      C.c_void_p, C.POINTER(Faces)]),
     "msp_bvh_build": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(C.c_void_p)]),
     "msp_bvh_free": (C.c_int, [C.c_void_p, C.c_void_p]),
     "msp_bvh_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

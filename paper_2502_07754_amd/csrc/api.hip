@@ -232,6 +232,11 @@ msp_status msp_convert_size(int64_t n, int K, int mode, int64_t* n_verts, int64_
 
 msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, int mode,
                        msp_faces* out) {
+  return msp_convert_ordered(ctx, g, K, sigma, opac_mul, mode, nullptr, out);
+}
+
+msp_status msp_convert_ordered(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma, float opac_mul, int mode,
+                               const int32_t* order, msp_faces* out) {
   if (!ctx) return MSP_EINVAL;
   if (!g || !out) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_convert: null argument");
   int64_t V, F;
@@ -255,9 +260,9 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
     cs[K + k] = (float)std::sin(th);
   }
   if (mode == MSP_FAN_3D)
-    MSP_TIMED(ctx, ST_CONVERT, launch_convert_three(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+    MSP_TIMED(ctx, ST_CONVERT, launch_convert_three(ctx->stream, g, K, sigma, opac_mul, cs.data(), order, out));
   else
-    MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+    MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), order, out));
   return MSP_OK;
 }
 
@@ -523,6 +528,31 @@ msp_status msp_bvh_status(msp_ctx* ctx, const msp_bvh* b, int64_t* n_leaves, int
   return MSP_OK;
 }
 
+msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* order) {
+  if (!ctx) return MSP_EINVAL;
+  if (!g || g->n < 0 || g->n >= (int64_t(1) << 31) || (g->n > 0 && (!g->mean || !order)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_spatial_order: bad argument");
+  if (g->n == 0) return MSP_OK;
+  DeviceGuard dg(ctx->device);
+  const int64_t n = g->n, tiles = (n + 2047) / 2048;
+  msp_bvh tmp;  // scratch of the same shape as a hierarchy build's sort, freed below
+  int rc;
+  if ((rc = msp_ensure(ctx, tmp.part, 6 * 1024 * sizeof(float))) || (rc = msp_ensure(ctx, tmp.boxes, 16 * sizeof(float))) ||
+      (rc = msp_ensure(ctx, tmp.keys0, n * 4)) || (rc = msp_ensure(ctx, tmp.keys1, n * 4)) ||
+      (rc = msp_ensure(ctx, tmp.vals1, n * 4)) || (rc = msp_ensure(ctx, tmp.counts, 256 * tiles * 4)) ||
+      (rc = msp_ensure(ctx, tmp.offs, (256 * tiles + 1) * 8)) ||
+      (rc = msp_ensure(ctx, tmp.scan, scan_scratch_bytes(256 * tiles)))) {
+    bvh_release(&tmp);
+    return (msp_status)rc;
+  }
+  hipError_t e = launch_spatial_order(ctx->stream, g->mean, n, tmp.view(), order);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  bvh_release(&tmp);
+  if (e != hipSuccess)
+    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("msp_spatial_order: ") + hipGetErrorString(e));
+  return MSP_OK;
+}
+
 static bool rays_ok(const msp_rays* r) {
   return r && r->n >= 0 && (r->n == 0 || (r->origin && r->dir && r->tmin && r->tmax));
 }
@@ -630,7 +660,7 @@ msp_status msp_refiner_apply(msp_ctx* ctx, const msp_gaussians* g, int K, float 
     cs[k] = (float)std::cos(-pi + 2.0 * pi * k / K);
     cs[K + k] = (float)std::sin(-pi + 2.0 * pi * k / K);
   }
-  MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), out));
+  MSP_TIMED(ctx, ST_CONVERT, launch_convert_flat(ctx->stream, g, K, sigma, opac_mul, cs.data(), nullptr, out));
   MSP_TIMED(ctx, ST_CONVERT, launch_refiner_apply(ctx->stream, g, K, sigma, opac_mul, y, 3 * K + 4, out));
   return MSP_OK;
 }

@@ -127,9 +127,10 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n);
 hipError_t launch_fill_f32(hipStream_t s, float* p, float v, int64_t n);
 
 hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
-                               const float* cos_sin, msp_faces* out);
+                               const float* cos_sin, const int32_t* order, msp_faces* out);
 hipError_t launch_convert_three(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
-                                const float* cos_sin, msp_faces* out);
+                                const float* cos_sin, const int32_t* order, msp_faces* out);
+hipError_t launch_spatial_order(hipStream_t s, const float* mean, int64_t n, const BvhBufs& b, int32_t* order);
 
 // exclusive scan of n uint32 values into n+1 int64 offsets (last = total); scratch sized by scan_scratch_bytes
 size_t scan_scratch_bytes(int64_t n);

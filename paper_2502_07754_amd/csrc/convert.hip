@@ -30,6 +30,14 @@ __device__ inline void rot_column(float w, float x, float y, float z, int col, f
   }
 }
 
+// Gaussian behind output block g: order[g] when an order is given (an index
+// outside [0, n) gives -1: NaN positions, zero opacity and colour, gid -1).
+__device__ __forceinline__ int64_t source_of(const int32_t* __restrict__ order, int64_t g, int64_t n) {
+  if (!order) return g;
+  const int32_t o = order[g];
+  return (o >= 0 && (int64_t)o < n) ? (int64_t)o : -1;
+}
+
 // The fan spans the two largest scales (ties to the lower index), in index order.
 __device__ inline void pick_axes(float s0, float s1, float s2, int& a, int& b) {
   int drop;
@@ -40,16 +48,28 @@ __device__ inline void pick_axes(float s0, float s1, float s2, int& a, int& b) {
   b = drop == 2 ? 1 : 2;
 }
 
+__device__ __forceinline__ void invalid_vertex(float* pos, float* vop, float* vrgb, int64_t V, int64_t v) {
+  const float nan = __int_as_float(0x7fc00000);
+  pos[v] = pos[V + v] = pos[2 * V + v] = nan;
+  vop[v] = 0.f;
+  vrgb[v] = vrgb[V + v] = vrgb[2 * V + v] = 0.f;
+}
+
 __global__ void k_convert_vertices(const float* __restrict__ mean, const float* __restrict__ scale,
                                    const float* __restrict__ quat, const float* __restrict__ opacity,
                                    const float* __restrict__ rgb, int64_t n, int K, float sigma,
-                                   float opac_mul, CosSin cs, float* __restrict__ pos,
-                                   float* __restrict__ vop, float* __restrict__ vrgb) {
+                                   float opac_mul, CosSin cs, const int32_t* __restrict__ order,
+                                   float* __restrict__ pos, float* __restrict__ vop, float* __restrict__ vrgb) {
   const int64_t V = n * (K + 1);
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const int64_t g = v / (K + 1);
-  const int j = (int)(v - g * (K + 1));
+  const int64_t blk = v / (K + 1);
+  const int j = (int)(v - blk * (K + 1));
+  const int64_t g = source_of(order, blk, n);
+  if (g < 0) {
+    invalid_vertex(pos, vop, vrgb, V, v);
+    return;
+  }
   const float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
   float px = mx, py = my, pz = mz;
   const float o = opacity[g];
@@ -76,21 +96,22 @@ __global__ void k_convert_vertices(const float* __restrict__ mean, const float* 
   vrgb[2 * V + v] = rgb[2 * n + g];
 }
 
-__global__ void k_convert_faces(int64_t n, int K, const float* __restrict__ sh, int32_t* __restrict__ idx,
-                                int32_t* __restrict__ gid, float* __restrict__ fsh) {
+__global__ void k_convert_faces(int64_t n, int K, const float* __restrict__ sh, const int32_t* __restrict__ order,
+                                int32_t* __restrict__ idx, int32_t* __restrict__ gid, float* __restrict__ fsh) {
   const int64_t F = n * K;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
-  const int64_t g = f / K;
-  const int k = (int)(f - g * K);
-  const int32_t c = (int32_t)(g * (K + 1));
+  const int64_t blk = f / K;
+  const int k = (int)(f - blk * K);
+  const int32_t c = (int32_t)(blk * (K + 1));
   idx[f] = c;
   idx[F + f] = c + 1 + k;
   idx[2 * F + f] = c + 1 + (k + 1) % K;
+  const int64_t g = source_of(order, blk, n);
   if (gid) gid[f] = (int32_t)g;
   if (sh && fsh) {
 #pragma unroll 4
-    for (int r = 0; r < 48; ++r) fsh[r * F + f] = sh[r * n + g];
+    for (int r = 0; r < 48; ++r) fsh[r * F + f] = g >= 0 ? sh[r * n + g] : 0.f;
   }
 }
 
@@ -108,14 +129,19 @@ __device__ __forceinline__ void plane_axes(int p, int& i, int& j) {
 __global__ void k_convert3_vertices(const float* __restrict__ mean, const float* __restrict__ scale,
                                     const float* __restrict__ quat, const float* __restrict__ opacity,
                                     const float* __restrict__ rgb, int64_t n, int K, float sigma,
-                                    float opac_mul, CosSin cs, float* __restrict__ pos,
-                                    float* __restrict__ vop, float* __restrict__ vrgb) {
+                                    float opac_mul, CosSin cs, const int32_t* __restrict__ order,
+                                    float* __restrict__ pos, float* __restrict__ vop, float* __restrict__ vrgb) {
   const int per = 7 + 3 * (K - 4);
   const int64_t V = n * per;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const int64_t g = v / per;
-  const int j = (int)(v - g * per);
+  const int64_t blk = v / per;
+  const int j = (int)(v - blk * per);
+  const int64_t g = source_of(order, blk, n);
+  if (g < 0) {
+    invalid_vertex(pos, vop, vrgb, V, v);
+    return;
+  }
   const float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
   float px = mx, py = my, pz = mz;
   const float o = opacity[g];
@@ -168,22 +194,23 @@ __device__ __forceinline__ int32_t ring3(int32_t base, int p, int k, int K) {
   return base + 7 + p * (K - 4) + (k - k / q4 - 1);
 }
 
-__global__ void k_convert3_faces(int64_t n, int K, const float* __restrict__ sh, int32_t* __restrict__ idx,
-                                 int32_t* __restrict__ gid, float* __restrict__ fsh) {
+__global__ void k_convert3_faces(int64_t n, int K, const float* __restrict__ sh, const int32_t* __restrict__ order,
+                                 int32_t* __restrict__ idx, int32_t* __restrict__ gid, float* __restrict__ fsh) {
   const int64_t F = n * 3 * K;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
-  const int64_t g = f / (3 * K);
-  const int rem = (int)(f - g * 3 * K);
+  const int64_t blk = f / (3 * K);
+  const int rem = (int)(f - blk * 3 * K);
   const int p = rem / K, k = rem - p * K;
-  const int32_t base = (int32_t)(g * (7 + 3 * (K - 4)));
+  const int32_t base = (int32_t)(blk * (7 + 3 * (K - 4)));
   idx[f] = base;
   idx[F + f] = ring3(base, p, k, K);
   idx[2 * F + f] = ring3(base, p, (k + 1) % K, K);
+  const int64_t g = source_of(order, blk, n);
   if (gid) gid[f] = (int32_t)g;
   if (sh && fsh) {
 #pragma unroll 4
-    for (int r = 0; r < 48; ++r) fsh[r * F + f] = sh[r * n + g];
+    for (int r = 0; r < 48; ++r) fsh[r * F + f] = g >= 0 ? sh[r * n + g] : 0.f;
   }
 }
 
@@ -221,7 +248,7 @@ hipError_t launch_fill_f32(hipStream_t s, float* p, float v, int64_t n) {
 }
 
 hipError_t launch_convert_three(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
-                                const float* cos_sin, msp_faces* out) {
+                                const float* cos_sin, const int32_t* order, msp_faces* out) {
   if (g->n == 0) return hipSuccess;
   CosSin cs;
   for (int k = 0; k < kMaxK; ++k) {
@@ -230,16 +257,16 @@ hipError_t launch_convert_three(hipStream_t s, const msp_gaussians* g, int K, fl
   }
   const int64_t V = g->n * (7 + 3 * (K - 4)), F = g->n * 3 * K;
   hipLaunchKernelGGL(k_convert3_vertices, dim3(grid_for(V, 256)), dim3(256), 0, s, g->mean, g->scale, g->quat,
-                     g->opacity, g->rgb, g->n, K, sigma, opac_mul, cs, out->pos, out->opacity, out->rgb);
+                     g->opacity, g->rgb, g->n, K, sigma, opac_mul, cs, order, out->pos, out->opacity, out->rgb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_convert3_faces, dim3(grid_for(F, 256)), dim3(256), 0, s, g->n, K, g->sh, out->idx, out->gid,
-                     out->sh);
+  hipLaunchKernelGGL(k_convert3_faces, dim3(grid_for(F, 256)), dim3(256), 0, s, g->n, K, g->sh, order, out->idx,
+                     out->gid, out->sh);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
-                               const float* cos_sin, msp_faces* out) {
+                               const float* cos_sin, const int32_t* order, msp_faces* out) {
   if (g->n == 0) return hipSuccess;
   CosSin cs;
   for (int k = 0; k < kMaxK; ++k) {
@@ -248,10 +275,10 @@ hipError_t launch_convert_flat(hipStream_t s, const msp_gaussians* g, int K, flo
   }
   const int64_t V = g->n * (K + 1), F = g->n * K;
   hipLaunchKernelGGL(k_convert_vertices, dim3(grid_for(V, 256)), dim3(256), 0, s, g->mean, g->scale, g->quat,
-                     g->opacity, g->rgb, g->n, K, sigma, opac_mul, cs, out->pos, out->opacity, out->rgb);
+                     g->opacity, g->rgb, g->n, K, sigma, opac_mul, cs, order, out->pos, out->opacity, out->rgb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_convert_faces, dim3(grid_for(F, 256)), dim3(256), 0, s, g->n, K, g->sh, out->idx, out->gid,
-                     out->sh);
+  hipLaunchKernelGGL(k_convert_faces, dim3(grid_for(F, 256)), dim3(256), 0, s, g->n, K, g->sh, order, out->idx,
+                     out->gid, out->sh);
   return hipGetLastError();
 }

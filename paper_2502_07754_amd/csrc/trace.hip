@@ -61,14 +61,32 @@ __device__ __forceinline__ float wave_max(float x) {
   return x;
 }
 
-// per block: min and max of the centroids (NaN centroids are ignored by fminf / fmaxf)
-__global__ __launch_bounds__(256) void k_box_partial(const float* __restrict__ pos, const int32_t* __restrict__ idx,
-                                                     int64_t V, int64_t F, float* __restrict__ part) {
+// the points a hierarchy or an order is built over: face centroids, or Gaussian means
+struct FaceCentroids {
+  const float* pos;
+  const int32_t* idx;
+  int64_t V, F;
+  __device__ __forceinline__ void get(int64_t f, float c[3]) const { centroid(pos, idx, V, F, f, c); }
+};
+
+struct Points {
+  const float* p;  // [3][n]
+  int64_t n;
+  __device__ __forceinline__ void get(int64_t i, float c[3]) const {
+    c[0] = p[i];
+    c[1] = p[n + i];
+    c[2] = p[2 * n + i];
+  }
+};
+
+// per block: min and max of the points (NaN points are ignored by fminf / fmaxf)
+template <class Src>
+__global__ __launch_bounds__(256) void k_box_partial(Src src, int64_t F, float* __restrict__ part) {
   __shared__ float red[4][6];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t f = blockIdx.x * 256ll + threadIdx.x; f < F; f += (int64_t)gridDim.x * 256) {
     float c[3];
-    centroid(pos, idx, V, F, f, c);
+    src.get(f, c);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = fminf(lo[d], c[d]);
@@ -148,13 +166,13 @@ __device__ __forceinline__ uint32_t quant10(float c, float lo, float hi) {
   return (uint32_t)fminf(x * 1024.f, 1023.f);
 }
 
-__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pos, const int32_t* __restrict__ idx,
-                                                int64_t V, int64_t F, const float* __restrict__ box,
+template <class Src>
+__global__ __launch_bounds__(256) void k_morton(Src src, int64_t F, const float* __restrict__ box,
                                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const float lo0 = box[0], lo1 = box[1], lo2 = box[2], hi0 = box[3], hi1 = box[4], hi2 = box[5];
   for (int64_t f = blockIdx.x * 256ll + threadIdx.x; f < F; f += (int64_t)gridDim.x * 256) {
     float c[3];
-    centroid(pos, idx, V, F, f, c);
+    src.get(f, c);
     keys[f] = (spread10(quant10(c[0], lo0, hi0)) << 2) | (spread10(quant10(c[1], lo1, hi1)) << 1) |
               spread10(quant10(c[2], lo2, hi2));
     vals[f] = (uint32_t)f;
@@ -569,19 +587,19 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_closest(const float4* _
   count_visits(n_nodes, n_leaf, err);
 }
 
-}  // namespace
 
-hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b) {
-  const int64_t F = f->n_faces, V = f->n_verts;
-  if (F == 0) return hipSuccess;
+// Morton codes of the points in their own box, then the stable radix sort:
+// codes and point indices sorted in keys[0] / vals[0] (four passes)
+template <class Src>
+hipError_t morton_sort(hipStream_t s, Src src, int64_t F, const BvhBufs& b, uint32_t* vals0) {
   const unsigned gb = grid_for(F, 256) > 1024 ? 1024 : grid_for(F, 256);
-  hipLaunchKernelGGL(k_box_partial, dim3(gb), dim3(256), 0, s, f->pos, f->idx, V, F, b.part);
+  hipLaunchKernelGGL(k_box_partial<Src>, dim3(gb), dim3(256), 0, s, src, F, b.part);
   hipLaunchKernelGGL(k_box_final, dim3(1), dim3(256), 0, s, b.part, (int)gb, b.scene_box);
-  hipLaunchKernelGGL(k_morton, dim3(grid_for(F, 256)), dim3(256), 0, s, f->pos, f->idx, V, F, b.scene_box, b.keys[0],
-                     b.vals[0]);
+  hipLaunchKernelGGL(k_morton<Src>, dim3(grid_for(F, 256)), dim3(256), 0, s, src, F, b.scene_box, b.keys[0], vals0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nblk = (F + kRsTile - 1) / kRsTile;
+  uint32_t* vals[2] = {vals0, b.vals[1]};
   int cur = 0;
   for (int shift = 0; shift < 32; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, b.keys[cur], F, shift, b.counts, nblk);
@@ -589,12 +607,28 @@ hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b)
     if (e != hipSuccess) return e;
     e = launch_scan_u32(s, b.counts, b.offs, 256 * nblk, b.scan);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, b.keys[cur], b.vals[cur],
-                       b.keys[cur ^ 1], b.vals[cur ^ 1], F, shift, b.offs, nblk);
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, b.keys[cur], vals[cur],
+                       b.keys[cur ^ 1], vals[cur ^ 1], F, shift, b.offs, nblk);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
   }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_spatial_order(hipStream_t s, const float* mean, int64_t n, const BvhBufs& b, int32_t* order) {
+  if (n == 0) return hipSuccess;
+  return morton_sort(s, Points{mean, n}, n, b, reinterpret_cast<uint32_t*>(order));
+}
+
+hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b) {
+  const int64_t F = f->n_faces, V = f->n_verts;
+  if (F == 0) return hipSuccess;
+  hipError_t e = morton_sort(s, FaceCentroids{f->pos, f->idx, V, F}, F, b, b.vals[0]);
+  if (e != hipSuccess) return e;
+  const int cur = 0;
   // four passes: the sorted codes and face ids are back in buffer 0
   hipLaunchKernelGGL(k_leaves, dim3(grid_for(F, 256)), dim3(256), 0, s, f->pos, f->opacity, f->idx, V, F,
                      b.vals[cur], (float4*)b.leaves);
