@@ -307,8 +307,8 @@ __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
 // chunk are chunk-sorted, then merged pairwise through global memory, one
 // chunk of output at a time (split found by a cooperative search, both input
 // ranges staged in LDS).
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 32;
+constexpr int kSortThreads = 512;
+constexpr int kSortItems = 16;
 constexpr int kSortChunk = kSortThreads * kSortItems;  // 8192 keys, 64 KiB (+ padding) of LDS
 constexpr uint64_t kSentinel = ~0ull;                 // above every key (float bits of a finite z)
 
@@ -905,7 +905,7 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
 }
 
 template <int KB, bool SHP>
-__global__ __launch_bounds__(256) void k_composite(RasterArgs a, uint32_t n_items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_composite(RasterArgs a, uint32_t n_items) {
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
