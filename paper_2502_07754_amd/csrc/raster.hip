@@ -47,9 +47,11 @@ constexpr float kMargin = 0.00390625f;  // 2^-8 pixel
 constexpr int kRec = 28;                // floats per staged face record
 constexpr int kWavesPerWG = 4;
 constexpr int kHashSlots = 128;         // per-wave gradient table
+constexpr int kHashBits = 7;            // log2(kHashSlots)
 constexpr int kHashFill = 64;           // flushed once it holds more faces than this (short probe chains)
 constexpr int kHashProbes = 16;
 static_assert(kHashSlots >= 2 * MSP_WAVE, "a flushed table must hold one row's faces after a full table");
+static_assert((1 << kHashBits) == kHashSlots, "slot bits");
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 enum : int { DONE = 0, ACTIVE = 1, RESTART = 2 };
@@ -1004,8 +1006,8 @@ struct GradLayout {
   static constexpr int POS = SH ? 6 : 12;
   // per-vertex entry: dop | (RGB: drgb[3]) | dpos world[3]
   static constexpr int VW = SH ? 4 : 7;
-  static constexpr int VSLOTS = SH ? 512 : 256;
-  static constexpr int VBITS = SH ? 9 : 8;
+  static constexpr int VSLOTS = 256;
+  static constexpr int VBITS = 8;
   static constexpr int VFILL = VSLOTS * 3 / 4;
 };
 
@@ -1178,7 +1180,6 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   __shared__ uint32_t hkeys[kWavesPerWG][kHashSlots];
   __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];  // [slot][value]: one face's values side by side
   __shared__ uint32_t hfill[kWavesPerWG];
-  __shared__ uint32_t howner[kWavesPerWG][kHashSlots];
   __shared__ uint32_t vkeys[kWavesPerWG][L::VSLOTS];
   __shared__ float vvals[kWavesPerWG][L::VW * L::VSLOTS];
   __shared__ uint32_t vfill[kWavesPerWG];
@@ -1187,7 +1188,6 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   uint32_t* keys = hkeys[wid];
   float* vals = hvals[wid];
   uint32_t* fill = &hfill[wid];
-  uint32_t* owner = howner[wid];
   const VertTable<SH> vt{vkeys[wid], vvals[wid], &vfill[wid]};
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
@@ -1355,10 +1355,11 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       merge_step<0x4E, 2, L::NV>(f, act, val, lane);   // quad_perm [2,3,0,1]: lane ^ 2
       merge_step<0x128, 8, L::NV>(f, act, val, lane);  // row_ror:8: lane ^ 8 within 16 lanes
       // Slots for the remaining lanes, then plain read-add-write instead of LDS
-      // float atomics (which run one lane at a time): in each round one lane
-      // per slot (the last writer of the slot's owner word) updates it. Lanes
-      // that found no slot retry after a flush; the emptied table then holds
-      // at most 64 keys in kHashSlots = 128 slots and a full probe finds one.
+      // float atomics (which run one lane at a time): in each round the lowest
+      // lane of every group of lanes sharing a slot (found with one ballot per
+      // slot bit) updates it, so a round retires at least one lane per slot.
+      // Lanes that found no slot retry after a flush; the emptied table then
+      // holds at most 64 keys in kHashSlots = 128 slots and a full probe finds one.
       bool pend = act;
       int probes = kHashProbes;
       for (;;) {
@@ -1368,10 +1369,14 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         bool todo = got;
         while (__any(todo)) {
-          if (todo) __hip_atomic_store(&owner[slot], (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          if (todo && __hip_atomic_load(&owner[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint32_t)lane) {
+          uint64_t same = __ballot(todo);
+#pragma unroll
+          for (int b = 0; b < kHashBits; ++b) {
+            const bool bit = todo && ((slot >> b) & 1);
+            const uint64_t bb = __ballot(bit);
+            same &= bit ? bb : ~bb;
+          }
+          if (todo && (same & lanemask_lt(lane)) == 0) {
 #pragma unroll
             for (int qq = 0; qq < L::NV; ++qq) vals[slot * L::NV + qq] += val[qq];
             todo = false;
