@@ -106,8 +106,10 @@ def test_weights_and_weighted_loss(gpu):
     r = gpu.Refiner(3 * K + 4)
     a = rng.normal(size=(300, 3 * K + 4)).astype(np.float32)
     b = rng.normal(size=(300, 3 * K + 4)).astype(np.float32)
-    L, dy = gpu.refiner_loss(r, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), w)
-    rl, rg = om.weighted_mse(a, b, w.cpu().numpy().astype(np.float64))
+    # the weighted loss takes the oracle's weights (float32) on both sides
+    w32 = ref.astype(np.float32)
+    L, dy = gpu.refiner_loss(r, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), torch.from_numpy(w32).cuda())
+    rl, rg = om.weighted_mse(a, b, w32.astype(np.float64))
     assert float(L.item()) == pytest.approx(rl, rel=1e-5)
     np.testing.assert_allclose(dy.cpu().numpy(), rg, rtol=1e-5, atol=1e-12)
 
