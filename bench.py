@@ -147,11 +147,12 @@ def bench_rays(args):
     log(f"hierarchy over {faces['idx'].shape[1]} faces built in {build_ms:.2f} ms")
 
     def step(times=None):
+        # rays are traced in the Morton order of their origins (computed inside the step)
         e = [ev() for _ in range(3)]
         e[0].record()
-        T = bvh.transmittance(*shadow, t_eps=1e-6)
+        T = bvh.transmittance(*shadow, t_eps=1e-6, order=msp.point_order(shadow[0]))
         e[1].record()
-        hit = bvh.closest(*scatter, alpha_min=0.0)
+        hit = bvh.closest(*scatter, alpha_min=0.0, order=msp.point_order(scatter[0]))
         e[2].record()
         if times is not None:
             times.append(e)
@@ -193,7 +194,7 @@ def bench_rays(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.n} flat Gaussians, one fan of K={p['K']}, {faces['idx'].shape[1]} faces; "
                                f"{R} shadow segments to a point light and {R} isotropic rays per step",
-                   "rays_per_query": R, "build_ms": build_ms, "transmittance_ms": ms_T, "closest_ms": ms_C,
+                   "rays_per_query": R, "ray_order": "morton of the origins", "build_ms": build_ms, "transmittance_ms": ms_T, "closest_ms": ms_C,
                    "occluded_fraction": occl, "hit_fraction": hits,
                    "node_visits_per_ray": visits / (2 * R), "leaf_tests_per_ray": leaf / (2 * R)},
         "roofline": roof,

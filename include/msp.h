@@ -167,6 +167,8 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
  * runs and neighbouring faces share cache lines. Synchronises. EINVAL: NULL
  * arguments with n > 0, n >= 2^31. */
 msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* order);
+/* The same order for any n points [3][n] (DEVICE), e.g. ray origins. Synchronises. */
+msp_status msp_point_order(msp_ctx* ctx, const float* points, int64_t n, int32_t* order);
 /* msp_convert with the output blocks permuted: the faces and vertices of
  * output block i (the i-th group of K faces and K + 1 vertices, or 3K faces
  * and 7 + 3 (K - 4) vertices for MSP_FAN_3D) are those of Gaussian order[i],
@@ -324,6 +326,9 @@ typedef struct msp_rays {
   const float* dir;     /* [3][n]; any non-zero length (t is in units of |dir|) */
   const float* tmin;    /* [n] */
   const float* tmax;    /* [n], may be +inf */
+  const int32_t* order; /* [n] or NULL: the order in which rays are traced (e.g. msp_point_order of the
+                           origins, so that neighbouring threads walk the same nodes); results are still
+                           written at each ray's own index; entries outside [0, n) are skipped */
 } msp_rays;
 
 typedef struct msp_bvh msp_bvh;  /* library-owned bounding-volume hierarchy over a face soup */

@@ -21,7 +21,7 @@ __all__ = ["convert", "render", "render_backward", "RenderOptions", "RenderState
            "camera_struct", "load_library", "GraphStep", "autotune", "loss", "adam_step", "prune", "convert_rings",
            "Refiner", "refiner_features", "refiner_apply", "refiner_targets", "refiner_weights",
            "refiner_apply_backward", "refiner_loss", "MSP_FAN_FLAT", "MSP_FAN_3D", "prior_init", "prior_vertices",
-           "prior_backward", "Bvh", "spatial_order"]
+           "prior_backward", "Bvh", "spatial_order", "point_order"]
 
 MSP_COLOR_RGB = 0
 MSP_COLOR_SH3 = 1
@@ -65,6 +65,19 @@ def spatial_order(g: dict):
     order = torch.empty((mean.shape[1],), dtype=torch.int32, device=mean.device)
     G = _lib.Gaussians(mean.shape[1], _dev_ptr(mean), None, None, None, None, None)
     ctx.check(ctx.lib.msp_spatial_order(ctx.h, C.byref(G), _dev_ptr(order)), "msp_spatial_order")
+    return order
+
+
+def point_order(points):
+    """msp_point_order: int32 [n] order of points [3][n] along their Morton curve (e.g. ray origins)."""
+    import torch
+    p = _need(points, torch.float32, "points")
+    if p.dim() != 2 or p.shape[0] != 3:
+        raise ValueError("points must be [3][n]")
+    ctx = _ctx(p)
+    ctx.bind_stream()
+    order = torch.empty((p.shape[1],), dtype=torch.int32, device=p.device)
+    ctx.check(ctx.lib.msp_point_order(ctx.h, _dev_ptr(p), p.shape[1], _dev_ptr(order)), "msp_point_order")
     return order
 
 
@@ -513,7 +526,7 @@ class Bvh:
             self.h = None
 
     @staticmethod
-    def _rays(origin, direction, tmin, tmax):
+    def _rays(origin, direction, tmin, tmax, order=None):
         import torch
         o = _need(origin, torch.float32, "origin")
         d = _need(direction, torch.float32, "dir")
@@ -524,22 +537,27 @@ class Bvh:
         t1 = _need(tmax, torch.float32, "tmax")
         if t0.numel() != n or t1.numel() != n:
             raise ValueError("tmin and tmax must have n entries")
-        return _lib.Rays(n, _dev_ptr(o), _dev_ptr(d), _dev_ptr(t0), _dev_ptr(t1)), n
+        if order is not None:
+            _need(order, torch.int32, "order")
+            if order.numel() != n:
+                raise ValueError("order must have n entries")
+        return _lib.Rays(n, _dev_ptr(o), _dev_ptr(d), _dev_ptr(t0), _dev_ptr(t1), _dev_ptr(order)), n
 
-    def transmittance(self, origin, direction, tmin, tmax, t_eps: float = 0.0):
-        """msp_trace_transmittance: T [n]."""
+    def transmittance(self, origin, direction, tmin, tmax, t_eps: float = 0.0, order=None):
+        """msp_trace_transmittance: T [n]. `order` (int32 [n], e.g. point_order(origin)) is the
+        order in which the rays are traced; results stay at each ray's index."""
         import torch
-        R, n = self._rays(origin, direction, tmin, tmax)
+        R, n = self._rays(origin, direction, tmin, tmax, order)
         T = torch.empty((n,), dtype=torch.float32, device=self.device)
         self.ctx.bind_stream()
         self.ctx.check(self.ctx.lib.msp_trace_transmittance(self.ctx.h, self.h, C.byref(R), float(t_eps),
                                                             _dev_ptr(T)), "msp_trace_transmittance")
         return T
 
-    def closest(self, origin, direction, tmin, tmax, alpha_min: float = 0.0):
-        """msp_trace_closest: (t, face, u, v), each [n]."""
+    def closest(self, origin, direction, tmin, tmax, alpha_min: float = 0.0, order=None):
+        """msp_trace_closest: (t, face, u, v), each [n]; `order` as for transmittance."""
         import torch
-        R, n = self._rays(origin, direction, tmin, tmax)
+        R, n = self._rays(origin, direction, tmin, tmax, order)
         e = lambda dt: torch.empty((n,), dtype=dt, device=self.device)
         t, f, u, v = e(torch.float32), e(torch.int32), e(torch.float32), e(torch.float32)
         self.ctx.bind_stream()

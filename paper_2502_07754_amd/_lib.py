@@ -34,7 +34,7 @@ class Mesh(C.Structure):
 
 class Rays(C.Structure):
     _fields_ = [("n", C.c_int64), ("origin", C.c_void_p), ("dir", C.c_void_p), ("tmin", C.c_void_p),
-                ("tmax", C.c_void_p)]
+                ("tmax", C.c_void_p), ("order", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -101,6 +101,7 @@ EXPORTS = {
     "msp_prior_vertices": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p]),
     "msp_prior_backward": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "msp_spatial_order": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_void_p]),
+    "msp_point_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "msp_convert_ordered": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float, C.c_int,
                                       C.c_void_p, C.POINTER(Faces)]),
     "msp_bvh_build": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(C.c_void_p)]),

@@ -530,11 +530,17 @@ msp_status msp_bvh_status(msp_ctx* ctx, const msp_bvh* b, int64_t* n_leaves, int
 
 msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* order) {
   if (!ctx) return MSP_EINVAL;
-  if (!g || g->n < 0 || g->n >= (int64_t(1) << 31) || (g->n > 0 && (!g->mean || !order)))
-    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_spatial_order: bad argument");
-  if (g->n == 0) return MSP_OK;
+  if (!g) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_spatial_order: bad argument");
+  return msp_point_order(ctx, g->mean, g->n, order);
+}
+
+msp_status msp_point_order(msp_ctx* ctx, const float* points, int64_t n, int32_t* order) {
+  if (!ctx) return MSP_EINVAL;
+  if (n < 0 || n >= (int64_t(1) << 31) || (n > 0 && (!points || !order)))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_point_order: bad argument");
+  if (n == 0) return MSP_OK;
   DeviceGuard dg(ctx->device);
-  const int64_t n = g->n, tiles = (n + 2047) / 2048;
+  const int64_t tiles = (n + 2047) / 2048;
   msp_bvh tmp;  // scratch of the same shape as a hierarchy build's sort, freed below
   int rc;
   if ((rc = msp_ensure(ctx, tmp.part, 6 * 1024 * sizeof(float))) || (rc = msp_ensure(ctx, tmp.boxes, 16 * sizeof(float))) ||
@@ -545,11 +551,11 @@ msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* orde
     bvh_release(&tmp);
     return (msp_status)rc;
   }
-  hipError_t e = launch_spatial_order(ctx->stream, g->mean, n, tmp.view(), order);
+  hipError_t e = launch_spatial_order(ctx->stream, points, n, tmp.view(), order);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   bvh_release(&tmp);
   if (e != hipSuccess)
-    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("msp_spatial_order: ") + hipGetErrorString(e));
+    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("msp_point_order: ") + hipGetErrorString(e));
   return MSP_OK;
 }
 

@@ -377,8 +377,16 @@ struct RayIn {
   const float* d;
   const float* t0;
   const float* t1;
+  const int32_t* order;
   int64_t n;
 };
+
+// the ray a thread traces: order[j] when an order is given (-1 outside [0, n))
+__device__ __forceinline__ int64_t ray_of(const RayIn& r, int64_t j) {
+  if (!r.order) return j;
+  const int32_t i = r.order[j];
+  return (i >= 0 && (int64_t)i < r.n) ? (int64_t)i : -1;
+}
 
 struct Ray {
   float o[3], d[3], id[3], t0, t1;
@@ -461,7 +469,9 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_transmittance(const flo
   const int tid = threadIdx.x;
   uint64_t n_nodes = 0, n_leaf = 0;
   for (int64_t r = blockIdx.x * (int64_t)kTraceThreads + tid; r < rin.n; r += (int64_t)gridDim.x * kTraceThreads) {
-    const Ray y = load_ray(rin, r);
+    const int64_t ri = ray_of(rin, r);
+    if (ri < 0) continue;
+    const Ray y = load_ray(rin, ri);
     float T = 1.f;
     bool overflow = false;
     if (n_leaves > 0 && box_hit(y, root_box[0], root_box[1], root_box[2], root_box[3], root_box[4], root_box[5], y.t1)) {
@@ -504,7 +514,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_transmittance(const flo
       T = __int_as_float(0x7fc00000);
       atomicOr(err, 1u);
     }
-    T_out[r] = T;
+    T_out[ri] = T;
   }
   count_visits(n_nodes, n_leaf, err);
 }
@@ -519,7 +529,9 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_closest(const float4* _
   const int tid = threadIdx.x;
   uint64_t n_nodes = 0, n_leaf = 0;
   for (int64_t r = blockIdx.x * (int64_t)kTraceThreads + tid; r < rin.n; r += (int64_t)gridDim.x * kTraceThreads) {
-    const Ray y = load_ray(rin, r);
+    const int64_t ri = ray_of(rin, r);
+    if (ri < 0) continue;
+    const Ray y = load_ray(rin, ri);
     float bt = INFINITY, bu = 0.f, bv = 0.f;
     int32_t bf = -1;
     bool overflow = false;
@@ -579,10 +591,10 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_closest(const float4* _
       bf = -1;
       atomicOr(err, 1u);
     }
-    t_out[r] = bt;
-    f_out[r] = bf;
-    if (u_out) u_out[r] = bu;
-    if (v_out) v_out[r] = bv;
+    t_out[ri] = bt;
+    f_out[ri] = bf;
+    if (u_out) u_out[ri] = bu;
+    if (v_out) v_out[ri] = bv;
   }
   count_visits(n_nodes, n_leaf, err);
 }
@@ -647,7 +659,7 @@ hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b)
 hipError_t launch_trace_transmittance(hipStream_t s, const BvhBufs& b, int64_t n_leaves, const msp_rays* r,
                                       float t_eps, float* T, uint32_t* err) {
   if (r->n == 0) return hipSuccess;
-  RayIn rin{r->origin, r->dir, r->tmin, r->tmax, r->n};
+  RayIn rin{r->origin, r->dir, r->tmin, r->tmax, r->order, r->n};
   hipLaunchKernelGGL(k_trace_transmittance, dim3(grid_for(r->n, kTraceThreads)), dim3(kTraceThreads), 0, s,
                      (const float4*)b.nodes, (const float4*)b.leaves, n_leaves, b.root_box, rin, t_eps, T, err);
   return hipGetLastError();
@@ -656,7 +668,7 @@ hipError_t launch_trace_transmittance(hipStream_t s, const BvhBufs& b, int64_t n
 hipError_t launch_trace_closest(hipStream_t s, const BvhBufs& b, int64_t n_leaves, const msp_rays* r, float alpha_min,
                                 float* t, int32_t* face, float* u, float* v, uint32_t* err) {
   if (r->n == 0) return hipSuccess;
-  RayIn rin{r->origin, r->dir, r->tmin, r->tmax, r->n};
+  RayIn rin{r->origin, r->dir, r->tmin, r->tmax, r->order, r->n};
   hipLaunchKernelGGL(k_trace_closest, dim3(grid_for(r->n, kTraceThreads)), dim3(kTraceThreads), 0, s,
                      (const float4*)b.nodes, (const float4*)b.leaves, n_leaves, b.root_box, rin, alpha_min, t, face, u,
                      v, err);

@@ -211,3 +211,28 @@ def test_transmittance_full_size_sampled(gpu):
     ref, n_flag = _check_transmittance(f, O[:, sample], D[:, sample], t0[sample], t1[sample], T[sample])
     _say("full size: occluded", float(np.mean(T < 1)), "sampled", ref, "flagged", n_flag)
     assert n_flag <= 1
+
+
+def test_ray_order_gives_the_same_results(gpu):
+    """Tracing in any order (a random permutation, the Morton order of the
+    origins) gives bit-identical results at each ray's own index; order
+    entries outside [0, n) are skipped."""
+    import torch
+    f = _fans(500, 13, lo=0.05, hi=0.3)
+    O, D, t0, t1 = _rays(4000, 14)
+    b = gpu.Bvh(to_gpu(f))
+    rays = _gpu_rays(O, D, t0, t1)
+    T = b.transmittance(*rays).cpu().numpy()
+    hit = [x.cpu().numpy() for x in b.closest(*rays, alpha_min=0.2)]
+    perm = torch.from_numpy(np.random.default_rng(3).permutation(4000).astype(np.int32)).cuda()
+    for order in (perm, gpu.point_order(rays[0])):
+        assert np.array_equal(np.sort(order.cpu().numpy()), np.arange(4000))
+        assert np.array_equal(b.transmittance(*rays, order=order).cpu().numpy(), T)
+        got = [x.cpu().numpy() for x in b.closest(*rays, alpha_min=0.2, order=order)]
+        for a, c in zip(got, hit):
+            assert np.array_equal(a, c)
+    bad = np.arange(4000, dtype=np.int32)
+    bad[:10] = 4000
+    bad[10:20] = -1
+    T2 = b.transmittance(*rays, order=torch.from_numpy(bad).cuda())
+    assert np.array_equal(T2.cpu().numpy()[20:], T[20:])
