@@ -60,10 +60,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, cams, K, sigma, seconds: float):
-    """The float64 oracle (brute force over every face per pixel) on a few
-    pixels of view 0 of the same workload, forward and backward; extrapolated
-    to Mpix/s. Single process."""
+_CPU = {}
+
+
+def _cpu_prepare(n: int, views: int):
+    """Oracle inputs of the batched-render workload (view 0), kept in module state for forked workers."""
     import numpy as np
 
     from oracle import convert as oc
@@ -71,16 +72,26 @@ def cpu_baseline(g, cams, K, sigma, seconds: float):
     from oracle import sh as osh
     from paper_2502_07754_amd import scenes
 
-    f = oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, K, sigma, sh=g.sh)
+    g, cams, p = scenes.config3(n=n, views=views)
+    f = oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, p["K"], p["sigma"], sh=g.sh)
     f = {k: (v.astype(np.float32).astype(np.float64) if v.dtype == np.float64 else v) for k, v in f.items()}
     cam = cams[0]
     col, _ = osh.face_colours(f["sh"], f["pos"], f["idx"], cam)
-    geom = orr.face_geometry(f["pos"], f["idx"], cam)
-    rng = np.random.default_rng(7)
-    dimg = scenes.upstream_grad(1, cam.height, cam.width, 3, 1e-3)
+    _CPU.update(f=f, cam=cam, col=col, geom=orr.face_geometry(f["pos"], f["idx"], cam),
+                dimg=scenes.upstream_grad(1, cam.height, cam.width, 3, 1e-3))
+
+
+def _cpu_worker(args):
+    """Forward + backward of seeded pixels of the central half of view 0 until the deadline."""
+    import numpy as np
+
+    from oracle import render as orr
+    from oracle import sh as osh
+    wid, deadline = args
+    f, cam, col, geom, dimg = (_CPU[k] for k in ("f", "cam", "col", "geom", "dimg"))
+    rng = np.random.default_rng(7 + wid)
     done = 0
-    t0 = time.perf_counter()
-    while True:
+    while time.time() < deadline and done < 64:
         i = int(rng.integers(cam.width // 4, 3 * cam.width // 4))
         j = int(rng.integers(cam.height // 4, 3 * cam.height // 4))
         fr = orr.pixel_fragments(f, cam, i, j, geom)
@@ -89,12 +100,36 @@ def cpu_baseline(g, cams, K, sigma, seconds: float):
         r = orr.pixel_backward(f, cam, i, j, dimg[0, :, j, i], fr, view_col=col, geom=geom)
         osh.face_colours_backward(f["sh"][:, r["fid"]], f["pos"], f["idx"][:, r["fid"]], cam, r["dcol"].T)
         done += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or done >= 64:
-            break
-    return dict(value=done / el / 1e6, unit="Mpix/s", cores=1, kind="oracle",
+    return done
+
+
+def cpu_baseline_child(n: int, views: int, seconds: float, procs: int) -> dict:
+    """Runs in a process of its own that never touches the GPU: the float64
+    oracle (brute force over every face per pixel) on seeded pixels of view 0
+    of the same workload, forward and backward, one forked worker per core."""
+    import multiprocessing as mp
+    _cpu_prepare(n, views)
+    t0 = time.time()
+    deadline = t0 + seconds
+    with mp.get_context("fork").Pool(procs) as pool:
+        counts = pool.map(_cpu_worker, [(w, deadline) for w in range(procs)])
+    el = time.time() - t0
+    done = int(sum(counts))
+    return dict(value=done / el / 1e6, unit="Mpix/s", cores=procs, kind="oracle",
                 sample=f"{done} pixels of view 0 (central half), forward + backward, brute force over all "
-                       f"{f['idx'].shape[1]} faces per pixel, float64, {el:.1f} s")
+                       f"{_CPU['f']['idx'].shape[1]} faces per pixel, float64, {procs} processes, {el:.1f} s")
+
+
+def cpu_baseline(n: int, views: int, seconds: float) -> dict:
+    """The oracle leg, started as a child process (the GPU process only waits for its JSON line)."""
+    import subprocess
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--n", str(n), "--views", str(views),
+           "--cpu-seconds", str(seconds), "--cpu-procs", str(procs)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=seconds + 600)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def copy_bandwidth(gib: float, reps: int):
@@ -234,7 +269,12 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device-to-device copy of this many GiB (bandwidth and "
                          "HBM-counter calibration) and exit")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-procs", type=int, default=1, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        print(json.dumps(cpu_baseline_child(args.n, args.views, args.cpu_seconds, args.cpu_procs)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
@@ -265,6 +305,7 @@ def main():
     ctx = _lib.Context.get(0)
     ctx.timing(True)
     mesh = None
+    prep_ms = {}
     if args.scene == "prior":
         m = scenes.icosphere(args.prior_level, 0)
         mesh = {k: torch.from_numpy(v).to(dev) for k, v in dict(pos=m.pos, idx=m.idx, rgb=m.rgb).items()}
@@ -273,8 +314,14 @@ def main():
         cm = msp.MSP_COLOR_RGB
     else:
         # the same scene with its faces laid out along the Morton curve of the Gaussian means
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
         order = None if args.input_order else msp.spatial_order(gg)
+        torch.cuda.synchronize()
+        t_o = time.perf_counter()
         faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT, order=order)
+        torch.cuda.synchronize()
+        prep_ms = dict(spatial_order_ms=(t_o - t_c) * 1e3, convert_ms=(time.perf_counter() - t_o) * 1e3)
         cm = msp.MSP_COLOR_SH3
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
@@ -392,12 +439,12 @@ def main():
                    "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
                    "face_order": "input" if (args.input_order or mesh is not None) else "morton",
                    "entries_per_step": entries, "fragments_per_step": frags,
-                   "fragments_per_s": frags / dt},
+                   "fragments_per_s": frags / dt, "entries_per_s": entries / dt, **prep_ms},
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.scene == "flat" and not args.fan3:
         log("timing the oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(g, cams, K, sigma, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.n, args.views, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
