@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--prior-n", type=int, default=2, help="secondary triangles per mesh face: n^2")
     ap.add_argument("--fan3", action="store_true",
                     help="convert with three fans per Gaussian (3D-Gaussian conversion) instead of one")
+    ap.add_argument("--rgb", action="store_true",
+                    help="per-vertex RGB colours instead of degree-3 SH (the colour mode of fine-tuning)")
     ap.add_argument("--input-order", action="store_true",
                     help="convert the Gaussians in their drawn order instead of the spatial (Morton) order")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -319,10 +321,12 @@ def main():
         order = None if args.input_order else msp.spatial_order(gg)
         torch.cuda.synchronize()
         t_o = time.perf_counter()
+        if args.rgb:
+            gg.pop("sh", None)
         faces = msp.convert(gg, K, sigma, mode=msp.MSP_FAN_3D if args.fan3 else msp.MSP_FAN_FLAT, order=order)
         torch.cuda.synchronize()
         prep_ms = dict(spatial_order_ms=(t_o - t_c) * 1e3, convert_ms=(time.perf_counter() - t_o) * 1e3)
-        cm = msp.MSP_COLOR_SH3
+        cm = msp.MSP_COLOR_RGB if args.rgb else msp.MSP_COLOR_SH3
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
     opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=cm,
@@ -411,7 +415,7 @@ def main():
         roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                     traffic=None)
     mt = MEASURED_TRAFFIC
-    if (dom in mt and args.scene == "flat" and not args.fan3 and not args.input_order
+    if (dom in mt and args.scene == "flat" and not args.fan3 and not args.input_order and not args.rgb
             and kernel_sources_sha256() == mt["sources_sha256"]
             and [opts.tile_w, opts.tile_h] == mt["tile"] and opts.kbuf == mt["kbuf"] and args.n == 500_000
             and args.views == 8):
@@ -427,7 +431,8 @@ def main():
                     f"secondary positions + fwd + bwd + logit adjoint")
     else:
         workload = (f"{args.n} {'flat' if args.scene == 'flat' else '3D'} Gaussians, "
-                    f"{'three fans' if args.fan3 else 'one fan'} of K={K}, sigma={sigma}, SH degree 3, "
+                    f"{'three fans' if args.fan3 else 'one fan'} of K={K}, sigma={sigma}, "
+                    f"{'RGB' if args.rgb else 'SH degree 3'}, "
                     f"{args.views} views {W}x{H}, fwd+bwd")
     out = {
         "metric": "Mpix/s fwd+bwd at 1080p, 500k Gaussians K=16; fine-tune s to target MSE",
@@ -442,7 +447,7 @@ def main():
                    "fragments_per_s": frags / dt, "entries_per_s": entries / dt, **prep_ms},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and args.scene == "flat" and not args.fan3:
+    if not args.no_cpu_baseline and args.scene == "flat" and not args.fan3 and not args.rgb:
         log("timing the oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(args.n, args.views, args.cpu_seconds)
     print(json.dumps(out), flush=True)

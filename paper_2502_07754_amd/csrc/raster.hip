@@ -907,10 +907,8 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
 }
 
 template <int KB, bool SHP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_composite(RasterArgs a, uint32_t n_items) {
-  __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
+__device__ __forceinline__ void composite_items(const RasterArgs& a, uint32_t n_items, float* slab) {
   const int lane = lane_id();
-  float* slab = slabs[threadIdx.x / MSP_WAVE];
   RegBuf<KB, !SHP> kb;  // with SH the colour comes from the face when a fragment is composited
   uint64_t frags = 0;
   uint32_t restarts = 0;
@@ -950,6 +948,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     atomicAdd(&a.counters[0], (unsigned long long)frags);
     if (restarts) atomicAdd(&a.counters[1], (unsigned long long)restarts);
   }
+}
+
+// The SH kernel keeps only depth, id and alpha per buffer slot (the colour is
+// fetched when a fragment is composited), which at a budget of 168 registers
+// runs three waves per SIMD with a few spills: faster than two without. The
+// RGB kernel keeps the interpolated colour per slot as well.
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_composite_sh(RasterArgs a,
+                                                                                            uint32_t n_items) {
+  __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
+  composite_items<KB, true>(a, n_items, slabs[threadIdx.x / MSP_WAVE]);
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void k_composite_rgb(RasterArgs a, uint32_t n_items) {
+  __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
+  composite_items<KB, false>(a, n_items, slabs[threadIdx.x / MSP_WAVE]);
 }
 
 // per 8x8 block: the longest fragment list of its pixels (rows of the backward slab)
@@ -1450,8 +1465,13 @@ hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a) {
 
 template <int KB, bool SHP>
 static void launch_comp(hipStream_t s, const RasterArgs& a, int n_cu, uint32_t n_items) {
-  const int g = persistent_grid(k_composite<KB, SHP>, n_cu, n_items);
-  hipLaunchKernelGGL((k_composite<KB, SHP>), dim3(g), dim3(256), 0, s, a, n_items);
+  if (SHP) {
+    const int g = persistent_grid(k_composite_sh<KB>, n_cu, n_items);
+    hipLaunchKernelGGL((k_composite_sh<KB>), dim3(g), dim3(256), 0, s, a, n_items);
+  } else {
+    const int g = persistent_grid(k_composite_rgb<KB>, n_cu, n_items);
+    hipLaunchKernelGGL((k_composite_rgb<KB>), dim3(g), dim3(256), 0, s, a, n_items);
+  }
 }
 
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu) {
