@@ -164,10 +164,11 @@ msp_status msp_convert(msp_ctx* ctx, const msp_gaussians* g, int K, float sigma,
  * box (stable, so equal codes keep index order). Not in the paper: a layout
  * choice. Faces converted in this order (msp_convert_ordered) keep the faces
  * of nearby Gaussians at nearby ids, so binning writes its tile-list keys in
- * runs and neighbouring faces share cache lines. Synchronises. EINVAL: NULL
- * arguments with n > 0, n >= 2^31. */
+ * runs and neighbouring faces share cache lines. Asynchronous; the sort's
+ * scratch is kept by the context (grown, with a synchronisation, when n
+ * grows). EINVAL: NULL arguments with n > 0, n >= 2^31. */
 msp_status msp_spatial_order(msp_ctx* ctx, const msp_gaussians* g, int32_t* order);
-/* The same order for any n points [3][n] (DEVICE), e.g. ray origins. Synchronises. */
+/* The same order for any n points [3][n] (DEVICE), e.g. ray origins. */
 msp_status msp_point_order(msp_ctx* ctx, const float* points, int64_t n, int32_t* order);
 /* msp_convert with the output blocks permuted: the faces and vertices of
  * output block i (the i-th group of K faces and K + 1 vertices, or 3K faces

@@ -163,7 +163,9 @@ msp_status msp_destroy(msp_ctx* ctx) {
   }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   DevBuf* bufs[] = {&ctx->loss_scratch, &ctx->pr_keep, &ctx->pr_used, &ctx->pr_foff, &ctx->pr_voff,
-                    &ctx->pr_scan, &ctx->pr_tmpi, &ctx->pr_tmpf};
+                    &ctx->pr_scan, &ctx->pr_tmpi, &ctx->pr_tmpf, &ctx->ord_part, &ctx->ord_boxes,
+                    &ctx->ord_keys0, &ctx->ord_keys1, &ctx->ord_vals1, &ctx->ord_counts, &ctx->ord_offs,
+                    &ctx->ord_scan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   delete ctx;
@@ -541,21 +543,24 @@ msp_status msp_point_order(msp_ctx* ctx, const float* points, int64_t n, int32_t
   if (n == 0) return MSP_OK;
   DeviceGuard dg(ctx->device);
   const int64_t tiles = (n + 2047) / 2048;
-  msp_bvh tmp;  // scratch of the same shape as a hierarchy build's sort, freed below
   int rc;
-  if ((rc = msp_ensure(ctx, tmp.part, 6 * 1024 * sizeof(float))) || (rc = msp_ensure(ctx, tmp.boxes, 16 * sizeof(float))) ||
-      (rc = msp_ensure(ctx, tmp.keys0, n * 4)) || (rc = msp_ensure(ctx, tmp.keys1, n * 4)) ||
-      (rc = msp_ensure(ctx, tmp.vals1, n * 4)) || (rc = msp_ensure(ctx, tmp.counts, 256 * tiles * 4)) ||
-      (rc = msp_ensure(ctx, tmp.offs, (256 * tiles + 1) * 8)) ||
-      (rc = msp_ensure(ctx, tmp.scan, scan_scratch_bytes(256 * tiles)))) {
-    bvh_release(&tmp);
+  if ((rc = msp_ensure(ctx, ctx->ord_part, 6 * 1024 * sizeof(float))) ||
+      (rc = msp_ensure(ctx, ctx->ord_boxes, 16 * sizeof(float))) || (rc = msp_ensure(ctx, ctx->ord_keys0, n * 4)) ||
+      (rc = msp_ensure(ctx, ctx->ord_keys1, n * 4)) || (rc = msp_ensure(ctx, ctx->ord_vals1, n * 4)) ||
+      (rc = msp_ensure(ctx, ctx->ord_counts, 256 * tiles * 4)) ||
+      (rc = msp_ensure(ctx, ctx->ord_offs, (256 * tiles + 1) * 8)) ||
+      (rc = msp_ensure(ctx, ctx->ord_scan, scan_scratch_bytes(256 * tiles))))
     return (msp_status)rc;
-  }
-  hipError_t e = launch_spatial_order(ctx->stream, points, n, tmp.view(), order);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  bvh_release(&tmp);
-  if (e != hipSuccess)
-    return (msp_status)msp_fail(ctx, MSP_EHIP, std::string("msp_point_order: ") + hipGetErrorString(e));
+  BvhBufs b;
+  b.part = (float*)ctx->ord_part.p;
+  b.scene_box = (float*)ctx->ord_boxes.p;
+  b.keys[0] = (uint32_t*)ctx->ord_keys0.p;
+  b.keys[1] = (uint32_t*)ctx->ord_keys1.p;
+  b.vals[1] = (uint32_t*)ctx->ord_vals1.p;
+  b.counts = (uint32_t*)ctx->ord_counts.p;
+  b.offs = (int64_t*)ctx->ord_offs.p;
+  b.scan = ctx->ord_scan.p;
+  MSP_TIMED(ctx, ST_OTHER, launch_spatial_order(ctx->stream, points, n, b, order));
   return MSP_OK;
 }
 

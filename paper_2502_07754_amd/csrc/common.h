@@ -34,6 +34,8 @@ struct msp_ctx {
   // autotuned tile choice per (n_faces bucket, width, height, n_views), filled by msp_autotune
   int tuned_tile_w = 0, tuned_tile_h = 0, tuned_kbuf = 0;
   DevBuf loss_scratch, pr_keep, pr_used, pr_foff, pr_voff, pr_scan, pr_tmpi, pr_tmpf;
+  // scratch of msp_point_order (Morton codes and their radix sort), grow-only
+  DevBuf ord_part, ord_boxes, ord_keys0, ord_keys1, ord_vals1, ord_counts, ord_offs, ord_scan;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
 };
