@@ -14,9 +14,12 @@ front to back through the alpha channel, final RGB and alpha read out):
     which are the perspective-correct ones;
   * alpha = clamp(sum_k b_k o_k, 0, 1), colour = sum_k b_k c_k (or the face's
     per-view colour when colours come from spherical harmonics);
-  * all hits are sorted by (depth, face id) and composited front to back with
-    no early stop: C = sum_i T_i a_i c_i, T_{i+1} = T_i (1 - a_i),
-    RGB = C + T_{n+1} bg, A = 1 - T_{n+1}.
+  * all hits are sorted by (depth, face id) and composited front to back:
+    C = sum_i T_i a_i c_i, T_{i+1} = T_i (1 - a_i), RGB = C + T_{n+1} bg,
+    A = 1 - T_{n+1}; by default with no early stop, and with t_eps > 0 only the
+    fragments whose transmittance before them is at least t_eps (the pixel
+    stops once it falls below; a list truncated there is composited as if it
+    ended there, and the adjoint differentiates that truncated list).
 
 The adjoint freezes the set and order of fragments (the derivative of an
 unantialiased rasteriser) and differentiates the rest exactly:
@@ -126,15 +129,33 @@ def composite(alpha, col, bg):
     return rgba, T
 
 
-def render_pixels(faces, cam, pixels, bg=(0.0, 0.0, 0.0), view_col=None, return_frags=False):
-    """RGBA at the listed pixels [(i, j), ...]; optionally the fragment lists."""
+def early_stop(alpha, t_eps):
+    """Number of leading fragments composited when a pixel stops once its
+    transmittance falls below t_eps: fragment k is composited iff the
+    transmittance before it is >= t_eps (t_eps = 0: all of them)."""
+    T = 1.0
+    for k, a in enumerate(alpha):
+        if T < t_eps:
+            return k
+        T *= 1.0 - a
+    return len(alpha)
+
+
+def _head(frags, n):
+    return {k: (None if v is None else v[:n]) for k, v in frags.items()}
+
+
+def render_pixels(faces, cam, pixels, bg=(0.0, 0.0, 0.0), view_col=None, return_frags=False, t_eps=0.0):
+    """RGBA at the listed pixels [(i, j), ...]; optionally the fragment lists (as composited)."""
     geom = face_geometry(faces["pos"], faces["idx"], cam)
     out = np.zeros((len(pixels), 4))
     frs = []
     for n, (i, j) in enumerate(pixels):
         fr = pixel_fragments(faces, cam, i, j, geom)
         a, _, c = fragment_attributes(faces, fr, view_col)
-        out[n], _ = composite(a, c, bg)
+        m = early_stop(a, t_eps)
+        fr = _head(fr, m)
+        out[n], _ = composite(a[:m], c[:m], bg)
         frs.append(fr)
     return (out, frs) if return_frags else out
 
@@ -178,8 +199,9 @@ def render_image(faces, cam, bg=(0.0, 0.0, 0.0), view_col=None, processes=1):
 # Adjoint
 # ---------------------------------------------------------------------------
 
-def pixel_backward(faces, cam, i, j, g_rgba, frags, bg=(0.0, 0.0, 0.0), view_col=None, geom=None):
-    """Gradient contributions of one pixel with a frozen fragment list.
+def pixel_backward(faces, cam, i, j, g_rgba, frags, bg=(0.0, 0.0, 0.0), view_col=None, geom=None, t_eps=0.0):
+    """Gradient contributions of one pixel with a frozen fragment list (truncated
+    by the early stop when t_eps > 0).
 
     Returns dict: vid [m] vertex ids, dpos [m][3] (world), dop [m], drgb [m][3],
     and, in per-view-colour mode, fid [n] with dcol [n][3].
@@ -187,7 +209,9 @@ def pixel_backward(faces, cam, i, j, g_rgba, frags, bg=(0.0, 0.0, 0.0), view_col
     c = cam_arrays(cam)
     v0, v1, v2, _ = geom if geom is not None else face_geometry(faces["pos"], faces["idx"], cam)
     alpha, raw, col = fragment_attributes(faces, frags, view_col)
-    n = len(alpha)
+    n = early_stop(alpha, t_eps)
+    frags = _head(frags, n)
+    alpha, raw, col = alpha[:n], raw[:n], col[:n]
     _, T = composite(alpha, col, bg)
     g = np.asarray(g_rgba[:3], np.float64)
     gA = float(g_rgba[3])
@@ -233,7 +257,7 @@ def pixel_backward(faces, cam, i, j, g_rgba, frags, bg=(0.0, 0.0, 0.0), view_col
     return out
 
 
-def render_backward_pixels(faces, cam, pixels, g_pixels, bg=(0.0, 0.0, 0.0), view_col=None):
+def render_backward_pixels(faces, cam, pixels, g_pixels, bg=(0.0, 0.0, 0.0), view_col=None, t_eps=0.0):
     """Sum of pixel_backward over the listed pixels -> per-vertex gradients (and per-face dcol)."""
     geom = face_geometry(faces["pos"], faces["idx"], cam)
     V = np.asarray(faces["opacity"]).shape[0]
@@ -244,7 +268,7 @@ def render_backward_pixels(faces, cam, pixels, g_pixels, bg=(0.0, 0.0, 0.0), vie
     dcol = np.zeros((F, 3))
     for (i, j), g in zip(pixels, g_pixels):
         fr = pixel_fragments(faces, cam, i, j, geom)
-        r = pixel_backward(faces, cam, i, j, g, fr, bg, view_col, geom)
+        r = pixel_backward(faces, cam, i, j, g, fr, bg, view_col, geom, t_eps)
         np.add.at(dpos, r["vid"], r["dpos"])
         np.add.at(dop, r["vid"], r["dop"])
         np.add.at(drgb, r["vid"], r["drgb"])

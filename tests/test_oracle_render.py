@@ -296,3 +296,55 @@ def test_adjoint_dot_product():
     lhs = (_frozen_loss(fp, cam, px, frs, g) - _frozen_loss(fm, cam, px, frs, g)) / (2 * h)
     rhs = np.sum(gr["dpos"] * dpos) + np.sum(gr["dop"] * dop) + np.sum(gr["drgb"] * drgb)
     np.testing.assert_allclose(lhs, rhs, rtol=1e-6)
+
+
+def test_early_stop_three_layers_closed_form():
+    """A pixel stops once its transmittance falls below t_eps: with three layers of
+    alpha 0.9 the transmittance before them is 1, 0.1, 0.01."""
+    cam = cam_identity()
+    big = np.array([[-50, -50, 0.0], [50, -50, 0.0], [0, 50, 0.0]])
+    cols = [[[0.9, 0.1, 0.5]] * 3, [[0.2, 0.4, 0.6]] * 3, [[0.7, 0.7, 0.1]] * 3]
+    f = soup([big + [0, 0, 2.0], big + [0, 0, 3.0], big + [0, 0, 4.0]], [[0.9] * 3] * 3, cols)
+    c = [np.array(x[0]) for x in cols]
+    px = [(8, 8)]
+    for t_eps, layers in ((0.0, 3), (0.005, 3), (0.05, 2), (0.5, 1), (1.0, 1)):
+        out = orr.render_pixels(f, cam, px, t_eps=t_eps)[0]
+        T, C = 1.0, np.zeros(3)
+        for k in range(layers):
+            C += T * 0.9 * c[k]
+            T *= 0.1
+        np.testing.assert_allclose(out, np.concatenate([C, [1 - T]]), atol=1e-14)
+    # just above the transmittance before the third layer: it is dropped; at it: kept
+    assert orr.early_stop(np.array([0.9, 0.9, 0.9]), 0.01 + 1e-12) == 2
+    assert orr.early_stop(np.array([0.9, 0.9, 0.9]), 0.01 - 1e-12) == 3
+
+
+def test_early_stop_adjoint_against_finite_differences():
+    """The adjoint with an early stop differentiates the truncated lists: finite
+    differences of the frozen truncated fragments, and zero gradients for faces
+    that only appear behind the stop."""
+    rng, cam, f, px, frs, g = _fd_setup(seed=23, F=30)
+    t_eps = 0.5
+    _, cut = orr.render_pixels(f, cam, px, return_frags=True, t_eps=t_eps)
+    assert sum(len(c["fid"]) < len(fr["fid"]) for c, fr in zip(cut, frs)) >= 5
+    gr = orr.render_backward_pixels(f, cam, px, g, t_eps=t_eps)
+    h = 1e-6
+    seen = np.unique(np.concatenate([c["fid"] for c in cut]))
+    used_v = np.unique(np.asarray(f["idx"])[:, seen])
+    for v in rng.choice(used_v, 6, replace=False):
+        for key, shape in (("pos", 3), ("rgb", 3), ("opacity", 1)):
+            for ax in range(shape):
+                fp = {k: np.array(x, copy=True) for k, x in f.items()}
+                fm = {k: np.array(x, copy=True) for k, x in f.items()}
+                if shape == 1:
+                    fp[key][v] += h
+                    fm[key][v] -= h
+                    want = gr["dop"][v]
+                else:
+                    fp[key][ax, v] += h
+                    fm[key][ax, v] -= h
+                    want = gr["dpos" if key == "pos" else "drgb"][ax, v]
+                fd = (_frozen_loss(fp, cam, px, cut, g) - _frozen_loss(fm, cam, px, cut, g)) / (2 * h)
+                np.testing.assert_allclose(want, fd, rtol=1e-6, atol=1e-8)
+    behind = np.setdiff1d(np.arange(f["opacity"].shape[0]), used_v)
+    assert len(behind) > 0 and np.all(gr["dop"][behind] == 0) and np.all(gr["dpos"][:, behind] == 0)
