@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--ft-steps", type=int, default=1000)
     ap.add_argument("--ft-mode", choices=("both", "plain", "refined"), default="both")
     ap.add_argument("--ft-target", type=float, default=0.0, help="target MSE of a refined-only run")
-    ap.add_argument("--ft-list-rows", type=int, default=128,
+    ap.add_argument("--ft-list-rows", type=int, default=0,
                     help="fragment-list rows per pixel the forward stores for the backward (0: recompute)")
     args = ap.parse_args()
     import statistics as st
@@ -323,15 +323,16 @@ def main():
         tgt = target_images(g, cams, 1, views_per_call=2)
         torch.cuda.synchronize()
         log(f"targets: {args.ft_views} views {args.ft_res[0]}x{args.ft_res[1]} in {time.perf_counter() - t:.1f} s")
-        # the same render options for both runs: fragment lists stored by the forward, the tile
-        # size and ordering-buffer depth autotuned once on this scene and view set
+        # the same render options for both runs: fragment lists recomputed by the backward (the
+        # workload's setting; --ft-list-rows > 0 stores them instead), the tile size and
+        # ordering-buffer depth autotuned once on this scene and view set
         f0 = convert(to_gpu(g), 8, 2.0)
         d0 = torch.zeros((args.ft_views, 4, args.ft_res[1], args.ft_res[0]), dtype=torch.float32, device="cuda")
         opts = autotune(f0, cams, RenderOptions(list_rows=args.ft_list_rows), d0)
         opts = RenderOptions(tile_w=opts.tile_w, tile_h=opts.tile_h, kbuf=opts.kbuf, list_rows=args.ft_list_rows)
         del f0, d0
         log(f"render options: tile {opts.tile_w}x{opts.tile_h}, ordering buffer {opts.kbuf}, "
-            f"stored list rows {opts.list_rows}")
+            f"stored list rows {opts.list_rows} (0: recomputed)")
         out = dict(n=args.ft_n, views=args.ft_views, res=list(args.ft_res), steps=args.ft_steps,
                    tile=[opts.tile_w, opts.tile_h], kbuf=opts.kbuf, list_rows=opts.list_rows)
         target = args.ft_target or None

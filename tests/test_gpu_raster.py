@@ -319,6 +319,65 @@ def test_backward_config2_sampled_pixels(gpu):
         assert np.count_nonzero(ref[rk]) > 0
 
 
+def test_backward_config2_finite_differences(gpu):
+    """Central finite differences (h = 1e-3) of the loss sum(g * image) on the
+    full 800x800 / 800k-face scene, for the opacity and the three colour
+    channels of one vertex of each of 64 random faces, against the adjoint.
+    These parameters change values, never coverage, so the difference quotient
+    is the frozen-fragment derivative; positions move coverage at h = 1e-3
+    (a quarter pixel here) and are checked against the oracle's gradient,
+    which finite differences pin on the CPU."""
+    import torch
+    g, cams, p = scenes.config2()
+    fg = to_gpu(_oracle_faces(g, p["K"], p["sigma"]))
+    opts = gpu.RenderOptions(t_eps=0.0)
+    img, st = gpu.render(fg, cams, opts)
+    up = torch.from_numpy(scenes.upstream_grad(1, 800, 800, seed=9)).cuda()
+    gr = gpu.render_backward(st, fg, up)
+    gr = {k: v.cpu().numpy().astype(np.float64) for k, v in gr.items()}
+    base = img.double()
+    rng = np.random.default_rng(12)
+    # 64 random faces among those with a visible vertex: a 1e-3 step of a hidden vertex changes
+    # no pixel at float32 resolution, so finite differences cannot resolve its (tiny) gradient
+    idx = fg["idx"].cpu().numpy()
+    corner = rng.integers(0, 3, idx.shape[1])
+    cand = np.flatnonzero(np.abs(gr["dopacity"][idx[corner, np.arange(idx.shape[1])]]) >= 1e-2)
+    faces = rng.choice(cand, 64, replace=False)
+    verts = idx[corner[faces], faces]
+    h = 1e-3
+    _say("finite differences config2")
+
+    def loss_delta(param, index):
+        """(L(+h) - L(-h)) / (actual step) with the float32 values actually rendered, and the
+        rounding bound of that quotient: 8 ulp(1) per changed pixel channel, weighted by |g|."""
+        x0 = float(param[index])
+        vals, noise = [], 0.0
+        for s in (+1, -1):
+            param[index] = x0 + s * h
+            xs = float(param[index])
+            im, _ = gpu.render(fg, cams, opts)
+            d = im.double() - base
+            vals.append((float((d * up.double()).sum()), xs))
+            noise += float(((d != 0).double() * up.double().abs()).sum()) * 8 * 2.0 ** -23
+        param[index] = x0
+        step = vals[0][1] - vals[1][1]
+        return (vals[0][0] - vals[1][0]) / step, noise / abs(step)
+
+    checked = 0
+    for v in verts:
+        v = int(v)
+        cases = [] if not (h < float(fg["opacity"][v]) < 1 - h) else [(fg["opacity"], v, gr["dopacity"][v])]
+        cases += [(fg["rgb"][c], v, gr["drgb"][c, v]) for c in range(3)]
+        for param, index, want in cases:
+            if abs(want) < 1e-3:
+                continue
+            fd, tol = loss_delta(param, index)
+            assert abs(fd - want) <= 1e-3 * abs(want) + tol, (v, fd, want, tol)
+            checked += 1
+    _say("finite differences checked", checked)
+    assert checked >= 128
+
+
 def test_autograd_function(gpu):
     import torch
     g = scenes.gaussians(100, 5, 0.02, 0.15, flat=True)
