@@ -1278,13 +1278,16 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     // Each lane walks its own list back to front from its own last fragment, so
     // the pixels a large face covers reach it at different steps (their list
     // lengths differ) instead of all at once: fewer same-address LDS atomics.
+    // the list entry of the next step is loaded one step ahead, so that its latency
+    // overlaps the current step's record loads instead of adding to them
+    uint2 e_next = nf > 0 ? list[(int64_t)(nf - 1) * MSP_WAVE + lane] : make_uint2(kEmpty, 0u);
     for (int t = 0; t < maxn; ++t) {
       bool act = t < nf;
-      const int k = nf - 1 - t;
       float val[L::NV];
       uint32_t f = kEmpty;
+      const uint2 e = e_next;
+      if (t + 1 < nf) e_next = list[(int64_t)(nf - 2 - t) * MSP_WAVE + lane];
       if (act) {
-        const uint2 e = list[(int64_t)k * MSP_WAVE + lane];
         f = e.x;
         const float Ti = __uint_as_float(e.y);
         act = (uint64_t)f < (uint64_t)a.n_faces;
