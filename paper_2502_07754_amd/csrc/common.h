@@ -84,7 +84,7 @@ struct BvhBufs {
   float* leaves = nullptr;     // [n][16]
   int32_t* parent = nullptr;   // [n - 1]
   int32_t* lparent = nullptr;  // [n]
-  uint32_t* flags = nullptr;   // [n - 1] arrival counts of the bottom-up pass
+  uint32_t* flags = nullptr;   // [n - 1] depths of the internal nodes (level-by-level box pass)
   uint32_t* err = nullptr;     // [1] traversal-stack overflow seen by a query
 };
 

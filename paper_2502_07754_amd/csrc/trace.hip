@@ -16,9 +16,9 @@
 //   5. hierarchy of Karras (2012): internal node i of the N - 1 finds its
 //      range and split from the longest common prefixes of neighbouring
 //      codes (equal codes are told apart by their index)
-//   6. boxes bottom-up: each leaf's thread writes its box into its parent
-//      and increments the parent's arrival count; the second arrival unites
-//      both child boxes and goes on, the first stops (no waiting)
+//   6. boxes bottom-up, one launch per depth from the deepest: each node
+//      unites its children's boxes and writes the result into its parent
+//      (no atomics: the launch boundaries order the levels)
 // Internal node record (64 bytes): both children's boxes side by side and the
 // two child references (>= 0 internal node, < 0 leaf ~index), so one node
 // visit is four 16-byte loads. The common prefix of a child's range is longer
@@ -322,52 +322,87 @@ __device__ __forceinline__ void put_box(float* nd, int slot, const float (&lo)[3
   b[5] = hi[2];
 }
 
-__global__ __launch_bounds__(256) void k_refit(const float4* __restrict__ leaves, int64_t n, float* nodes,
-                                               const int32_t* __restrict__ parent,
-                                               const int32_t* __restrict__ lparent, uint32_t* flags,
-                                               float* __restrict__ root_box) {
-  for (int64_t j = blockIdx.x * 256ll + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
-    const float4 a = leaves[4 * j], e1 = leaves[4 * j + 1], e2 = leaves[4 * j + 2];
-    const float p[3][3] = {{a.x, a.y, a.z}, {a.x + e1.x, a.y + e1.y, a.z + e1.z}, {a.x + e2.x, a.y + e2.y, a.z + e2.z}};
-    float lo[3], hi[3];
+__device__ __forceinline__ void leaf_bounds(const float4* __restrict__ leaves, int64_t j, float (&lo)[3],
+                                            float (&hi)[3]) {
+  const float4 a = leaves[4 * j], e1 = leaves[4 * j + 1], e2 = leaves[4 * j + 2];
+  const float p[3][3] = {{a.x, a.y, a.z}, {a.x + e1.x, a.y + e1.y, a.z + e1.z}, {a.x + e2.x, a.y + e2.y, a.z + e2.z}};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fminf(p[0][d], fminf(p[1][d], p[2][d]));
-      hi[d] = fmaxf(p[0][d], fmaxf(p[1][d], p[2][d]));
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = fminf(p[0][d], fminf(p[1][d], p[2][d]));
+    hi[d] = fmaxf(p[0][d], fmaxf(p[1][d], p[2][d]));
+  }
+}
+
+// depth of every internal node: parent steps to the root (at most 64, see the header;
+// the bound only guards the walk)
+__global__ __launch_bounds__(256) void k_depth(const int32_t* __restrict__ parent, int64_t n_int,
+                                               uint32_t* __restrict__ depth) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n_int; i += (int64_t)gridDim.x * 256) {
+    int32_t j = (int32_t)i;
+    uint32_t d = 0;
+    while (j != 0 && d < 4 * kStack) {
+      j = parent[j];
+      ++d;
     }
-    if (n == 1) {
+    depth[i] = d;
+  }
+}
+
+// Boxes level by level, deepest first (one launch per depth; the launch boundary
+// orders the levels): a node of this depth writes its leaf children's boxes into
+// its own slots, reads the slots its internal children filled one launch
+// earlier, and writes their union into its slot of its parent. Every slot has
+// one writer.
+__global__ __launch_bounds__(256) void k_level_boxes(const float4* __restrict__ leaves, int64_t n_int, float* nodes,
+                                                     const int32_t* __restrict__ parent,
+                                                     const uint32_t* __restrict__ depth, uint32_t level,
+                                                     float* __restrict__ root_box) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n_int; i += (int64_t)gridDim.x * 256) {
+    if (depth[i] != level) continue;
+    float* nd = nodes + 16 * i;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int32_t c = __float_as_int(nd[12 + slot]);
+      float blo[3], bhi[3];
+      if (c < 0) {
+        leaf_bounds(leaves, ~(int64_t)c, blo, bhi);
+        put_box(nd, slot, blo, bhi);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          blo[d] = nd[6 * slot + d];
+          bhi[d] = nd[6 * slot + 3 + d];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fminf(lo[d], blo[d]);
+        hi[d] = fmaxf(hi[d], bhi[d]);
+      }
+    }
+    if (i == 0) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         root_box[d] = lo[d];
         root_box[3 + d] = hi[d];
       }
-      continue;
+    } else {
+      float* pd = nodes + 16ll * parent[i];
+      put_box(pd, __float_as_int(pd[12]) == (int32_t)i ? 0 : 1, lo, hi);
     }
-    int32_t child = ~(int32_t)j;
-    int32_t node = lparent[j];
-    // at most 64 internal nodes on the way up (see the header); the bound only guards the loop
-    for (int step = 0; step < 4 * kStack && node >= 0; ++step) {
-      float* nd = nodes + 16ll * node;
-      const int32_t c0 = __float_as_int(nd[12]);
-      put_box(nd, c0 == child ? 0 : 1, lo, hi);
-      const uint32_t prev = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == 0) break;  // the sibling's thread continues from here
+  }
+}
+
+// a hierarchy of one face: its box is the root box
+__global__ void k_single_leaf_box(const float4* __restrict__ leaves, float* __restrict__ root_box) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float lo[3], hi[3];
+  leaf_bounds(leaves, 0, lo, hi);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = fminf(nd[d], nd[6 + d]);
-        hi[d] = fmaxf(nd[3 + d], nd[9 + d]);
-      }
-      if (node == 0) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          root_box[d] = lo[d];
-          root_box[3 + d] = hi[d];
-        }
-        break;
-      }
-      child = node;
-      node = parent[node];
-    }
+  for (int d = 0; d < 3; ++d) {
+    root_box[d] = lo[d];
+    root_box[3 + d] = hi[d];
   }
 }
 
@@ -649,10 +684,15 @@ hipError_t launch_bvh_build(hipStream_t s, const msp_faces* f, const BvhBufs& b)
                        b.parent, b.lparent);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_fill_u32(s, b.flags, 0u, F > 1 ? F - 1 : 1);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_refit, dim3(grid_for(F, 256)), dim3(256), 0, s, (const float4*)b.leaves, F, b.nodes, b.parent,
-                     b.lparent, b.flags, b.root_box);
+  if (F == 1) {
+    hipLaunchKernelGGL(k_single_leaf_box, dim3(1), dim3(64), 0, s, (const float4*)b.leaves, b.root_box);
+    return hipGetLastError();
+  }
+  // b.flags holds the depths
+  hipLaunchKernelGGL(k_depth, dim3(grid_for(F - 1, 256)), dim3(256), 0, s, b.parent, F - 1, b.flags);
+  for (int level = kStack; level >= 0; --level)
+    hipLaunchKernelGGL(k_level_boxes, dim3(grid_for(F - 1, 256)), dim3(256), 0, s, (const float4*)b.leaves, F - 1,
+                       b.nodes, b.parent, b.flags, (uint32_t)level, b.root_box);
   return hipGetLastError();
 }
 
