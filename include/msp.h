@@ -385,7 +385,8 @@ msp_status msp_refiner_set_weights(msp_ctx* ctx, msp_refiner* r, const float* W1
  * (mean (3), scale / 0.1 (3), unit quaternion with w >= 0 (4), opacity, rgb (3), K / 16). */
 msp_status msp_refiner_features(msp_ctx* ctx, const msp_gaussians* g, int K, float* x);
 /* y [n][n_out] = W3 relu(W2 relu(W1 x + b1) + b2) + b3 with x, W1, W2, W3 and
- * both hidden activations rounded to bfloat16 before each product. */
+ * both hidden activations rounded to bfloat16 before each product. x is read
+ * in 16-byte vectors and must be 16-byte aligned (MSP_EINVAL otherwise). */
 msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* x, int64_t n, float* y);
 /* Gradients of sum(y * dy) over the n samples (forward recomputed from x):
  * dW1 [256][15], db1 [256], dW2 [256][256], db2 [256], dW3 [n_out][256],

@@ -635,6 +635,7 @@ msp_status msp_refiner_features(msp_ctx* ctx, const msp_gaussians* g, int K, flo
 msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* x, int64_t n, float* y) {
   if (!ctx) return MSP_EINVAL;
   if (!r || n < 0 || (n > 0 && (!x || !y))) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_forward: bad argument");
+  if (((uintptr_t)x & 15) != 0) return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_forward: x not 16-byte aligned");
   DeviceGuard dg(ctx->device);
   MSP_TIMED(ctx, ST_OTHER, launch_refiner_forward(ctx->stream, r, x, n, y, ctx->n_cu));
   return MSP_OK;

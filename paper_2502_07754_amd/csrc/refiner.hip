@@ -4,9 +4,12 @@
 // Gaussian's fan so fine-tuning starts nearer its optimum; a zero last layer
 // reproduces the plain conversion.
 //
-// Forward: one wavefront per 16 samples, all three layers fused; the hidden
-// activations go through a per-wave LDS tile (bfloat16) to turn the MFMA
-// output layout into the next layer's operand layout. Weights are read from
+// Training forward: one wavefront per 16 samples, all three layers fused; the
+// hidden activations go through a per-wave LDS tile (bfloat16) to turn the MFMA
+// output layout into the next layer's operand layout (the backward needs them
+// there anyway). Inference keeps them in registers by computing each layer
+// transposed, over weight copies whose k-blocks are stored in the matching
+// slot order (k_mlp_infer). Weights are read from
 // global memory (L2-resident, 155 KB in bfloat16) as 16-byte operand
 // fragments, pre-packed as [out][in] rows so every fragment is contiguous.
 // Backward: the same tile recomputes the forward, then dH2 = (dY W3) * [h2>0],
@@ -32,12 +35,9 @@ constexpr int HID = 256;
 constexpr int LDH = HID + 8;  // LDS row stride (bf16 elements) of a 16 x 256 tile
 constexpr int WPB = 2;        // waves per block
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u | 0x00400000u) >> 16);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (NaN stays a quiet NaN): one
+// v_cvt_pk_bf16_f32 on gfx950.
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ bf16x8 frag_from_u4(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -46,16 +46,20 @@ __device__ __forceinline__ bf16x8 load_frag(const uint16_t* p) {  // 16-byte ali
 }
 
 __device__ __forceinline__ bf16x8 pack8(const float* v) {
-  u32x4 u;
-  u.x = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
-  u.y = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
-  u.z = (uint32_t)bf16_rne(v[4]) | ((uint32_t)bf16_rne(v[5]) << 16);
-  u.w = (uint32_t)bf16_rne(v[6]) | ((uint32_t)bf16_rne(v[7]) << 16);
-  return frag_from_u4(u);
+  const bf16x8 b = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
+                    (__bf16)v[4], (__bf16)v[5], (__bf16)v[6], (__bf16)v[7]};
+  return b;
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Feature held by slot s = 8q + p of a 32-wide k-block in the transposed
+// inference layout: slots 8q..8q+3 are features 4q..4q+3, slots 8q+4..8q+7
+// are features 16+4q..16+4q+3.
+__host__ __device__ constexpr int slot_feature(int s) {  // s = 8q + p within a 32-wide k-block
+  return (s & 7) < 4 ? 4 * (s >> 3) + (s & 7) : 16 + 4 * (s >> 3) + (s & 7) - 4;
 }
 
 struct MlpArgs {
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ A, co
 // ---- packing: fp32 masters -> padded bf16 operands and transposed copies ----
 __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ W3,
                        const float* __restrict__ b3, int n_in, int n_out, uint16_t* w1, uint16_t* w2, uint16_t* w3,
-                       uint16_t* w2t, uint16_t* w3t, float* b3p) {
+                       uint16_t* w2t, uint16_t* w3t, uint16_t* w2p, uint16_t* w3p, float* b3p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < HID * 32) {
     const int o = i / 32, k = i % 32;
@@ -271,11 +275,14 @@ __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W
     w3t[i] = oo < n_out ? bf16_rne(W3[oo * HID + j]) : 0;
     const int o3 = i / HID, k3 = i % HID;  // w3[o][k]
     w3[i] = o3 < n_out ? bf16_rne(W3[o3 * HID + k3]) : 0;
+    const int f3 = (k3 & ~31) + slot_feature(k3 & 31);  // w3p[o][slot]
+    w3p[i] = o3 < n_out ? bf16_rne(W3[o3 * HID + f3]) : 0;
   }
   if (i < HID * HID) {
     w2[i] = bf16_rne(W2[i]);
     const int a = i / HID, b = i % HID;  // w2t[a][b] = W2[b][a]
     w2t[i] = bf16_rne(W2[b * HID + a]);
+    w2p[i] = bf16_rne(W2[a * HID + (b & ~31) + slot_feature(b & 31)]);  // w2p[o][slot]
   }
   if (i < 32) b3p[i] = i < n_out ? b3[i] : 0.f;
 }
@@ -525,108 +532,128 @@ __global__ void k_vec_mse_sum(const double* __restrict__ part, int nb, double sc
 
 inline unsigned gfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
-// Inference: a wavefront takes RT row tiles (16 RT samples) at a time and
-// applies every weight fragment it loads to all of them, so the weights (read
-// from L2) are read once per 16 RT samples instead of once per 16. The same
-// operations in the same order as the training forward (bit-identical output);
-// each row tile's LDS buffer holds H1, then H2 once H1 is in registers.
+// Inference computes every layer transposed, D = W H^T (output features x
+// samples): the D fragments of output blocks 2c and 2c + 1 then hold, in lane
+// (sample r, q), features 32c + 4q + e and 32c + 16 + 4q + e (e = 0..3), which
+// is the B-operand layout of the k-block c of the next layer once the slots
+// 8q..8q+7 of that block are read as those eight features. The packed copies
+// w2p and w3p store each row's k-blocks in that slot order, so the hidden
+// activations stay in registers (no LDS) and each product is over the same
+// 32 features as in the training forward (the same sums; only the order in
+// which the matrix core adds the 32 products of a block may differ).
+
+__device__ __forceinline__ f32x4 ld_f4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+
+__device__ __forceinline__ bf16x8 relu_pack(f32x4 a, f32x4 b) {
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    v[e] = fmaxf(a[e], 0.f);
+    v[4 + e] = fmaxf(b[e], 0.f);
+  }
+  return pack8(v);
+}
+
+// A wavefront takes RT row tiles (16 RT samples) at a time and applies every
+// weight fragment it loads to all of them; the next output block's W2
+// fragments are loaded while the current block's products run. Layer 3 is
+// folded into layer 2: each pair of layer-2 output blocks, once rectified and
+// rounded, is one k-block of layer 3.
 template <int RT>
-__global__ __launch_bounds__(64 * WPB) void k_mlp_fwd(const float* __restrict__ x, int64_t N, MlpArgs m,
-                                                      float* __restrict__ y) {
-  __shared__ uint16_t lds[WPB][RT][16 * LDH];
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RT <= 2 ? 2 : 1))) void k_mlp_infer(const float* __restrict__ x, int64_t N, MlpArgs m,
+                                                        const uint16_t* __restrict__ w2p,
+                                                        const uint16_t* __restrict__ w3p, float* __restrict__ y) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const int64_t groups = (N + 16 * RT - 1) / (16 * RT);
   for (int64_t gi = (int64_t)blockIdx.x * WPB + wid; gi < groups; gi += (int64_t)gridDim.x * WPB) {
     const int64_t s0 = gi * 16 * RT;
-    // ---- layer 1 ----
-    bf16x8 ax[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int64_t srow = s0 + 16 * rt + r;
-      float xv[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) xv[e] = (q == 0 || q == 1) && srow < N ? x[srow * 16 + 8 * q + e] : 0.f;
-      ax[rt] = pack8(xv);
-    }
-#pragma unroll 2
-    for (int nb = 0; nb < 16; ++nb) {
-      const bf16x8 w = load_frag(m.w1 + (nb * 16 + r) * 32 + 8 * q);
-      const float b = m.b1[nb * 16 + r];
+    // ---- layer 1: H1^T = relu(W1 X^T + b1), natural k order (x is the B operand) ----
+    bf16x8 h1[RT][8];
+    {
+      bf16x8 xb[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(ax[rt], w, acc);
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
-        store_tile(lds[wid][rt], nb, lane, v);
+        const int64_t srow = s0 + 16 * rt + r;
+        f32x4 lo = zero, hi = zero;
+        if (q < 2 && srow < N) {
+          lo = ld_f4(x + srow * 16 + 8 * q);
+          hi = ld_f4(x + srow * 16 + 8 * q + 4);
+        }
+        const float xv[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        xb[rt] = pack8(xv);
       }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    // ---- layer 2 ----
-    bf16x8 a[RT][8];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(lds[wid][rt], kb, lane);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    for (int nb = 0; nb < 16; ++nb) {
-      f32x4 acc[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const uint16_t* wb = m.w2 + (nb * 16 + r) * HID + 8 * q;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        const bf16x8 w = load_frag(wb + kb * 32);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(a[rt][kb], w, acc[rt]);
-      }
-      const float b = m.b2[nb * 16 + r];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[rt][e] + b, 0.f);
-        store_tile(lds[wid][rt], nb, lane, v);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    // ---- layer 3 ----
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(lds[wid][rt], kb, lane);
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      f32x4 acc[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const uint16_t* wb = m.w3 + (nb * 16 + r) * HID + 8 * q;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        const bf16x8 w = load_frag(wb + kb * 32);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(a[rt][kb], w, acc[rt]);
-      }
-      const int j = nb * 16 + r;
-      if (j < m.n_out) {
-        const float b = m.b3[j];
+      for (int c = 0; c < 8; ++c) {
+        const bf16x8 wa = load_frag(m.w1 + (32 * c + r) * 32 + 8 * q);
+        const bf16x8 wb = load_frag(m.w1 + (32 * c + 16 + r) * 32 + 8 * q);
+        const f32x4 ba = ld_f4(m.b1 + 32 * c + 4 * q), bb = ld_f4(m.b1 + 32 * c + 16 + 4 * q);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t sidx = s0 + 16 * rt + 4 * q + e;
-            if (sidx < N) y[sidx * m.n_out + j] = acc[rt][e] + b;
-          }
+          h1[rt][c] = relu_pack(mfma(wa, xb[rt], zero) + ba, mfma(wb, xb[rt], zero) + bb);
+        if (c % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bounds the loads hoisted ahead
       }
     }
-    // the next group's layer 1 overwrites the tiles this group just read
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // ---- layers 2 and 3 ----
+    bf16x8 w[8];  // W2 fragments of the output block in flight
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) w[kb] = load_frag(w2p + r * HID + kb * 32 + 8 * q);
+    f32x4 acc3[RT][2];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc3[rt][0] = acc3[rt][1] = zero;
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 w3a = load_frag(w3p + r * HID + c * 32 + 8 * q);
+      const bf16x8 w3b = load_frag(w3p + (16 + r) * HID + c * 32 + 8 * q);
+      f32x4 d[2][RT];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int nb = 2 * c + h;
+        const int nn = nb < 15 ? nb + 1 : nb;  // the last block reloads itself
+        // loads complete in issue order: the bias goes first so that waiting
+        // for it does not wait for the prefetch
+        const f32x4 b = ld_f4(m.b2 + nb * 16 + 4 * q);
+        bf16x8 wn[8];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) wn[kb] = load_frag(w2p + (nn * 16 + r) * HID + kb * 32 + 8 * q);
+        // keeps these loads ahead of the block's products (under register
+        // pressure the scheduler would otherwise sink each next to its use)
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4 acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = zero;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(w[kb], h1[rt][kb], acc[rt]);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) d[h][rt] = acc[rt] + b;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) w[kb] = wn[kb];
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const bf16x8 h2 = relu_pack(d[0][rt], d[1][rt]);
+        acc3[rt][0] = mfma(w3a, h2, acc3[rt][0]);
+        acc3[rt][1] = mfma(w3b, h2, acc3[rt][1]);
+      }
+    }
+    // ---- output: lane (sample r, q) holds outputs 16 h + 4q + e ----
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x4 b = ld_f4(m.b3 + 16 * h + 4 * q);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int64_t srow = s0 + 16 * rt + r;
+        if (srow >= N) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 16 * h + 4 * q + e;
+          if (j < m.n_out) y[srow * m.n_out + j] = acc3[rt][h][e] + b[e];
+        }
+      }
+    }
   }
 }
 
@@ -634,7 +661,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_fwd(const float* __restrict__ 
 
 struct msp_refiner {
   int n_in = 15, n_out = 0;
-  DevBuf w1, w2, w3, w2t, w3t, b1, b2, b3p, train, grads, part;
+  DevBuf w1, w2, w3, w2t, w3t, w2p, w3p, b1, b2, b3p, train, grads, part;
   int64_t train_pad = 0;
 };
 
@@ -652,7 +679,7 @@ hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, c
                                const float* b2, const float* W3, const float* b3) {
   hipLaunchKernelGGL(k_pack, dim3(gfor(HID * HID)), dim3(256), 0, s, W1, W2, W3, b3, r->n_in, r->n_out,
                      (uint16_t*)r->w1.p, (uint16_t*)r->w2.p, (uint16_t*)r->w3.p, (uint16_t*)r->w2t.p,
-                     (uint16_t*)r->w3t.p, (float*)r->b3p.p);
+                     (uint16_t*)r->w3t.p, (uint16_t*)r->w2p.p, (uint16_t*)r->w3p.p, (float*)r->b3p.p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(r->b1.p, b1, 4 * HID, hipMemcpyDeviceToDevice, s);
@@ -681,7 +708,7 @@ static unsigned tile_grid(int64_t N, int n_cu) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-constexpr int kFwdRT = 4;  // row tiles per wavefront in inference
+constexpr int kFwdRT = 6;  // row tiles per wavefront in inference
 
 hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu) {
   if (N == 0) return hipSuccess;
@@ -689,7 +716,8 @@ hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const flo
   int64_t g = (groups + WPB - 1) / WPB;
   const int64_t cap = (int64_t)n_cu * 8;
   g = g < 1 ? 1 : (g > cap ? cap : g);
-  hipLaunchKernelGGL(k_mlp_fwd<kFwdRT>, dim3((unsigned)g), dim3(64 * WPB), 0, s, x, N, margs(r), y);
+  hipLaunchKernelGGL(k_mlp_infer<kFwdRT>, dim3((unsigned)g), dim3(64 * WPB), 0, s, x, N, margs(r),
+                     (const uint16_t*)r->w2p.p, (const uint16_t*)r->w3p.p, y);
   return hipGetLastError();
 }
 
@@ -808,7 +836,8 @@ int refiner_alloc(msp_ctx* ctx, msp_refiner* r) {
   int rc;
   if ((rc = msp_ensure(ctx, r->part, 8 * 1024)) || (rc = msp_ensure(ctx, r->w1, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2, 2 * HID * HID)) ||
       (rc = msp_ensure(ctx, r->w3, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->w2t, 2 * HID * HID)) ||
-      (rc = msp_ensure(ctx, r->w3t, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
+      (rc = msp_ensure(ctx, r->w3t, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2p, 2 * HID * HID)) ||
+      (rc = msp_ensure(ctx, r->w3p, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
       (rc = msp_ensure(ctx, r->b2, 4 * HID)) || (rc = msp_ensure(ctx, r->b3p, 4 * 32)) ||
       (rc = msp_ensure(ctx, r->grads, 4 * HID * 32 * 2)))
     return rc;
@@ -820,7 +849,7 @@ int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N) {
 }
 
 void refiner_free_bufs(msp_refiner* r) {
-  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part};
+  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->w2p, &r->w3p, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part};
   for (DevBuf* x : b)
     if (x->p) (void)hipFree(x->p);
 }
