@@ -9,7 +9,7 @@
 // output layout into the next layer's operand layout (the backward needs them
 // there anyway). Inference keeps them in registers by computing each layer
 // transposed, over weight copies whose k-blocks are stored in the matching
-// slot order (k_mlp_infer). Weights are read from
+// slot order, held in LDS (k_mlp_infer_lds). Training reads its weights from
 // global memory (L2-resident, 155 KB in bfloat16) as 16-byte operand
 // fragments, pre-packed as [out][in] rows so every fragment is contiguous.
 // Backward: the same tile recomputes the forward, then dH2 = (dY W3) * [h2>0],
@@ -538,7 +538,7 @@ inline unsigned gfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b
 // is the B-operand layout of the k-block c of the next layer once the slots
 // 8q..8q+7 of that block are read as those eight features. The packed copies
 // w2p and w3p store each row's k-blocks in that slot order, so the hidden
-// activations stay in registers (no LDS) and each product is over the same
+// activations stay in registers and each product is over the same
 // 32 features as in the training forward (the same sums; only the order in
 // which the matrix core adds the 32 products of a block may differ).
 
@@ -554,20 +554,45 @@ __device__ __forceinline__ bf16x8 relu_pack(f32x4 a, f32x4 b) {
   return pack8(v);
 }
 
-// A wavefront takes RT row tiles (16 RT samples) at a time and applies every
-// weight fragment it loads to all of them; the next output block's W2
-// fragments are loaded while the current block's products run. Layer 3 is
-// folded into layer 2: each pair of layer-2 output blocks, once rectified and
-// rounded, is one k-block of layer 3.
+// relu, then bfloat16 pairs: elements 0..3 of an operand fragment
+__device__ __forceinline__ uint2 relu_pack4(f32x4 a) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 lo = {(__bf16)fmaxf(a[0], 0.f), (__bf16)fmaxf(a[1], 0.f)};
+  const bf16x2 hi = {(__bf16)fmaxf(a[2], 0.f), (__bf16)fmaxf(a[3], 0.f)};
+  return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+}
+
+// W2 and W3 (slot-ordered copies) stay resident in LDS: one block per CU
+// copies them once (rows padded to 528 bytes, so the 16 lanes r of a fragment
+// read hit distinct bank groups), then each of its wavefronts runs through
+// groups of RT row tiles (16 RT samples) on its own, applying every weight
+// fragment it reads to all RT tiles; layer 3 is folded into layer 2 (each
+// pair of layer-2 output blocks, once rectified and rounded, is one k-block
+// of layer 3). Fragments come from LDS rather than L2, so no registers hold
+// prefetched weights and a SIMD runs three wavefronts; W1 (16 KB) and the
+// biases are read through L1.
+constexpr int kInferWaves = 12;  // wavefronts per block (three per SIMD)
+constexpr int LDW = HID + 8;     // LDS row stride (bf16 elements) of the weight copies
+constexpr int kInferRows = HID + 32;  // W2 rows, then W3 rows
+
 template <int RT>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RT <= 2 ? 2 : 1))) void k_mlp_infer(const float* __restrict__ x, int64_t N, MlpArgs m,
-                                                        const uint16_t* __restrict__ w2p,
-                                                        const uint16_t* __restrict__ w3p, float* __restrict__ y) {
+__global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_eu(kInferWaves / 4))) void k_mlp_infer_lds(
+    const float* __restrict__ x, int64_t N, MlpArgs m, const uint16_t* __restrict__ w2p,
+    const uint16_t* __restrict__ w3p, float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) uint16_t wl[kInferRows * LDW];
+  for (int i = threadIdx.x; i < kInferRows * 32; i += blockDim.x) {
+    const int row = i >> 5, ch = i & 31;  // 16-byte chunk ch of the row
+    const uint16_t* src = row < HID ? w2p + row * HID + ch * 8 : w3p + (row - HID) * HID + ch * 8;
+    *reinterpret_cast<u32x4*>(wl + row * LDW + ch * 8) = *reinterpret_cast<const u32x4*>(src);
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const int64_t groups = (N + 16 * RT - 1) / (16 * RT);
-  for (int64_t gi = (int64_t)blockIdx.x * WPB + wid; gi < groups; gi += (int64_t)gridDim.x * WPB) {
+  const int64_t stride = (int64_t)gridDim.x * kInferWaves;
+  const uint16_t* wr = wl + r * LDW + 8 * q;  // this lane's fragment base
+  for (int64_t gi = (int64_t)blockIdx.x * kInferWaves + wid; gi < groups; gi += stride) {
     const int64_t s0 = gi * 16 * RT;
     // ---- layer 1: H1^T = relu(W1 X^T + b1), natural k order (x is the B operand) ----
     bf16x8 h1[RT][8];
@@ -596,45 +621,34 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RT <= 
       }
     }
     // ---- layers 2 and 3 ----
-    bf16x8 w[8];  // W2 fragments of the output block in flight
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) w[kb] = load_frag(w2p + r * HID + kb * 32 + 8 * q);
     f32x4 acc3[RT][2];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc3[rt][0] = acc3[rt][1] = zero;
 #pragma unroll 1
     for (int c = 0; c < 8; ++c) {
-      const bf16x8 w3a = load_frag(w3p + r * HID + c * 32 + 8 * q);
-      const bf16x8 w3b = load_frag(w3p + (16 + r) * HID + c * 32 + 8 * q);
-      f32x4 d[2][RT];
+      uint2 h2p[2][RT];  // rectified bf16 halves: features 32c + 4q + e, then 32c + 16 + 4q + e
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int nb = 2 * c + h;
-        const int nn = nb < 15 ? nb + 1 : nb;  // the last block reloads itself
-        // loads complete in issue order: the bias goes first so that waiting
-        // for it does not wait for the prefetch
         const f32x4 b = ld_f4(m.b2 + nb * 16 + 4 * q);
-        bf16x8 wn[8];
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) wn[kb] = load_frag(w2p + (nn * 16 + r) * HID + kb * 32 + 8 * q);
-        // keeps these loads ahead of the block's products (under register
-        // pressure the scheduler would otherwise sink each next to its use)
-        __builtin_amdgcn_sched_barrier(0);
         f32x4 acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = zero;
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
+        for (int kb = 0; kb < 8; ++kb) {
+          const bf16x8 w = load_frag(wr + nb * 16 * LDW + kb * 32);
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(w[kb], h1[rt][kb], acc[rt]);
+          for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(w, h1[rt][kb], acc[rt]);
+        }
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) d[h][rt] = acc[rt] + b;
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) w[kb] = wn[kb];
+        for (int rt = 0; rt < RT; ++rt) h2p[h][rt] = relu_pack4(acc[rt] + b);
       }
+      const bf16x8 w3a = load_frag(wr + HID * LDW + c * 32);
+      const bf16x8 w3b = load_frag(wr + (HID + 16) * LDW + c * 32);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const bf16x8 h2 = relu_pack(d[0][rt], d[1][rt]);
+        const u32x4 u = {h2p[0][rt].x, h2p[0][rt].y, h2p[1][rt].x, h2p[1][rt].y};
+        const bf16x8 h2 = frag_from_u4(u);
         acc3[rt][0] = mfma(w3a, h2, acc3[rt][0]);
         acc3[rt][1] = mfma(w3b, h2, acc3[rt][1]);
       }
@@ -708,15 +722,14 @@ static unsigned tile_grid(int64_t N, int n_cu) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-constexpr int kFwdRT = 6;  // row tiles per wavefront in inference
+constexpr int kInferRT = 2;  // row tiles per wavefront in inference
 
 hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu) {
   if (N == 0) return hipSuccess;
-  const int64_t groups = (N + 16 * kFwdRT - 1) / (16 * kFwdRT);
-  int64_t g = (groups + WPB - 1) / WPB;
-  const int64_t cap = (int64_t)n_cu * 8;
-  g = g < 1 ? 1 : (g > cap ? cap : g);
-  hipLaunchKernelGGL(k_mlp_infer<kFwdRT>, dim3((unsigned)g), dim3(64 * WPB), 0, s, x, N, margs(r),
+  const int64_t groups = (N + 16 * kInferRT - 1) / (16 * kInferRT);
+  int64_t g = (groups + kInferWaves - 1) / kInferWaves;
+  g = g < 1 ? 1 : (g > n_cu ? n_cu : g);  // the LDS copy of the weights allows one block per CU
+  hipLaunchKernelGGL(k_mlp_infer_lds<kInferRT>, dim3((unsigned)g), dim3(64 * kInferWaves), 0, s, x, N, margs(r),
                      (const uint16_t*)r->w2p.p, (const uint16_t*)r->w3p.p, y);
   return hipGetLastError();
 }

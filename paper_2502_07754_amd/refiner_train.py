@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--load-weights", default="", help="refiner weights (.npz) instead of training")
     ap.add_argument("--save-weights", default="")
     ap.add_argument("--infer-n", type=int, default=1_000_000)
+    ap.add_argument("--infer-only", action="store_true",
+                    help="time the inference forward of a randomly initialised refiner (no training)")
     ap.add_argument("--ft-n", type=int, default=0, help="Gaussians of the time-to-MSE run (0: skip)")
     ap.add_argument("--ft-views", type=int, default=16)
     ap.add_argument("--ft-res", type=int, nargs=2, default=(1920, 1080))
@@ -267,7 +269,14 @@ def main():
         print(*a, flush=True)
 
     res = {}
-    if args.load_weights:
+    if args.infer_only:
+        p = init_params(3 * 8 + 4, seed=0)
+        gen = torch.Generator(device="cuda").manual_seed(1)
+        p["W3"] = (torch.randn(p["W3"].shape, generator=gen, device="cuda") * math.sqrt(2 / HIDDEN)).contiguous()
+        R = Refiner(3 * 8 + 4)
+        R.set_weights(p)
+        args.ft_n = 0
+    elif args.load_weights:
         R, p = load_refiner(args.load_weights)
     else:
         if not args.skip_pairs:

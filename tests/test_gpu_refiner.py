@@ -31,6 +31,41 @@ def test_forward_parity(gpu, N):
     assert err <= 1e-3 * np.abs(ref).max()
 
 
+def test_forward_parity_persistent_grid(gpu):
+    """Enough samples that every wavefront of the inference grid (one block
+    per CU) takes several 32-sample groups, with a ragged last group: every
+    row against the oracle. Rows agree to float32 accumulation order except
+    where a hidden pre-activation lies so close to a bfloat16 rounding
+    boundary that the float32 sum and the float64 sum round it to neighbouring
+    bfloat16 values (one unit in the last place of one hidden unit, about 0.1%
+    of rows): the bulk is held to 1e-6 of the output scale, the rare rows to a
+    few such flips."""
+    import torch
+    N = 250_003
+    p = om.init_params(28, seed=5, zero_last=False)
+    x = np.random.default_rng(5).normal(size=(N, 15)).astype(np.float32)
+    x16 = np.concatenate([x, np.zeros((N, 1), np.float32)], 1)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    y = r.forward(torch.from_numpy(x16).cuda()).cpu().numpy()
+    ref, _ = om.forward(p, x.astype(np.float64))
+    e = np.abs(y - ref).max(1) / np.abs(ref).max()
+    print("row error quantiles (50, 99, 99.9, max)", np.quantile(e, [0.5, 0.99, 0.999, 1.0]), flush=True)
+    assert np.quantile(e, 0.99) <= 1e-6
+    assert np.mean(e > 1e-5) <= 0.01
+    assert e.max() <= 3e-3
+
+
+def test_forward_rejects_unaligned_input(gpu):
+    import torch
+    from paper_2502_07754_amd._lib import MspError
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(om.init_params(28, seed=1, zero_last=False)))
+    buf = torch.zeros(65 * 16, dtype=torch.float32, device="cuda")
+    with pytest.raises(MspError, match="aligned"):
+        r.forward(buf[1:1 + 64 * 16].view(64, 16))
+
+
 @pytest.mark.parametrize("N", [50, 2048, 5000])
 def test_backward_parity(gpu, N):
     import torch
