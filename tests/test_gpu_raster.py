@@ -140,10 +140,12 @@ def test_tile_lists_bit_exact_config2(gpu):
     assert np.array_equal(keys, rkeys)
 
 
-@pytest.mark.parametrize("n,seed", [(2000, 41), (6000, 42)])
+@pytest.mark.parametrize("n,seed", [(2000, 41), (6000, 42), (9000, 43), (16000, 45)])
 def test_tile_lists_bit_exact_long_lists(gpu, n, seed):
-    """Large Gaussians over a small image: tile lists of ~9k and ~27k entries,
-    longer than one sorting chunk, so they go through the pairwise merges."""
+    """Large Gaussians over a small image: tile lists of ~9k to ~71k entries,
+    longer than one sorting chunk, so they go through the pairwise merges
+    (several passes, and odd run counts that carry a run through a pass
+    unmerged)."""
     g = scenes.gaussians(n, seed, 0.3, 0.6, flat=True)
     f = _oracle_faces(g, 8, 2.0)
     cams = scenes.ring_cameras(1, 64, 48)
