@@ -108,9 +108,8 @@ __device__ __forceinline__ float col_sum(const float v[4]) {
   return s;
 }
 
-template <bool BWD>
-__global__ __launch_bounds__(64 * WPB) void k_mlp_tile(const float* __restrict__ x, int64_t N, MlpArgs m,
-                                                       float* __restrict__ y, TrainBufs tb) {
+__global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict__ x, int64_t N, MlpArgs m,
+                                                        TrainBufs tb) {
   __shared__ uint16_t lds[WPB][3][16 * LDH];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
@@ -126,7 +125,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_tile(const float* __restrict__
 #pragma unroll
     for (int e = 0; e < 8; ++e) xv[e] = (q == 0 || q == 1) && srow < N ? x[srow * 16 + 8 * q + e] : 0.f;
     const bf16x8 ax = pack8(xv);
-    if (BWD && q < 2) {  // x^T for dW1 (features 0..15)
+    if (q < 2) {  // x^T for dW1 (features 0..15)
 #pragma unroll
       for (int e = 0; e < 8; ++e) tb.xt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(xv[e]);
     }
@@ -139,7 +138,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_tile(const float* __restrict__
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
       store_tile(H1s, nb, lane, v);
-      if (BWD) store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+      store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -157,32 +156,10 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_tile(const float* __restrict__
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
       store_tile(H2s, nb, lane, v);
-      if (BWD) store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+      store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    // ---- layer 3 ----
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(H2s, kb, lane);
-    if (!BWD) {
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const uint16_t* wb = m.w3 + (nb * 16 + r) * HID + 8 * q;
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
-        const int j = nb * 16 + r;
-        if (j < m.n_out) {
-          const float b = m.b3[j];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t s = s0 + 4 * q + e;
-            if (s < N) y[s * m.n_out + j] = acc[e] + b;
-          }
-        }
-      }
-      continue;
-    }
     // ---- backward: dY (K = 32, outputs padded) ----
     float dv[8];
 #pragma unroll
@@ -766,8 +743,7 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   if ((e = hipMemsetAsync(g1, 0, 4 * (HID * 32 * 2), s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
   if (N > 0) {
-    hipLaunchKernelGGL(k_mlp_tile<true>, dim3(tile_grid(N, n_cu)), dim3(64 * WPB), 0, s, x, N, margs(r),
-                       (float*)nullptr, tb);
+    hipLaunchKernelGGL(k_mlp_train, dim3(tile_grid(N, n_cu)), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t chunk = 2048;
     const unsigned ny = (unsigned)((np + chunk - 1) / chunk);
