@@ -546,8 +546,9 @@ __device__ __forceinline__ uint2 relu_pack4(f32x4 a) {
 // fragment it reads to all RT tiles; layer 3 is folded into layer 2 (each
 // pair of layer-2 output blocks, once rectified and rounded, is one k-block
 // of layer 3). Fragments come from LDS rather than L2, so no registers hold
-// prefetched weights and a SIMD runs three wavefronts; W1 (16 KB) and the
-// biases are read through L1.
+// prefetched weights and a SIMD runs three wavefronts. The biases and the
+// nonzero half of W1 (input features 0..15, 8 KB) sit in LDS too, so after
+// the copy the only global traffic is the inputs and the outputs.
 constexpr int kInferWaves = 12;  // wavefronts per block (three per SIMD)
 constexpr int LDW = HID + 8;     // LDS row stride (bf16 elements) of the weight copies
 constexpr int kInferRows = HID + 32;  // W2 rows, then W3 rows
@@ -557,11 +558,17 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
     const float* __restrict__ x, int64_t N, MlpArgs m, const uint16_t* __restrict__ w2p,
     const uint16_t* __restrict__ w3p, float* __restrict__ y) {
   __shared__ __attribute__((aligned(16))) uint16_t wl[kInferRows * LDW];
+  __shared__ __attribute__((aligned(16))) float bl[2 * HID + 32];  // b1, b2, b3 (padded to 32)
+  __shared__ __attribute__((aligned(16))) uint16_t w1l[HID * 16];   // W1 rows, input features 0..15
   for (int i = threadIdx.x; i < kInferRows * 32; i += blockDim.x) {
     const int row = i >> 5, ch = i & 31;  // 16-byte chunk ch of the row
     const uint16_t* src = row < HID ? w2p + row * HID + ch * 8 : w3p + (row - HID) * HID + ch * 8;
     *reinterpret_cast<u32x4*>(wl + row * LDW + ch * 8) = *reinterpret_cast<const u32x4*>(src);
   }
+  for (int i = threadIdx.x; i < HID * 2; i += blockDim.x)  // two 16-byte chunks per row
+    *reinterpret_cast<u32x4*>(w1l + i * 8) = *reinterpret_cast<const u32x4*>(m.w1 + (i >> 1) * 32 + (i & 1) * 8);
+  for (int i = threadIdx.x; i < 2 * HID + 32; i += blockDim.x)
+    bl[i] = i < HID ? m.b1[i] : i < 2 * HID ? m.b2[i - HID] : m.b3[i - 2 * HID];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
@@ -569,7 +576,21 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
   const int64_t groups = (N + 16 * RT - 1) / (16 * RT);
   const int64_t stride = (int64_t)gridDim.x * kInferWaves;
   const uint16_t* wr = wl + r * LDW + 8 * q;  // this lane's fragment base
-  for (int64_t gi = (int64_t)blockIdx.x * kInferWaves + wid; gi < groups; gi += stride) {
+  // a group's inputs in the B-operand layout (lane (sample r, q < 2) holds
+  // features 8q..8q+7), loaded one group ahead: the loop's only other global
+  // accesses are the output stores, issued after them
+  int64_t gi = (int64_t)blockIdx.x * kInferWaves + wid;
+  f32x4 xlo[RT], xhi[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t srow = gi * 16 * RT + 16 * rt + r;
+    xlo[rt] = xhi[rt] = zero;
+    if (gi < groups && q < 2 && srow < N) {
+      xlo[rt] = ld_f4(x + srow * 16 + 8 * q);
+      xhi[rt] = ld_f4(x + srow * 16 + 8 * q + 4);
+    }
+  }
+  for (; gi < groups; gi += stride) {
     const int64_t s0 = gi * 16 * RT;
     // ---- layer 1: H1^T = relu(W1 X^T + b1), natural k order (x is the B operand) ----
     bf16x8 h1[RT][8];
@@ -577,20 +598,27 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
       bf16x8 xb[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const int64_t srow = s0 + 16 * rt + r;
-        f32x4 lo = zero, hi = zero;
-        if (q < 2 && srow < N) {
-          lo = ld_f4(x + srow * 16 + 8 * q);
-          hi = ld_f4(x + srow * 16 + 8 * q + 4);
-        }
-        const float xv[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        const float xv[8] = {xlo[rt][0], xlo[rt][1], xlo[rt][2], xlo[rt][3],
+                             xhi[rt][0], xhi[rt][1], xhi[rt][2], xhi[rt][3]};
         xb[rt] = pack8(xv);
+      }
+      const int64_t gn = gi + stride;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int64_t srow = gn * 16 * RT + 16 * rt + r;
+        xlo[rt] = xhi[rt] = zero;
+        if (gn < groups && q < 2 && srow < N) {
+          xlo[rt] = ld_f4(x + srow * 16 + 8 * q);
+          xhi[rt] = ld_f4(x + srow * 16 + 8 * q + 4);
+        }
       }
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const bf16x8 wa = load_frag(m.w1 + (32 * c + r) * 32 + 8 * q);
-        const bf16x8 wb = load_frag(m.w1 + (32 * c + 16 + r) * 32 + 8 * q);
-        const f32x4 ba = ld_f4(m.b1 + 32 * c + 4 * q), bb = ld_f4(m.b1 + 32 * c + 16 + 4 * q);
+        // lanes q >= 2 carry input slots 16..31, where x is zero: they read the
+        // same weights as q - 2, and their products vanish
+        const bf16x8 wa = load_frag(w1l + (32 * c + r) * 16 + 8 * (q & 1));
+        const bf16x8 wb = load_frag(w1l + (32 * c + 16 + r) * 16 + 8 * (q & 1));
+        const f32x4 ba = ld_f4(bl + 32 * c + 4 * q), bb = ld_f4(bl + 32 * c + 16 + 4 * q);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
           h1[rt][c] = relu_pack(mfma(wa, xb[rt], zero) + ba, mfma(wb, xb[rt], zero) + bb);
@@ -607,7 +635,7 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int nb = 2 * c + h;
-        const f32x4 b = ld_f4(m.b2 + nb * 16 + 4 * q);
+        const f32x4 b = ld_f4(bl + HID + nb * 16 + 4 * q);
         f32x4 acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = zero;
@@ -633,7 +661,7 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
     // ---- output: lane (sample r, q) holds outputs 16 h + 4q + e ----
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const f32x4 b = ld_f4(m.b3 + 16 * h + 4 * q);
+      const f32x4 b = ld_f4(bl + 2 * HID + 16 * h + 4 * q);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int64_t srow = s0 + 16 * rt + r;
