@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--infer-n", type=int, default=1_000_000)
     ap.add_argument("--infer-only", action="store_true",
                     help="time the inference forward of a randomly initialised refiner (no training)")
+    ap.add_argument("--train-n", type=int, default=0,
+                    help="samples of a timed training step (backward, and forward + backward + Adam); 0: skip")
     ap.add_argument("--ft-n", type=int, default=0, help="Gaussians of the time-to-MSE run (0: skip)")
     ap.add_argument("--ft-views", type=int, default=16)
     ap.add_argument("--ft-res", type=int, nargs=2, default=(1920, 1080))
@@ -325,6 +327,36 @@ def main():
                                 frac_of_bf16_peak=flop / dt / 2.5e15)
         log(json.dumps(res["inference"]))
         del xi
+    if args.train_n:
+        # one training step on random output gradients: the MFMA backward (forward recomputed,
+        # dH2, dH1, split-K weight gradients), then the whole step with Adam and the repack
+        g = scenes.gaussians(args.train_n, 8, 0.01, 0.1, flat=True)
+        xt = refiner_features(to_gpu(g), 8)
+        gen = torch.Generator(device="cuda").manual_seed(2)
+        dy = torch.randn((args.train_n, R.n_out), generator=gen, device="cuda")
+        m = {k: torch.zeros_like(v) for k, v in p.items()}
+        v = {k: torch.zeros_like(t) for k, t in p.items()}
+        R.backward(xt, dy)
+        torch.cuda.synchronize()
+        reps = 10
+        t = time.perf_counter()
+        for _ in range(reps):
+            R.backward(xt, dy)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        for s in range(1, reps + 1):
+            R.forward(xt)
+            gr = R.backward(xt, dy)
+            adam_step([dict(param=p[k], grad=gr[k], m=m[k], v=v[k], lr=1e-6) for k in p], s)
+            R.set_weights(p)
+        torch.cuda.synchronize()
+        dts = (time.perf_counter() - t) / reps
+        flop = 3 * 2.0 * (16 * 256 + 256 * 256 + 256 * 32) * args.train_n
+        res["training"] = dict(n=args.train_n, backward_ms=dtb * 1e3, backward_tflops=flop / dtb / 1e12,
+                               backward_frac_of_bf16_peak=flop / dtb / 2.5e15, step_ms=dts * 1e3)
+        log(json.dumps(res["training"]))
+        del xt, dy
     if args.ft_n:
         g = scenes.gaussians(args.ft_n, 0, 0.01, 0.1, flat=True)
         cams = scenes.ring_cameras(args.ft_views, args.ft_res[0], args.ft_res[1])
