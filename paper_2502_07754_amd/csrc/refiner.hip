@@ -108,16 +108,36 @@ __device__ __forceinline__ float col_sum(const float v[4]) {
   return s;
 }
 
+// bit e set when v[e], rounded to bfloat16, is positive (sign clear, not zero)
+__device__ __forceinline__ uint64_t positive_bits(const float v[4]) {
+  uint64_t bits = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint16_t h = bf16_rne(v[e]);
+    bits |= (uint64_t)((h & 0x7fffu) != 0 && !(h & 0x8000u)) << e;
+  }
+  return bits;
+}
+
 __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict__ x, int64_t N, MlpArgs m,
                                                         TrainBufs tb) {
-  __shared__ uint16_t lds[WPB][3][16 * LDH];
+  __shared__ uint16_t lds[WPB][16 * LDH];
+  __shared__ float dbl[WPB][2 * HID + 32];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
-  uint16_t* H1s = lds[wid][0];
-  uint16_t* H2s = lds[wid][1];
-  uint16_t* G2s = lds[wid][2];
+  // one LDS tile per wave: H1 (re-laid out as layer 2's operand), then dH2
+  // (as the operand of dH1); the ReLU masks stay in registers, one bit per
+  // element this lane holds (block nb, row 4q + e -> bit 4 nb + e)
+  uint16_t* T = lds[wid];
+  // this wave's bias-gradient sums (db1, db2, db3), each address owned by one
+  // lane; added to the global sums once, after the wave's last tile
+  float* dbw = dbl[wid];
+  for (int i = lane; i < 2 * HID + 32; i += 64) dbw[i] = 0.f;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   const int64_t tiles = (N + 15) / 16;
-  for (int64_t t = (int64_t)blockIdx.x * WPB + wid; t < tiles; t += (int64_t)gridDim.x * WPB) {
+  const int64_t t0 = (int64_t)blockIdx.x * WPB + wid;
+  for (int64_t t = t0; t < tiles; t += (int64_t)gridDim.x * WPB) {
     const int64_t s0 = t * 16;
     const int64_t srow = s0 + r;  // the sample whose A row this lane carries
     // ---- layer 1: A = x rows (16 features, padded to K = 32) ----
@@ -129,6 +149,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
 #pragma unroll
       for (int e = 0; e < 8; ++e) tb.xt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(xv[e]);
     }
+    uint64_t m1 = 0, m2 = 0;  // [h1 > 0], [h2 > 0] as rounded to bfloat16
 #pragma unroll 2
     for (int nb = 0; nb < 16; ++nb) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -137,7 +158,8 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       float v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
-      store_tile(H1s, nb, lane, v);
+      m1 |= positive_bits(v) << (4 * nb);
+      store_tile(T, nb, lane, v);
       store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
     // ---- layer 2 ----
     bf16x8 a[8];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(H1s, kb, lane);
+    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(T, kb, lane);
     for (int nb = 0; nb < 16; ++nb) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       const uint16_t* wb = m.w2 + (nb * 16 + r) * HID + 8 * q;
@@ -155,7 +177,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       float v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
-      store_tile(H2s, nb, lane, v);
+      m2 |= positive_bits(v) << (4 * nb);
       store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
@@ -177,7 +199,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       s += __shfl_xor(s, 2);
       s += __shfl_xor(s, 4);
       s += __shfl_xor(s, 8);
-      if (r == 0 && 8 * q + e < m.n_out) atomicAdd(&tb.db3[8 * q + e], s);
+      if (r == 0) dbw[2 * HID + 8 * q + e] += s;
     }
     // dH2 = (dY W3) * [h2 > 0]
     for (int nb = 0; nb < 16; ++nb) {
@@ -186,20 +208,17 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       const int j = nb * 16 + r;
       float v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint16_t h = H2s[(4 * q + e) * LDH + j];
-        v[e] = (h & 0x7fffu) != 0 && !(h & 0x8000u) ? acc[e] : 0.f;  // h2 > 0
-      }
+      for (int e = 0; e < 4; ++e) v[e] = (m2 >> (4 * nb + e)) & 1u ? acc[e] : 0.f;  // h2 > 0
       const float sj = col_sum(v);
-      if (q == 0) atomicAdd(&tb.db2[j], sj);
-      store_tile(G2s, nb, lane, v);
+      if (q == 0) dbw[HID + j] += sj;
+      store_tile(T, nb, lane, v);
       store_t(tb.dh2t, tb.n_pad, j, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     // dH1 = (dH2 W2) * [h1 > 0]
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(G2s, kb, lane);
+    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(T, kb, lane);
     for (int nb = 0; nb < 16; ++nb) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       const uint16_t* wb = m.w2t + (nb * 16 + r) * HID + 8 * q;
@@ -208,36 +227,62 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       const int j = nb * 16 + r;
       float v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint16_t h = H1s[(4 * q + e) * LDH + j];
-        v[e] = (h & 0x7fffu) != 0 && !(h & 0x8000u) ? acc[e] : 0.f;
-      }
+      for (int e = 0; e < 4; ++e) v[e] = (m1 >> (4 * nb + e)) & 1u ? acc[e] : 0.f;  // h1 > 0
       const float sj = col_sum(v);
-      if (q == 0) atomicAdd(&tb.db1[j], sj);
+      if (q == 0) dbw[j] += sj;
       store_t(tb.dh1t, tb.n_pad, j, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
+  if (t0 < tiles) {
+    for (int i = lane; i < 2 * HID + 32; i += 64) {
+      if (i < HID) atomicAdd(&tb.db1[i], dbw[i]);
+      else if (i < 2 * HID) atomicAdd(&tb.db2[i - HID], dbw[i]);
+      else if (i - 2 * HID < m.n_out) atomicAdd(&tb.db3[i - 2 * HID], dbw[i]);
+    }
+  }
 }
 
-// C[m][n] += sum_s A[m][s] B[n][s] for s in this wave's chunk (bf16 rows of length n_pad).
-// Grid: x = (M/16) * (Nc/16) blocks of 16x16, y = sample chunks.
+// C[m][n] += sum_s A[m][s] B[n][s] for s in this wave's chunk (bf16 rows of
+// length n_pad). Each wave computes a (16 TM) x (16 TN) block of C: per 32
+// samples it loads TM + TN operand fragments and runs TM TN products.
+// Grid: x = (M / 16 TM) * (Nc / 16 TN) blocks, y = sample chunks.
+template <int TM, int TN>
 __global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int M,
                                               int Nc, int64_t n_pad, int64_t chunk, float* __restrict__ C) {
   const int lane = threadIdx.x, q = lane >> 4, r = lane & 15;
-  const int nbn = Nc / 16;
+  const int nbn = Nc / (16 * TN);
   const int mb = blockIdx.x / nbn, nb = blockIdx.x % nbn;
   const int64_t k0 = (int64_t)blockIdx.y * chunk;
   int64_t k1 = k0 + chunk;
   if (k1 > n_pad) k1 = n_pad;
-  const uint16_t* ap = A + (int64_t)(mb * 16 + r) * n_pad + 8 * q;
-  const uint16_t* bp = B + (int64_t)(nb * 16 + r) * n_pad + 8 * q;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t k = k0; k < k1; k += 32) acc = mfma(load_frag(ap + k), load_frag(bp + k), acc);
-  const int j = nb * 16 + r;
+  const uint16_t* ap = A + (int64_t)(mb * 16 * TM + r) * n_pad + 8 * q;
+  const uint16_t* bp = B + (int64_t)(nb * 16 * TN + r) * n_pad + 8 * q;
+  f32x4 acc[TM][TN];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) atomicAdd(&C[(mb * 16 + 4 * q + e) * Nc + j], acc[e]);
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k = k0; k < k1; k += 32) {
+    bf16x8 fa[TM], fb[TN];
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) fa[tm] = load_frag(ap + (int64_t)tm * 16 * n_pad + k);
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) fb[tn] = load_frag(bp + (int64_t)tn * 16 * n_pad + k);
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma(fa[tm], fb[tn], acc[tm][tn]);
+  }
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+      const int j = (nb * TN + tn) * 16 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) atomicAdd(&C[((mb * TM + tm) * 16 + 4 * q + e) * Nc + j], acc[tm][tn][e]);
+    }
 }
 
 // ---- packing: fp32 masters -> padded bf16 operands and transposed copies ----
@@ -776,11 +821,14 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
     const int64_t chunk = 2048;
     const unsigned ny = (unsigned)((np + chunk - 1) / chunk);
     // dW3 = dY^T H2 : [32][256];  dW2 = dH2^T H1 : [256][256];  dW1 = dH1^T X : [256][32]
-    hipLaunchKernelGGL(k_wgrad, dim3(2 * 16, ny), dim3(64), 0, s, tb.dyt, tb.h2t, 32, 256, np, chunk, g3);
+    hipLaunchKernelGGL((k_wgrad<2, 4>), dim3((32 / 32) * (256 / 64), ny), dim3(64), 0, s, tb.dyt, tb.h2t, 32, 256, np,
+                       chunk, g3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad, dim3(16 * 16, ny), dim3(64), 0, s, tb.dh2t, tb.h1t, 256, 256, np, chunk, dW2);
+    hipLaunchKernelGGL((k_wgrad<4, 4>), dim3((256 / 64) * (256 / 64), ny), dim3(64), 0, s, tb.dh2t, tb.h1t, 256, 256,
+                       np, chunk, dW2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad, dim3(16 * 2, ny), dim3(64), 0, s, tb.dh1t, tb.xt, 256, 32, np, chunk, g1);
+    hipLaunchKernelGGL((k_wgrad<4, 2>), dim3((256 / 64) * (32 / 32), ny), dim3(64), 0, s, tb.dh1t, tb.xt, 256, 32, np,
+                       chunk, g1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_unpack_grads, dim3(gfor(HID * 32)), dim3(256), 0, s, g1, g3, r->n_in, r->n_out, dW1, dW3);
