@@ -119,82 +119,120 @@ __device__ __forceinline__ uint64_t positive_bits(const float v[4]) {
   return bits;
 }
 
+// One wavefront takes RT tiles of 16 samples at a time and applies every
+// weight fragment it loads to all of them.
+template <int RT>
 __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict__ x, int64_t N, MlpArgs m,
                                                         TrainBufs tb) {
-  __shared__ uint16_t lds[WPB][16 * LDH];
+  __shared__ uint16_t lds[WPB][RT][16 * LDH];
   __shared__ float dbl[WPB][2 * HID + 32];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, r = lane & 15;
-  // one LDS tile per wave: H1 (re-laid out as layer 2's operand), then dH2
-  // (as the operand of dH1); the ReLU masks stay in registers, one bit per
-  // element this lane holds (block nb, row 4q + e -> bit 4 nb + e)
-  uint16_t* T = lds[wid];
+  // one LDS tile per wave and row tile: H1 (re-laid out as layer 2's
+  // operand), then dH2 (as the operand of dH1); the ReLU masks stay in
+  // registers, one bit per element this lane holds (block nb, row 4q + e ->
+  // bit 4 nb + e)
+  uint16_t* T[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) T[rt] = lds[wid][rt];
   // this wave's bias-gradient sums (db1, db2, db3), each address owned by one
-  // lane; added to the global sums once, after the wave's last tile
+  // lane; added to the global sums once, after the wave's last group
   float* dbw = dbl[wid];
   for (int i = lane; i < 2 * HID + 32; i += 64) dbw[i] = 0.f;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  const int64_t tiles = (N + 15) / 16;
-  const int64_t t0 = (int64_t)blockIdx.x * WPB + wid;
-  for (int64_t t = t0; t < tiles; t += (int64_t)gridDim.x * WPB) {
-    const int64_t s0 = t * 16;
-    const int64_t srow = s0 + r;  // the sample whose A row this lane carries
+  const int64_t groups = (N + 16 * RT - 1) / (16 * RT);
+  const int64_t g0 = (int64_t)blockIdx.x * WPB + wid;
+  for (int64_t gi = g0; gi < groups; gi += (int64_t)gridDim.x * WPB) {
+    const int64_t s0 = gi * 16 * RT;
     // ---- layer 1: A = x rows (16 features, padded to K = 32) ----
-    float xv[8];
+    bf16x8 ax[RT];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) xv[e] = (q == 0 || q == 1) && srow < N ? x[srow * 16 + 8 * q + e] : 0.f;
-    const bf16x8 ax = pack8(xv);
-    if (q < 2) {  // x^T for dW1 (features 0..15)
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t srow = s0 + 16 * rt + r;  // the sample whose A row this lane carries
+      float xv[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) tb.xt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(xv[e]);
+      for (int e = 0; e < 8; ++e) xv[e] = (q == 0 || q == 1) && srow < N ? x[srow * 16 + 8 * q + e] : 0.f;
+      ax[rt] = pack8(xv);
+      if (q < 2) {  // x^T for dW1 (features 0..15)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tb.xt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(xv[e]);
+      }
     }
-    uint64_t m1 = 0, m2 = 0;  // [h1 > 0], [h2 > 0] as rounded to bfloat16
+    uint64_t m1[RT], m2[RT];  // [h1 > 0], [h2 > 0] as rounded to bfloat16
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) m1[rt] = m2[rt] = 0;
 #pragma unroll 2
     for (int nb = 0; nb < 16; ++nb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(ax, load_frag(m.w1 + (nb * 16 + r) * 32 + 8 * q), acc);
+      const bf16x8 w = load_frag(m.w1 + (nb * 16 + r) * 32 + 8 * q);
       const float b = m.b1[nb * 16 + r];
-      float v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
-      m1 |= positive_bits(v) << (4 * nb);
-      store_tile(T, nb, lane, v);
-      store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+      for (int rt = 0; rt < RT; ++rt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(ax[rt], w, acc);
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
+        m1[rt] |= positive_bits(v) << (4 * nb);
+        store_tile(T[rt], nb, lane, v);
+        store_t(tb.h1t, tb.n_pad, nb * 16 + r, s0 + 16 * rt + 4 * q, v);
+      }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     // ---- layer 2 ----
-    bf16x8 a[8];
+    bf16x8 a[RT][8];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(T, kb, lane);
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(T[rt], kb, lane);
     for (int nb = 0; nb < 16; ++nb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
       const uint16_t* wb = m.w2 + (nb * 16 + r) * HID + 8 * q;
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
-      const float b = m.b2[nb * 16 + r];
-      float v[4];
+      for (int kb = 0; kb < 8; ++kb) {
+        const bf16x8 w = load_frag(wb + kb * 32);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[e] + b, 0.f);
-      m2 |= positive_bits(v) << (4 * nb);
-      store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 4 * q, v);
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(a[rt][kb], w, acc[rt]);
+      }
+      const float b = m.b2[nb * 16 + r];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[rt][e] + b, 0.f);
+        m2[rt] |= positive_bits(v) << (4 * nb);
+        store_t(tb.h2t, tb.n_pad, nb * 16 + r, s0 + 16 * rt + 4 * q, v);
+      }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     // ---- backward: dY (K = 32, outputs padded) ----
-    float dv[8];
+    bf16x8 ady[RT];
+    float s3[8];  // db3: sums over this group's samples (lanes sharing q)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int o = 8 * q + e;
-      dv[e] = (o < m.n_out && srow < N) ? tb.dy[srow * m.n_out + o] : 0.f;
+    for (int e = 0; e < 8; ++e) s3[e] = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t srow = s0 + 16 * rt + r;
+      float dv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int o = 8 * q + e;
+        dv[e] = (o < m.n_out && srow < N) ? tb.dy[srow * m.n_out + o] : 0.f;
+      }
+      ady[rt] = pack8(dv);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        tb.dyt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(dv[e]);
+        s3[e] += dv[e];
+      }
     }
-    const bf16x8 ady = pack8(dv);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      tb.dyt[(int64_t)(8 * q + e) * tb.n_pad + srow] = bf16_rne(dv[e]);
-      // db3: sum over the 16 samples (lanes sharing q)
-      float s = dv[e];
+      float s = s3[e];
       s += __shfl_xor(s, 1);
       s += __shfl_xor(s, 2);
       s += __shfl_xor(s, 4);
@@ -203,39 +241,56 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
     }
     // dH2 = (dY W3) * [h2 > 0]
     for (int nb = 0; nb < 16; ++nb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(ady, load_frag(m.w3t + (nb * 16 + r) * 32 + 8 * q), acc);
+      const bf16x8 w = load_frag(m.w3t + (nb * 16 + r) * 32 + 8 * q);
       const int j = nb * 16 + r;
-      float v[4];
+      float sj = 0.f;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = (m2 >> (4 * nb + e)) & 1u ? acc[e] : 0.f;  // h2 > 0
-      const float sj = col_sum(v);
+      for (int rt = 0; rt < RT; ++rt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(ady[rt], w, acc);
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (m2[rt] >> (4 * nb + e)) & 1u ? acc[e] : 0.f;  // h2 > 0
+        sj += col_sum(v);
+        store_tile(T[rt], nb, lane, v);
+        store_t(tb.dh2t, tb.n_pad, j, s0 + 16 * rt + 4 * q, v);
+      }
       if (q == 0) dbw[HID + j] += sj;
-      store_tile(T, nb, lane, v);
-      store_t(tb.dh2t, tb.n_pad, j, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     // dH1 = (dH2 W2) * [h1 > 0]
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) a[kb] = tile_frag(T, kb, lane);
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(T[rt], kb, lane);
     for (int nb = 0; nb < 16; ++nb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
       const uint16_t* wb = m.w2t + (nb * 16 + r) * HID + 8 * q;
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb) acc = mfma(a[kb], load_frag(wb + kb * 32), acc);
-      const int j = nb * 16 + r;
-      float v[4];
+      for (int kb = 0; kb < 8; ++kb) {
+        const bf16x8 w = load_frag(wb + kb * 32);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = (m1 >> (4 * nb + e)) & 1u ? acc[e] : 0.f;  // h1 > 0
-      const float sj = col_sum(v);
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma(a[rt][kb], w, acc[rt]);
+      }
+      const int j = nb * 16 + r;
+      float sj = 0.f;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (m1[rt] >> (4 * nb + e)) & 1u ? acc[rt][e] : 0.f;  // h1 > 0
+        sj += col_sum(v);
+        store_t(tb.dh1t, tb.n_pad, j, s0 + 16 * rt + 4 * q, v);
+      }
       if (q == 0) dbw[j] += sj;
-      store_t(tb.dh1t, tb.n_pad, j, s0 + 4 * q, v);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  if (t0 < tiles) {
+  if (g0 < groups) {
     for (int i = lane; i < 2 * HID + 32; i += 64) {
       if (i < HID) atomicAdd(&tb.db1[i], dbw[i]);
       else if (i < 2 * HID) atomicAdd(&tb.db2[i - HID], dbw[i]);
@@ -765,13 +820,6 @@ static MlpArgs margs(const msp_refiner* r) {
   return m;
 }
 
-static unsigned tile_grid(int64_t N, int n_cu) {
-  const int64_t tiles = (N + 15) / 16;
-  int64_t g = (tiles + WPB - 1) / WPB;
-  const int64_t cap = (int64_t)n_cu * 8;
-  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
-}
-
 constexpr int kInferRT = 2;  // row tiles per wavefront in inference
 
 hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu) {
@@ -816,7 +864,11 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   if ((e = hipMemsetAsync(g1, 0, 4 * (HID * 32 * 2), s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
   if (N > 0) {
-    hipLaunchKernelGGL(k_mlp_train, dim3(tile_grid(N, n_cu)), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
+    // two row tiles per wavefront: the 32-sample groups end at np (N rounded up to 32)
+    const int64_t groups = np / 32;
+    int64_t gb = (groups + WPB - 1) / WPB;
+    gb = gb > (int64_t)n_cu * 8 ? (int64_t)n_cu * 8 : gb;
+    hipLaunchKernelGGL(k_mlp_train<2>, dim3((unsigned)gb), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t chunk = 2048;
     const unsigned ny = (unsigned)((np + chunk - 1) / chunk);
