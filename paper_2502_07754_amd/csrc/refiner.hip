@@ -854,8 +854,11 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   tb.db2 = db2;
   tb.db3 = db3;
   hipError_t e;
-  // the padded samples and feature rows must read as zero
-  if ((e = hipMemsetAsync(base, 0, refiner_train_bytes(N) - 256, s)) != hipSuccess) return e;
+  // k_mlp_train writes every column (the 32-sample groups end at np, padded
+  // samples as zeros or as the zero-input activations, whose gradients are
+  // zero) of every row except the input feature rows 16..31 of xt, which must
+  // read as zero
+  if ((e = hipMemsetAsync(tb.xt + 16 * np, 0, 2 * 16 * np, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(db1, 0, 4 * HID, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(db2, 0, 4 * HID, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(db3, 0, 4 * r->n_out, s)) != hipSuccess) return e;

@@ -86,6 +86,27 @@ def test_backward_parity(gpu, N):
         assert err <= 1e-3 * np.abs(ref[k]).max(), k
 
 
+def test_backward_reuses_its_buffers(gpu):
+    """A larger backward, then a smaller one on other data with the same
+    refiner: the second must not see the first's intermediates (the training
+    buffer is cleared only where the kernels do not write)."""
+    import torch
+    p = om.init_params(28, seed=3, zero_last=False)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    for N, seed in ((5000, 21), (1000, 22)):
+        rng = np.random.default_rng(seed)
+        x = rng.normal(size=(N, 15)).astype(np.float32)
+        dy = rng.normal(size=(N, 28)).astype(np.float32)
+        x16 = np.concatenate([x, np.zeros((N, 1), np.float32)], 1)
+        g = r.backward(torch.from_numpy(x16).cuda(), torch.from_numpy(dy).cuda())
+    _, cache = om.forward(p, x.astype(np.float64))
+    ref = om.backward(p, cache, dy.astype(np.float64))
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a = g[k].cpu().numpy()
+        assert np.abs(a - ref[k]).max() <= 1e-3 * np.abs(ref[k]).max(), k
+
+
 def test_features_and_apply(gpu):
     g = scenes.gaussians(500, 4, 0.01, 0.1, flat=True)
     gg = gaussians_gpu(g)
