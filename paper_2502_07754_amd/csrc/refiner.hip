@@ -4,19 +4,20 @@
 // Gaussian's fan so fine-tuning starts nearer its optimum; a zero last layer
 // reproduces the plain conversion.
 //
-// Training forward: one wavefront per 16 samples, all three layers fused; the
-// hidden activations go through a per-wave LDS tile (bfloat16) to turn the MFMA
-// output layout into the next layer's operand layout (the backward needs them
-// there anyway). Inference keeps them in registers by computing each layer
-// transposed, over weight copies whose k-blocks are stored in the matching
-// slot order, held in LDS (k_mlp_infer_lds). Training reads its weights from
-// global memory (L2-resident, 155 KB in bfloat16) as 16-byte operand
-// fragments, pre-packed as [out][in] rows so every fragment is contiguous.
-// Backward: the same tile recomputes the forward, then dH2 = (dY W3) * [h2>0],
-// dH1 = (dH2 W2) * [h1>0] (transposed weight copies keep fragments
-// contiguous), bias gradients by wave reductions, and bfloat16 feature-major
-// copies of x, h1, h2, dy, dh2, dh1 for the weight-gradient products
-// dW = dH^T H, which a second MFMA kernel computes with split-K over samples.
+// Inference (k_mlp_infer_lds) computes each layer transposed, so the hidden
+// activations stay in registers, over weight copies whose k-blocks are stored
+// in the matching slot order and held in LDS.
+// Training (k_mlp_train) recomputes the forward one 32-sample group (two row
+// tiles) per wavefront, the hidden activations going through a per-wave LDS
+// tile (bfloat16) to turn the MFMA output layout into the next operand
+// layout; its weights come from global memory (L2-resident, 155 KB in
+// bfloat16) as 16-byte operand fragments, pre-packed as [out][in] rows (and
+// transposed copies) so every fragment is contiguous, each applied to both
+// row tiles. Then dH2 = (dY W3) * [h2>0] and dH1 = (dH2 W2) * [h1>0] (masks
+// as register bits), bias gradients summed per wave in LDS, and bfloat16
+// feature-major copies of x, h1, h2, dy, dh2, dh1 for the weight-gradient
+// products dW = dH^T H, which k_wgrad computes in 64 x 64 blocks with split-K
+// over samples.
 //
 // MFMA 16x16x32 operand layout (lane l = 0..63, q = l / 16, r = l % 16):
 //   A[i][k]: lane (i, q) holds k = 8q..8q+7;  B[k][j]: lane (j, q) holds k = 8q..8q+7;
