@@ -16,8 +16,8 @@
 // row tiles. Then dH2 = (dY W3) * [h2>0] and dH1 = (dH2 W2) * [h1>0] (masks
 // as register bits), bias gradients summed per wave in LDS, and bfloat16
 // feature-major copies of x, h1, h2, dy, dh2, dh1 for the weight-gradient
-// products dW = dH^T H, which k_wgrad computes in 64 x 64 blocks with split-K
-// over samples.
+// products dW = dH^T H, which k_wgrad_blocks computes per range of samples
+// (each operand read once, partial products summed by k_wgrad_sum).
 //
 // MFMA 16x16x32 operand layout (lane l = 0..63, q = l / 16, r = l % 16):
 //   A[i][k]: lane (i, q) holds k = 8q..8q+7;  B[k][j]: lane (j, q) holds k = 8q..8q+7;
@@ -300,45 +300,127 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
   }
 }
 
-// C[m][n] += sum_s A[m][s] B[n][s] for s in this wave's chunk (bf16 rows of
-// length n_pad). Each wave computes a (16 TM) x (16 TN) block of C: per 32
-// samples it loads TM + TN operand fragments and runs TM TN products.
-// Grid: x = (M / 16 TM) * (Nc / 16 TN) blocks, y = sample chunks.
-template <int TM, int TN>
-__global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int M,
-                                              int Nc, int64_t n_pad, int64_t chunk, float* __restrict__ C) {
-  const int lane = threadIdx.x, q = lane >> 4, r = lane & 15;
-  const int nbn = Nc / (16 * TN);
-  const int mb = blockIdx.x / nbn, nb = blockIdx.x % nbn;
-  const int64_t k0 = (int64_t)blockIdx.y * chunk;
-  int64_t k1 = k0 + chunk;
-  if (k1 > n_pad) k1 = n_pad;
-  const uint16_t* ap = A + (int64_t)(mb * 16 * TM + r) * n_pad + 8 * q;
-  const uint16_t* bp = B + (int64_t)(nb * 16 * TN + r) * n_pad + 8 * q;
-  f32x4 acc[TM][TN];
+// Weight gradients C = A B^T, C[m][n] = sum_s A[m][s] B[n][s] over all samples
+// (A, B bf16 feature-major rows of length n_pad), each operand read once:
+// every block takes a contiguous range of samples and the whole M x NC
+// product. Per 32 samples it stages both operands' columns in LDS (rows padded
+// to 80 bytes, so the 16 lanes r of a fragment read hit distinct bank groups;
+// the next step's columns are loaded while this step's products run), and
+// each wavefront computes a (16 TM) x (16 TN) part of C from them. The block
+// writes its partial product to part[block]; k_wgrad_sum adds the partials in
+// block order (no atomics, the same result on every run).
+template <int M, int NC>
+struct WgradShape {
+  static constexpr int TM = (M < 64 ? M : 64) / 16, TN = (NC < 64 ? NC : 64) / 16;
+  static constexpr int WM = M / (16 * TM), WN = NC / (16 * TN), WAVES = WM * WN;
+  static constexpr int ROWS = M + NC, LDR = 40;  // LDS row stride in bf16 elements (80 bytes)
+  static constexpr int CHUNKS = ROWS * 4;        // 16-byte chunks of one 32-sample step
+  static constexpr int PER = (CHUNKS + 64 * WAVES - 1) / (64 * WAVES);
+};
+
+template <int M, int NC>
+__global__ __launch_bounds__((64 * WgradShape<M, NC>::WAVES)) void k_wgrad_blocks(const uint16_t* __restrict__ A,
+                                                                              const uint16_t* __restrict__ B,
+                                                                              int64_t n_pad, int64_t span,
+                                                                              float* __restrict__ part) {
+  using S = WgradShape<M, NC>;
+  constexpr int NT = 64 * S::WAVES;
+  __shared__ __attribute__((aligned(16))) uint16_t st[2][S::ROWS * S::LDR];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, q = lane >> 4, r = lane & 15;
+  const int wm = wid / S::WN, wn = wid % S::WN;
+  const int64_t k0 = (int64_t)blockIdx.x * span;
+  const int64_t k1 = k0 + span < n_pad ? k0 + span : n_pad;
+  u32x4 v[S::PER];
 #pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
+  for (int i = 0; i < S::PER; ++i) v[i] = u32x4{0u, 0u, 0u, 0u};
+  // columns [k, k + 32) of both operands: chunk c is 16 bytes of row c / 4
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k = k0; k < k1; k += 32) {
-    bf16x8 fa[TM], fb[TN];
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm) fa[tm] = load_frag(ap + (int64_t)tm * 16 * n_pad + k);
-#pragma unroll
-    for (int tn = 0; tn < TN; ++tn) fb[tn] = load_frag(bp + (int64_t)tn * 16 * n_pad + k);
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-      for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma(fa[tm], fb[tn], acc[tm][tn]);
+  for (int i = 0; i < S::PER; ++i) {
+    const int c = tid + i * NT;
+    if (c < S::CHUNKS && k0 < k1) {
+      const int row = c >> 2;
+      const uint16_t* src = row < M ? A + (int64_t)row * n_pad : B + (int64_t)(row - M) * n_pad;
+      v[i] = *reinterpret_cast<const u32x4*>(src + k0 + (c & 3) * 8);
+    }
   }
 #pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
+  for (int i = 0; i < S::PER; ++i) {
+    const int c = tid + i * NT;
+    if (c < S::CHUNKS) *reinterpret_cast<u32x4*>(st[0] + (c >> 2) * S::LDR + (c & 3) * 8) = v[i];
+  }
+  __syncthreads();
+  f32x4 acc[S::TM][S::TN];
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-      const int j = (nb * TN + tn) * 16 + r;
+  for (int tm = 0; tm < S::TM; ++tm)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) atomicAdd(&C[((mb * TM + tm) * 16 + 4 * q + e) * Nc + j], acc[tm][tn][e]);
+    for (int tn = 0; tn < S::TN; ++tn) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  for (int64_t k = k0; k < k1; k += 32) {
+    const bool more = k + 32 < k1;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < S::PER; ++i) {
+        const int c = tid + i * NT;
+        if (c < S::CHUNKS) {
+          const int row = c >> 2;
+          const uint16_t* src = row < M ? A + (int64_t)row * n_pad : B + (int64_t)(row - M) * n_pad;
+          v[i] = *reinterpret_cast<const u32x4*>(src + k + 32 + (c & 3) * 8);
+        }
+      }
     }
+    const uint16_t* sa = st[buf] + (wm * 16 * S::TM + r) * S::LDR + 8 * q;
+    const uint16_t* sb = st[buf] + (M + wn * 16 * S::TN + r) * S::LDR + 8 * q;
+    bf16x8 fa[S::TM], fb[S::TN];
+#pragma unroll
+    for (int tm = 0; tm < S::TM; ++tm) fa[tm] = load_frag(sa + tm * 16 * S::LDR);
+#pragma unroll
+    for (int tn = 0; tn < S::TN; ++tn) fb[tn] = load_frag(sb + tn * 16 * S::LDR);
+#pragma unroll
+    for (int tm = 0; tm < S::TM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < S::TN; ++tn) acc[tm][tn] = mfma(fa[tm], fb[tn], acc[tm][tn]);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < S::PER; ++i) {
+        const int c = tid + i * NT;
+        if (c < S::CHUNKS) *reinterpret_cast<u32x4*>(st[buf ^ 1] + (c >> 2) * S::LDR + (c & 3) * 8) = v[i];
+      }
+    }
+    __syncthreads();  // the other buffer is complete, this one free for the step after
+    buf ^= 1;
+  }
+  float* pb = part + (int64_t)blockIdx.x * M * NC;
+#pragma unroll
+  for (int tm = 0; tm < S::TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::TN; ++tn) {
+      const int col = (wn * S::TN + tn) * 16 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pb[((wm * S::TM + tm) * 16 + 4 * q + e) * NC + col] = acc[tm][tn][e];
+    }
+}
+
+// C[i] = sum over blocks b of part[b][i]: a workgroup of 256 threads takes 64
+// outputs; thread (o, g) sums the partials b = g, g + 4, ... of output o with
+// eight loads in flight, and the four sums of an output are added in a fixed
+// order (the same result on every run).
+__global__ __launch_bounds__(256) void k_wgrad_sum(const float* __restrict__ part, int nb, int64_t len,
+                                                   float* __restrict__ C) {
+  __shared__ float red[4][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < len) {
+    int b = g;
+    for (; b + 28 < nb; b += 32) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += part[(int64_t)(b + 4 * u) * len + i];
+    }
+    for (; b < nb; b += 4) acc[0] += part[(int64_t)b * len + i];
+  }
+  red[g][o] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (g == 0 && i < len) C[i] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
 }
 
 // ---- packing: fp32 masters -> padded bf16 operands and transposed copies ----
@@ -781,7 +863,7 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
 
 struct msp_refiner {
   int n_in = 15, n_out = 0;
-  DevBuf w1, w2, w3, w2t, w3t, w2p, w3p, b1, b2, b3p, train, grads, part;
+  DevBuf w1, w2, w3, w2t, w3t, w2p, w3p, b1, b2, b3p, train, grads, part, wpart;
   int64_t train_pad = 0;
 };
 
@@ -865,8 +947,10 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   if ((e = hipMemsetAsync(db3, 0, 4 * r->n_out, s)) != hipSuccess) return e;
   float* g1 = (float*)r->grads.p;  // [256][32]
   float* g3 = g1 + HID * 32;       // [32][256]
-  if ((e = hipMemsetAsync(g1, 0, 4 * (HID * 32 * 2), s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
+  if (N == 0) {  // no samples: zero weight gradients
+    if ((e = hipMemsetAsync(g1, 0, 4 * (HID * 32 * 2), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
+  }
   if (N > 0) {
     // two row tiles per wavefront: the 32-sample groups end at np (N rounded up to 32)
     const int64_t groups = np / 32;
@@ -874,17 +958,26 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
     gb = gb > (int64_t)n_cu * 8 ? (int64_t)n_cu * 8 : gb;
     hipLaunchKernelGGL(k_mlp_train<2>, dim3((unsigned)gb), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t chunk = 2048;
-    const unsigned ny = (unsigned)((np + chunk - 1) / chunk);
     // dW3 = dY^T H2 : [32][256];  dW2 = dH2^T H1 : [256][256];  dW1 = dH1^T X : [256][32]
-    hipLaunchKernelGGL((k_wgrad<2, 4>), dim3((32 / 32) * (256 / 64), ny), dim3(64), 0, s, tb.dyt, tb.h2t, 32, 256, np,
-                       chunk, g3);
+    // each over nbk sample ranges of `span` samples, then the partials summed
+    int64_t nbk = np / 32 < n_cu ? np / 32 : n_cu;
+    const int64_t span = (np / 32 + nbk - 1) / nbk * 32;
+    nbk = (np + span - 1) / span;
+    float* part = (float*)r->wpart.p;
+    hipLaunchKernelGGL((k_wgrad_blocks<32, HID>), dim3((unsigned)nbk), dim3(64 * WgradShape<32, HID>::WAVES), 0, s,
+                       tb.dyt, tb.h2t, np, span, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wgrad<4, 4>), dim3((256 / 64) * (256 / 64), ny), dim3(64), 0, s, tb.dh2t, tb.h1t, 256, 256,
-                       np, chunk, dW2);
+    hipLaunchKernelGGL(k_wgrad_sum, dim3(gfor(32 * HID, 64)), dim3(256), 0, s, part, (int)nbk, (int64_t)32 * HID, g3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wgrad<4, 2>), dim3((256 / 64) * (32 / 32), ny), dim3(64), 0, s, tb.dh1t, tb.xt, 256, 32, np,
-                       chunk, g1);
+    hipLaunchKernelGGL((k_wgrad_blocks<HID, HID>), dim3((unsigned)nbk), dim3(64 * WgradShape<HID, HID>::WAVES), 0, s,
+                       tb.dh2t, tb.h1t, np, span, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3(gfor(HID * HID, 64)), dim3(256), 0, s, part, (int)nbk, (int64_t)HID * HID, dW2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_wgrad_blocks<HID, 32>), dim3((unsigned)nbk), dim3(64 * WgradShape<HID, 32>::WAVES), 0, s,
+                       tb.dh1t, tb.xt, np, span, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3(gfor(HID * 32, 64)), dim3(256), 0, s, part, (int)nbk, (int64_t)HID * 32, g1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_unpack_grads, dim3(gfor(HID * 32)), dim3(256), 0, s, g1, g3, r->n_in, r->n_out, dW1, dW3);
@@ -966,11 +1059,14 @@ int refiner_alloc(msp_ctx* ctx, msp_refiner* r) {
 }
 
 int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N) {
-  return msp_ensure(ctx, r->train, refiner_train_bytes(N));
+  int rc;
+  if ((rc = msp_ensure(ctx, r->train, refiner_train_bytes(N)))) return rc;
+  // one partial weight gradient (up to 256 x 256) per block of the weight-gradient products
+  return msp_ensure(ctx, r->wpart, (size_t)4 * ctx->n_cu * HID * HID);
 }
 
 void refiner_free_bufs(msp_refiner* r) {
-  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->w2p, &r->w3p, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part};
+  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->w2p, &r->w3p, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part, &r->wpart};
   for (DevBuf* x : b)
     if (x->p) (void)hipFree(x->p);
 }
