@@ -391,7 +391,10 @@ msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* 
 /* Gradients of sum(y * dy) over the n samples (forward recomputed from x):
  * dW1 [256][15], db1 [256], dW2 [256][256], db2 [256], dW3 [n_out][256],
  * db3 [n_out] (DEVICE, overwritten). dy, dh2 and dh1 are rounded to bfloat16
- * before each product; bias gradients sum the unrounded values. */
+ * before each product; bias gradients sum the unrounded values. Weight
+ * gradients are summed in a fixed order (identical on every run); bias
+ * gradients are added per wavefront with float atomics (last-bit differences
+ * between runs). Calls on one refiner share its scratch: do not overlap them. */
 msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, const float* dy, int64_t n, float* dW1,
                                 float* db1, float* dW2, float* db2, float* dW3, float* db3);
 /* Fan conversion (as msp_convert, sizes from msp_convert_size) with the
