@@ -311,7 +311,9 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
 // block order (no atomics, the same result on every run).
 template <int M, int NC>
 struct WgradShape {
-  static constexpr int TM = (M < 64 ? M : 64) / 16, TN = (NC < 64 ? NC : 64) / 16;
+  // 64 x 64 per wavefront for the 256 x 256 product, 32 x 32 (eight waves)
+  // when one side is 32 wide
+  static constexpr int TM = (M < 64 || NC < 64) ? 2 : 4, TN = TM;
   static constexpr int WM = M / (16 * TM), WN = NC / (16 * TN), WAVES = WM * WN;
   static constexpr int ROWS = M + NC, LDR = 40;  // LDS row stride in bf16 elements (80 bytes)
   static constexpr int CHUNKS = ROWS * 4;        // 16-byte chunks of one 32-sample step
