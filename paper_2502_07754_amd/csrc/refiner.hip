@@ -917,14 +917,21 @@ hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const flo
   return hipGetLastError();
 }
 
+// Row tiles of 16 samples per wavefront in the training kernel; the samples
+// are padded to whole groups of 16 kTrainRT (a multiple of 32), so that the
+// groups write every column of the training copies.
+constexpr int kTrainRT = 2;
+static_assert((16 * kTrainRT) % 32 == 0, "the weight-gradient kernels step through 32 samples");
+static int64_t train_pad(int64_t N) { return (N + 16 * kTrainRT - 1) / (16 * kTrainRT) * (16 * kTrainRT); }
+
 size_t refiner_train_bytes(int64_t N) {
-  const int64_t np = (N + 31) / 32 * 32;
+  const int64_t np = train_pad(N);
   return (size_t)2 * np * (32 + 256 + 256 + 32 + 256 + 256) + 256;
 }
 
 hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x, const float* dy, int64_t N,
                                    float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, int n_cu) {
-  const int64_t np = (N + 31) / 32 * 32;
+  const int64_t np = train_pad(N);
   uint16_t* base = (uint16_t*)r->train.p;
   TrainBufs tb;
   tb.dy = dy;
@@ -939,7 +946,7 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   tb.db2 = db2;
   tb.db3 = db3;
   hipError_t e;
-  // k_mlp_train writes every column (the 32-sample groups end at np, padded
+  // k_mlp_train writes every column (its groups end at np, padded
   // samples as zeros or as the zero-input activations, whose gradients are
   // zero) of every row except the input feature rows 16..31 of xt, which must
   // read as zero
@@ -954,11 +961,11 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
     if ((e = hipMemsetAsync(dW2, 0, 4 * HID * HID, s)) != hipSuccess) return e;
   }
   if (N > 0) {
-    // two row tiles per wavefront: the 32-sample groups end at np (N rounded up to 32)
-    const int64_t groups = np / 32;
+    // kTrainRT row tiles per wavefront: the groups end at np
+    const int64_t groups = np / (16 * kTrainRT);
     int64_t gb = (groups + WPB - 1) / WPB;
     gb = gb > (int64_t)n_cu * 8 ? (int64_t)n_cu * 8 : gb;
-    hipLaunchKernelGGL(k_mlp_train<2>, dim3((unsigned)gb), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
+    hipLaunchKernelGGL(k_mlp_train<kTrainRT>, dim3((unsigned)gb), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // dW3 = dY^T H2 : [32][256];  dW2 = dH2^T H1 : [256][256];  dW1 = dH1^T X : [256][32]
     // each over nbk sample ranges of `span` samples, then the partials summed
