@@ -929,7 +929,7 @@ static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f,
   if (grads->dopacity) MSP_HIP(ctx, launch_fill_f32(s, grads->dopacity, 0.f, Vn));
   if (grads->drgb) MSP_HIP(ctx, launch_fill_f32(s, grads->drgb, 0.f, 3 * Vn));
   const bool shm = st->color_mode == MSP_COLOR_SH3;
-  if (shm && grads->dsh) MSP_HIP(ctx, launch_fill_f32(s, grads->dsh, 0.f, 48 * f->n_faces));
+  // dsh needs no clearing: the SH adjoint at the end writes all 48 F values
   if (f->n_faces == 0) return MSP_OK;
   if (shm && !f->sh) return bad("SH render state needs f->sh");
   const int64_t nb = (int64_t)st->n_views * ((st->W + 7) / 8) * ((st->H + 7) / 8);
