@@ -107,6 +107,27 @@ def test_backward_reuses_its_buffers(gpu):
         assert np.abs(a - ref[k]).max() <= 1e-3 * np.abs(ref[k]).max(), k
 
 
+def test_backward_weight_gradients_repeat_exactly(gpu):
+    """The weight gradients are summed in a fixed order (no float atomics):
+    two identical backwards give identical bits; the bias gradients, added per
+    wavefront with atomics, agree to rounding."""
+    import torch
+    p = om.init_params(28, seed=9, zero_last=False)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    rng = np.random.default_rng(9)
+    N = 20_000
+    x16 = np.concatenate([rng.normal(size=(N, 15)), np.zeros((N, 1))], 1).astype(np.float32)
+    dy = rng.normal(size=(N, 28)).astype(np.float32)
+    xg, dg = torch.from_numpy(x16).cuda(), torch.from_numpy(dy).cuda()
+    g1 = {k: v.cpu().numpy() for k, v in r.backward(xg, dg).items()}
+    g2 = {k: v.cpu().numpy() for k, v in r.backward(xg, dg).items()}
+    for k in ("W1", "W2", "W3"):
+        assert np.array_equal(g1[k], g2[k]), k
+    for k in ("b1", "b2", "b3"):
+        np.testing.assert_allclose(g1[k], g2[k], rtol=1e-5, atol=1e-5 * np.abs(g1[k]).max())
+
+
 def test_features_and_apply(gpu):
     g = scenes.gaussians(500, 4, 0.01, 0.1, flat=True)
     gg = gaussians_gpu(g)
