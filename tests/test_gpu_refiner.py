@@ -128,6 +128,34 @@ def test_backward_weight_gradients_repeat_exactly(gpu):
         np.testing.assert_allclose(g1[k], g2[k], rtol=1e-5, atol=1e-5 * np.abs(g1[k]).max())
 
 
+def test_forward_bf16_rounding_bitwise(gpu):
+    """Unit weights W1[0][0] = W2[0][0] = W3[0][0] = 1 (all else zero) pass
+    input feature 0 through the forward's three bfloat16 roundings unchanged
+    after the first, so output 0 is bf16(x0) for x0 >= 0: ties with even and
+    odd last bits, their neighbours one float32 ulp away, random low bits and
+    exact bfloat16 values, bit for bit against the oracle's rounding (positive
+    normal values; the matrix core may flush subnormals)."""
+    import torch
+    n_out = 28
+    p = {k: np.zeros_like(v) for k, v in om.init_params(n_out, seed=0, zero_last=False).items()}
+    p["W1"][0, 0] = p["W2"][0, 0] = p["W3"][0, 0] = 1.0
+    rng = np.random.default_rng(0)
+    hi = rng.integers(0x0080, 0x7F00, 2000).astype(np.uint32) << 16  # sign 0, exponent 1..253
+    tie = hi | 0x8000
+    bits = np.concatenate([tie, tie + 1, tie - 1, hi | rng.integers(0, 0x10000, 2000).astype(np.uint32), hi])
+    x0 = bits.view(np.float32)
+    assert np.all(np.isfinite(x0)) and np.all(x0 > 0)
+    N = len(x0)
+    x16 = np.zeros((N, 16), np.float32)
+    x16[:, 0] = x0
+    r = gpu.Refiner(n_out)
+    r.set_weights(_params_gpu(p))
+    y = r.forward(torch.from_numpy(x16).cuda()).cpu().numpy()
+    want = om.bf16_round(x0)
+    assert np.array_equal(y[:, 0].astype(np.float64), want)
+    assert np.all(y[:, 1:] == 0)
+
+
 def test_features_and_apply(gpu):
     g = scenes.gaussians(500, 4, 0.01, 0.1, flat=True)
     gg = gaussians_gpu(g)
