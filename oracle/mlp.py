@@ -77,7 +77,7 @@ def forward(p, x, rounding=True):
 
 
 def backward(p, cache, dy, rounding=True):
-    """Gradients of sum(y * dy) w.r.t. W1, b1, W2, b2, W3, b3."""
+    """Gradients of sum(y * dy) w.r.t. W1, b1, W2, b2, W3, b3 and the input x."""
     r = bf16_round if rounding else (lambda a: np.asarray(a, np.float64))
     x, h1, h2 = cache
     dy = np.asarray(dy, np.float64)
@@ -90,6 +90,7 @@ def backward(p, cache, dy, rounding=True):
     dh1 = (r(dh2) @ r(p["W2"])) * (h1 > 0)
     g["W1"] = r(dh1).T @ r(x)
     g["b1"] = dh1.sum(0)
+    g["x"] = r(dh1) @ r(p["W1"])  # input gradient [N][15], dh1 and W1 rounded like the other products
     return g
 
 

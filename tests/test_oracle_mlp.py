@@ -52,7 +52,7 @@ def test_mlp_matches_torch_autograd():
     y, cache = om.forward(p, x, rounding=False)
     g = om.backward(p, cache, dy, rounding=False)
     t = {k: torch.tensor(v.astype(np.float64), requires_grad=True) for k, v in p.items()}
-    xt = torch.tensor(x)
+    xt = torch.tensor(x, requires_grad=True)
     h1 = torch.relu(xt @ t["W1"].T + t["b1"])
     h2 = torch.relu(h1 @ t["W2"].T + t["b2"])
     yt = h2 @ t["W3"].T + t["b3"]
@@ -60,6 +60,7 @@ def test_mlp_matches_torch_autograd():
     np.testing.assert_allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-12)
     for k in p:
         np.testing.assert_allclose(g[k], t[k].grad.numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g["x"], xt.grad.numpy(), rtol=1e-10, atol=1e-12)
 
 
 def test_rounded_forward_is_near_unrounded():
