@@ -394,9 +394,12 @@ msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* 
  * before each product; bias gradients sum the unrounded values. Weight
  * gradients are summed in a fixed order (identical on every run); bias
  * gradients are added per wavefront with float atomics (last-bit differences
- * between runs). Calls on one refiner share its scratch: do not overlap them. */
+ * between runs). dx [n][16] (DEVICE, overwritten; NULL = not computed): the
+ * gradient with respect to the inputs, dh1 W1 with dh1 and W1 rounded to
+ * bfloat16, in the layout of x (column 15 zero). Calls on one refiner share
+ * its scratch: do not overlap them. */
 msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, const float* dy, int64_t n, float* dW1,
-                                float* db1, float* dW2, float* db2, float* dW3, float* db3);
+                                float* db1, float* dW2, float* db2, float* dW3, float* db3, float* dx);
 /* Fan conversion (as msp_convert, sizes from msp_convert_size) with the
  * refiner's outputs applied: boundary vertex k moves by
  * y[3k] a A^ + y[3k+1] b B^ + y[3k+2] sqrt(a b) (A^ x B^) from its plain

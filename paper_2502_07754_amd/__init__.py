@@ -629,7 +629,9 @@ class Refiner:
                        "msp_refiner_forward")
         return y
 
-    def backward(self, x, dy) -> dict:
+    def backward(self, x, dy, want_dx: bool = False) -> dict:
+        """Weight and bias gradients of sum(y * dy); with want_dx also "x", the
+        input gradient [n][16] (column 15 zero)."""
         import torch
         _need(x, torch.float32, "x")
         _need(dy, torch.float32, "dy")
@@ -637,10 +639,13 @@ class Refiner:
         g = dict(W1=torch.empty((256, 15), device=dev), b1=torch.empty(256, device=dev),
                  W2=torch.empty((256, 256), device=dev), b2=torch.empty(256, device=dev),
                  W3=torch.empty((self.n_out, 256), device=dev), b3=torch.empty(self.n_out, device=dev))
+        if want_dx:
+            g["x"] = torch.empty((x.shape[0], 16), device=dev)
         self.ctx.bind_stream()
         self.ctx.check(self.ctx.lib.msp_refiner_backward(self.ctx.h, self.h, _dev_ptr(x), _dev_ptr(dy), x.shape[0],
                                                          *[_dev_ptr(g[k]) for k in ("W1", "b1", "W2", "b2", "W3",
-                                                                                    "b3")]),
+                                                                                    "b3")],
+                                                         _dev_ptr(g["x"]) if want_dx else None),
                        "msp_refiner_backward")
         return g
 

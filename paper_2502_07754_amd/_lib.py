@@ -117,7 +117,7 @@ EXPORTS = {
     "msp_refiner_set_weights": (C.c_int, [C.c_void_p, C.c_void_p] + [C.c_void_p] * 6),
     "msp_refiner_features": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_void_p]),
     "msp_refiner_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
-    "msp_refiner_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64] + [C.c_void_p] * 6),
+    "msp_refiner_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64] + [C.c_void_p] * 7),
     "msp_refiner_apply": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float, C.c_void_p,
                                     C.POINTER(Faces)]),
     "msp_refiner_targets": (C.c_int, [C.c_void_p, C.POINTER(Gaussians), C.c_int, C.c_float, C.c_float,

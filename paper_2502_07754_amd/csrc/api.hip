@@ -642,7 +642,7 @@ msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* 
 }
 
 msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, const float* dy, int64_t n, float* dW1,
-                                float* db1, float* dW2, float* db2, float* dW3, float* db3) {
+                                float* db1, float* dW2, float* db2, float* dW3, float* db3, float* dx) {
   if (!ctx) return MSP_EINVAL;
   if (!r || n < 0 || (n > 0 && (!x || !dy)) || !dW1 || !db1 || !dW2 || !db2 || !dW3 || !db3)
     return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_refiner_backward: bad argument");
@@ -650,7 +650,7 @@ msp_status msp_refiner_backward(msp_ctx* ctx, msp_refiner* r, const float* x, co
   int rc;
   if ((rc = refiner_train_alloc(ctx, r, n))) return (msp_status)rc;
   MSP_TIMED(ctx, ST_OTHER,
-            launch_refiner_backward(ctx->stream, r, x, dy, n, dW1, db1, dW2, db2, dW3, db3, ctx->n_cu));
+            launch_refiner_backward(ctx->stream, r, x, dy, n, dW1, db1, dW2, db2, dW3, db3, dx, ctx->n_cu));
   return MSP_OK;
 }
 

@@ -225,7 +225,8 @@ hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, c
                                const float* b2, const float* W3, const float* b3);
 hipError_t launch_refiner_forward(hipStream_t s, const msp_refiner* r, const float* x, int64_t N, float* y, int n_cu);
 hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x, const float* dy, int64_t N,
-                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, int n_cu);
+                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, float* dx,
+                                   int n_cu);
 hipError_t launch_refiner_features(hipStream_t s, const msp_gaussians* g, int K, float* x);
 hipError_t launch_refiner_apply(hipStream_t s, const msp_gaussians* g, int K, float sigma, float opac_mul,
                                 const float* y, int n_out, msp_faces* out);

@@ -69,6 +69,7 @@ struct MlpArgs {
   const uint16_t* w3;   // [32][256]
   const uint16_t* w2t;  // [256][256]  w2t[i][o] = W2[o][i]
   const uint16_t* w3t;  // [256][32]   w3t[j][o] = W3[o][j]
+  const uint16_t* w1t;  // [32][256]   w1t[k][i] = W1[i][k] (k < n_in, else 0)
   const float* b1;      // [256]
   const float* b2;      // [256]
   const float* b3;      // [32]
@@ -80,6 +81,7 @@ struct TrainBufs {
   uint16_t *xt, *h1t, *h2t, *dyt, *dh2t, *dh1t;  // feature-major, row length n_pad
   int64_t n_pad;
   float *db1, *db2, *db3;  // accumulated with atomics (zeroed by the caller)
+  float* dx;               // [N][16] input gradient (column 15 zero), or null
 };
 
 // Writes a D fragment (+bias, optional relu) of column block nb into an LDS tile as bf16.
@@ -265,6 +267,9 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(T[rt], kb, lane);
+    // the tiles are read before dH1 overwrites them (when dX is wanted)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     for (int nb = 0; nb < 16; ++nb) {
       f32x4 acc[RT];
 #pragma unroll
@@ -285,11 +290,29 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
         for (int e = 0; e < 4; ++e) v[e] = (m1[rt] >> (4 * nb + e)) & 1u ? acc[rt][e] : 0.f;  // h1 > 0
         sj += col_sum(v);
         store_t(tb.dh1t, tb.n_pad, j, s0 + 16 * rt + 4 * q, v);
+        if (tb.dx) store_tile(T[rt], nb, lane, v);  // dH1 as the operand of dX
       }
       if (q == 0) dbw[j] += sj;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (tb.dx) {  // dX = dH1 W1 (input features 0..15; feature 15 has zero weights)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) a[rt][kb] = tile_frag(T[rt], kb, lane);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(a[rt][kb], load_frag(m.w1t + r * HID + kb * 32 + 8 * q), acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t sample = s0 + 16 * rt + 4 * q + e;
+          if (sample < N) tb.dx[sample * 16 + r] = acc[e];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    }
   }
   if (g0 < groups) {
     for (int i = lane; i < 2 * HID + 32; i += 64) {
@@ -428,7 +451,7 @@ __global__ __launch_bounds__(256) void k_wgrad_sum(const float* __restrict__ par
 // ---- packing: fp32 masters -> padded bf16 operands and transposed copies ----
 __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ W3,
                        const float* __restrict__ b3, int n_in, int n_out, uint16_t* w1, uint16_t* w2, uint16_t* w3,
-                       uint16_t* w2t, uint16_t* w3t, uint16_t* w2p, uint16_t* w3p, float* b3p) {
+                       uint16_t* w2t, uint16_t* w3t, uint16_t* w2p, uint16_t* w3p, uint16_t* w1t, float* b3p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < HID * 32) {
     const int o = i / 32, k = i % 32;
@@ -439,6 +462,8 @@ __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W
     w3[i] = o3 < n_out ? bf16_rne(W3[o3 * HID + k3]) : 0;
     const int f3 = (k3 & ~31) + slot_feature(k3 & 31);  // w3p[o][slot]
     w3p[i] = o3 < n_out ? bf16_rne(W3[o3 * HID + f3]) : 0;
+    const int k1 = i / HID, j1 = i % HID;  // w1t[k][i]
+    w1t[i] = k1 < n_in ? bf16_rne(W1[j1 * n_in + k1]) : 0;
   }
   if (i < HID * HID) {
     w2[i] = bf16_rne(W2[i]);
@@ -865,7 +890,7 @@ __global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_e
 
 struct msp_refiner {
   int n_in = 15, n_out = 0;
-  DevBuf w1, w2, w3, w2t, w3t, w2p, w3p, b1, b2, b3p, train, grads, part, wpart;
+  DevBuf w1, w2, w3, w2t, w3t, w2p, w3p, w1t, b1, b2, b3p, train, grads, part, wpart;
   int64_t train_pad = 0;
 };
 
@@ -883,7 +908,8 @@ hipError_t launch_refiner_pack(hipStream_t s, msp_refiner* r, const float* W1, c
                                const float* b2, const float* W3, const float* b3) {
   hipLaunchKernelGGL(k_pack, dim3(gfor(HID * HID)), dim3(256), 0, s, W1, W2, W3, b3, r->n_in, r->n_out,
                      (uint16_t*)r->w1.p, (uint16_t*)r->w2.p, (uint16_t*)r->w3.p, (uint16_t*)r->w2t.p,
-                     (uint16_t*)r->w3t.p, (uint16_t*)r->w2p.p, (uint16_t*)r->w3p.p, (float*)r->b3p.p);
+                     (uint16_t*)r->w3t.p, (uint16_t*)r->w2p.p, (uint16_t*)r->w3p.p, (uint16_t*)r->w1t.p,
+                     (float*)r->b3p.p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(r->b1.p, b1, 4 * HID, hipMemcpyDeviceToDevice, s);
@@ -898,6 +924,7 @@ static MlpArgs margs(const msp_refiner* r) {
   m.w3 = (const uint16_t*)r->w3.p;
   m.w2t = (const uint16_t*)r->w2t.p;
   m.w3t = (const uint16_t*)r->w3t.p;
+  m.w1t = (const uint16_t*)r->w1t.p;
   m.b1 = (const float*)r->b1.p;
   m.b2 = (const float*)r->b2.p;
   m.b3 = (const float*)r->b3p.p;
@@ -930,7 +957,8 @@ size_t refiner_train_bytes(int64_t N) {
 }
 
 hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x, const float* dy, int64_t N,
-                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, int n_cu) {
+                                   float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, float* dx,
+                                   int n_cu) {
   const int64_t np = train_pad(N);
   uint16_t* base = (uint16_t*)r->train.p;
   TrainBufs tb;
@@ -945,6 +973,7 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   tb.db1 = db1;
   tb.db2 = db2;
   tb.db3 = db3;
+  tb.dx = dx;
   hipError_t e;
   // k_mlp_train writes every column (its groups end at np, padded
   // samples as zeros or as the zero-input activations, whose gradients are
@@ -1060,7 +1089,8 @@ int refiner_alloc(msp_ctx* ctx, msp_refiner* r) {
   if ((rc = msp_ensure(ctx, r->part, 8 * 1024)) || (rc = msp_ensure(ctx, r->w1, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2, 2 * HID * HID)) ||
       (rc = msp_ensure(ctx, r->w3, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->w2t, 2 * HID * HID)) ||
       (rc = msp_ensure(ctx, r->w3t, 2 * HID * 32)) || (rc = msp_ensure(ctx, r->w2p, 2 * HID * HID)) ||
-      (rc = msp_ensure(ctx, r->w3p, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
+      (rc = msp_ensure(ctx, r->w3p, 2 * 32 * HID)) || (rc = msp_ensure(ctx, r->w1t, 2 * 32 * HID)) ||
+      (rc = msp_ensure(ctx, r->b1, 4 * HID)) ||
       (rc = msp_ensure(ctx, r->b2, 4 * HID)) || (rc = msp_ensure(ctx, r->b3p, 4 * 32)) ||
       (rc = msp_ensure(ctx, r->grads, 4 * HID * 32 * 2)))
     return rc;
@@ -1075,7 +1105,7 @@ int refiner_train_alloc(msp_ctx* ctx, msp_refiner* r, int64_t N) {
 }
 
 void refiner_free_bufs(msp_refiner* r) {
-  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->w2p, &r->w3p, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part, &r->wpart};
+  DevBuf* b[] = {&r->w1, &r->w2, &r->w3, &r->w2t, &r->w3t, &r->w2p, &r->w3p, &r->w1t, &r->b1, &r->b2, &r->b3p, &r->train, &r->grads, &r->part, &r->wpart};
   for (DevBuf* x : b)
     if (x->p) (void)hipFree(x->p);
 }

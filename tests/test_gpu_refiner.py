@@ -76,11 +76,14 @@ def test_backward_parity(gpu, N):
     x16 = np.concatenate([x, np.zeros((N, 1), np.float32)], 1)
     r = gpu.Refiner(28)
     r.set_weights(_params_gpu(p))
-    g = r.backward(torch.from_numpy(x16).cuda(), torch.from_numpy(dy).cuda())
+    g = r.backward(torch.from_numpy(x16).cuda(), torch.from_numpy(dy).cuda(), want_dx=True)
     _, cache = om.forward(p, x.astype(np.float64))
     ref = om.backward(p, cache, dy.astype(np.float64))
-    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        a = g[k].cpu().numpy()
+    dx = g.pop("x").cpu().numpy()
+    assert dx.shape == (N, 16) and np.all(dx[:, 15] == 0)
+    g["x"] = dx[:, :15]
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "x"):
+        a = g[k] if k == "x" else g[k].cpu().numpy()
         err = np.abs(a - ref[k]).max()
         print(k, "max err", err, "max |g|", np.abs(ref[k]).max(), flush=True)
         assert err <= 1e-3 * np.abs(ref[k]).max(), k
