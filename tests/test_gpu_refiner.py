@@ -159,6 +159,21 @@ def test_forward_bf16_rounding_bitwise(gpu):
     assert np.all(y[:, 1:] == 0)
 
 
+def test_empty_batch(gpu):
+    """No samples: the forward returns no rows, the backward zero gradients."""
+    import torch
+    p = om.init_params(28, seed=4, zero_last=False)
+    r = gpu.Refiner(28)
+    r.set_weights(_params_gpu(p))
+    x = torch.zeros((0, 16), dtype=torch.float32, device="cuda")
+    dy = torch.zeros((0, 28), dtype=torch.float32, device="cuda")
+    assert r.forward(x).shape == (0, 28)
+    g = r.backward(x, dy, want_dx=True)
+    assert g["x"].shape == (0, 16)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert torch.count_nonzero(g[k]).item() == 0, k
+
+
 def test_features_and_apply(gpu):
     g = scenes.gaussians(500, 4, 0.01, 0.1, flat=True)
     gg = gaussians_gpu(g)
