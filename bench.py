@@ -31,7 +31,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3           # packed FP32 (two lanes per instruction)
+FP32_VECTOR_UNPACKED_TFLOPS = 78.6        # what this build can reach: it never emits packed FP32
 
 # HBM bytes per launch (read, written) of the two heaviest kernels at the
 # autotuned configuration (tile 32x16, ordering buffer 16), from rocprofv3
@@ -237,6 +238,53 @@ def bench_rays(args):
     print(json.dumps(out), flush=True)
 
 
+def stage_roofline(stages: dict, steps: int, st: dict, F: int, views: int) -> dict:
+    """Per timed stage: duration per launch and its algorithmic work against the
+    roofline that bounds it. Work per unit (flop or bytes the method needs, not
+    what the kernel happens to move):
+      composite   8 flop per (face, pixel of its footprint) coverage test + 60 per composited fragment
+      bwd_grads   120 flop per fragment (adjoint recurrence, barycentrics, ray/triangle Jacobian)
+      bwd_lists   as composite (the forward's ordering recomputed)
+      setup       12 B indices + 36 B corners + 48 B record per (view, face)
+      emit        8 B per tile entry + 16 B footprint per (view, face)
+      sort        16 B per tile entry (read + write)
+      sh_eval     192 B coefficients + 36 B corners per face + 16 B colour per (view, face)
+      sh_bwd      192 B coefficients in + 192 B out + 36 B corners per face + 16 B per (view, face)
+    The arithmetic stages are priced against the FP32 vector peak (packed), with
+    the unpacked peak this build can reach beside it."""
+    frags, entries, fp = st["fragments"], st["entries"], st["footprint_pixels"]
+    work = {
+        "composite": ("alu", 8.0 * fp + 60.0 * frags),
+        "bwd_lists": ("alu", 8.0 * fp + 60.0 * frags),
+        "bwd_grads": ("alu", 120.0 * frags),
+        "setup": ("hbm", 96.0 * F * views),
+        "emit": ("hbm", 8.0 * entries + 16.0 * F * views),
+        "sort": ("hbm", 16.0 * entries),
+        "sh_eval": ("hbm", (192.0 + 36.0 + 16.0 * views) * F),
+        "sh_bwd": ("hbm", (384.0 + 36.0 + 16.0 * views) * F),
+    }
+    out = {}
+    for name, (ms_sum, calls) in stages.items():
+        if not calls or name not in work:
+            continue
+        ms = ms_sum / calls
+        bound, amount = work[name]
+        per_launch = amount  # every launch of a stage covers the whole step (all views)
+        if bound == "alu":
+            ach = per_launch / (ms * 1e-3) / 1e12
+            d = dict(bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                     frac=ach / FP32_VECTOR_PEAK_TFLOPS, peak_unpacked=FP32_VECTOR_UNPACKED_TFLOPS,
+                     frac_unpacked=ach / FP32_VECTOR_UNPACKED_TFLOPS, flop_per_launch=per_launch)
+        else:
+            ach = per_launch / (ms * 1e-3) / 1e9
+            d = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                     bytes_per_launch=per_launch)
+        d["ms"] = ms
+        d["calls"] = calls // max(1, steps)
+        out[name] = d
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +314,8 @@ def main():
                     help="convert with three fans per Gaussian (3D-Gaussian conversion) instead of one")
     ap.add_argument("--rgb", action="store_true",
                     help="per-vertex RGB colours instead of degree-3 SH (the colour mode of fine-tuning)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fixed-point gradient sums (identical bits on every run) instead of float atomics")
     ap.add_argument("--input-order", action="store_true",
                     help="convert the Gaussians in their drawn order instead of the spatial (Morton) order")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -329,14 +379,16 @@ def main():
         cm = msp.MSP_COLOR_RGB if args.rgb else msp.MSP_COLOR_SH3
     dimg = torch.from_numpy(scenes.upstream_grad(args.views, H, W, 3, 1e-3)).to(dev)
     th = args.tile_h or args.tile
+    det = 1 if args.deterministic else 0
     opts = msp.RenderOptions(tile_w=args.tile, tile_h=th, kbuf=args.kbuf, t_eps=1e-6, color_mode=cm,
-                             list_rows=args.list_rows)
+                             list_rows=args.list_rows, deterministic=det)
     if args.tile == 0 or args.kbuf == 0:
         t0 = time.perf_counter()
         tuned = msp.autotune(faces, cams, opts, dimg)
         log(f"autotuned tile {tuned.tile_w}x{tuned.tile_h}, kbuf {tuned.kbuf} in {time.perf_counter() - t0:.1f} s")
         opts = msp.RenderOptions(tile_w=args.tile or tuned.tile_w, tile_h=th or tuned.tile_h,
-                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=cm, list_rows=args.list_rows)
+                                 kbuf=args.kbuf or tuned.kbuf, t_eps=1e-6, color_mode=cm, list_rows=args.list_rows,
+                                 deterministic=det)
     state = msp.RenderState(ctx)
     if args.no_graph:
         def step():
@@ -393,37 +445,27 @@ def main():
     log(f"stats: {st}")
 
     # dominant kernel and its algorithmic work
-    dom = max((k for k in stages if stages[k][1]), key=lambda k: stages[k][0])
-    dom_ms = stages[dom][0] / max(1, stages[dom][1])
-    frags = st["fragments"]
-    entries = st["entries"]
-    if dom in ("composite", "bwd_lists"):
-        # per composited fragment: barycentrics, depth, alpha, colour, blend (~40 flop);
-        # per (face, pixel inside the face's pixel rectangle) one coverage test (3 edge functions, 12 flop)
-        flop = 40.0 * frags + 12.0 * st["footprint_pixels"]
-        roof = dict(bound="alu", achieved=flop / (dom_ms * 1e-3) / 1e12, peak=FP32_VECTOR_PEAK_TFLOPS,
-                    unit="TFLOP/s", traffic=None)
-    elif dom == "bwd_grads":
-        flop = 160.0 * frags
-        roof = dict(bound="alu", achieved=flop / (dom_ms * 1e-3) / 1e12, peak=FP32_VECTOR_PEAK_TFLOPS,
-                    unit="TFLOP/s", traffic=None)
-    else:
-        nbytes = {"sort": 16.0 * entries, "emit": 8.0 * entries + 64.0 * faces["idx"].shape[1] * args.views,
-                  "setup": (12 + 36 + 48) * faces["idx"].shape[1] * args.views,
-                  "sh_eval": (192 + 36 + 16 * args.views) * faces["idx"].shape[1],
-                  "sh_bwd": (192 * 2 + 36 + 12 * args.views) * faces["idx"].shape[1]}.get(dom, 0.0)
-        roof = dict(bound="hbm", achieved=nbytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                    traffic=None)
+    frags, entries = st["fragments"], st["entries"]
+    per_kernel = stage_roofline(stages, args.steps, st, int(faces["idx"].shape[1]), args.views)
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms"] * per_kernel[k]["calls"])
+    roof = {k: v for k, v in per_kernel[dom].items() if k not in ("ms", "calls")}
+    roof["traffic"] = None
     mt = MEASURED_TRAFFIC
     if (dom in mt and args.scene == "flat" and not args.fan3 and not args.input_order and not args.rgb
-            and kernel_sources_sha256() == mt["sources_sha256"]
+            and not args.deterministic and kernel_sources_sha256() == mt["sources_sha256"]
             and [opts.tile_w, opts.tile_h] == mt["tile"] and opts.kbuf == mt["kbuf"] and args.n == 500_000
             and args.views == 8):
         roof["traffic"] = float(sum(mt[dom]))
-    roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
-    roof["ms_per_launch"] = dom_ms
+    roof["ms_per_launch"] = per_kernel[dom]["ms"]
     roof["timing"] = timing_src
+    # every stage against its own roofline, and the step's time-weighted fraction
+    tot = sum(v["ms"] * v["calls"] for v in per_kernel.values())
+    roof["path_frac"] = sum(v["ms"] * v["calls"] * v["frac"] for v in per_kernel.values()) / tot if tot else None
+    roof["per_kernel"] = per_kernel
+    for name, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms"] * kv[1]["calls"]):
+        log(f"  roofline {name:10s} {v['ms']:8.3f} ms  {v['achieved']:10.2f} {v['unit']:8s} frac {v['frac']:.4f}")
+    log(f"  time-weighted path fraction {roof['path_frac']:.4f}")
 
     if mesh is not None:
         workload = (f"mesh prior: icosphere level {args.prior_level} ({mesh['idx'].shape[1]} faces), "
@@ -442,6 +484,7 @@ def main():
         "config": {"workload": workload, "views": args.views, "width": W, "height": H,
                    "faces": int(faces["idx"].shape[1]), "tile": [opts.tile_w, opts.tile_h], "kbuf": opts.kbuf,
                    "hip_graph": not args.no_graph, "stored_lists_rows": args.list_rows,
+                   "deterministic_sums": bool(args.deterministic),
                    "face_order": "input" if (args.input_order or mesh is not None) else "morton",
                    "entries_per_step": entries, "fragments_per_step": frags,
                    "fragments_per_s": frags / dt, "entries_per_s": entries / dt, **prep_ms},

@@ -97,6 +97,9 @@ typedef struct msp_render_opts {
                              list_rows fragments per pixel) for msp_render_backward, which then
                              does not recompute them; lists longer than that fall back to
                              recomputation. 0: the backward recomputes the lists (least memory). */
+  int32_t deterministic;  /* 1: msp_render_backward sums the gradients in 64-bit fixed point, so
+                             repeated backwards give identical bits (about 2x the gradient pass);
+                             0: float atomics, whose summation order (last bits) varies by run */
 } msp_render_opts;
 
 /* Gradients, caller-owned, OVERWRITTEN by msp_render_backward (not accumulated).
@@ -201,13 +204,36 @@ msp_status msp_render(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, 
                       const msp_render_opts* opts, float* img, msp_state* st);
 
 /* Adjoint of the last msp_render made with `st`. dimg is [n_views][4][H][W]
- * (dL/dRGBA). Fragment lists are recomputed, not stored. The derivative
- * freezes which fragments cover each pixel and their order (no edge or
- * visibility terms) and is exact otherwise; the opacity clamp passes the
- * gradient only where 0 < b . o < 1. Synchronises the stream once (to size the
- * recomputed lists). ESTALE if `f` is not the soup the state was rendered with. */
+ * (dL/dRGBA). The derivative freezes which fragments cover each pixel and
+ * their order (no edge or visibility terms) and is exact otherwise; the
+ * opacity clamp passes the gradient only where 0 < b . o < 1. Each fragment's
+ * barycentrics and ray/triangle Jacobian are recomputed in float64 from the
+ * world corners, so faces seen nearly edge-on keep full precision.
+ * Fragment lists: when the render stored them (opts.list_rows > 0) they are
+ * read as stored; this call then synchronises the stream once, to read a flag
+ * telling whether some pixel had more fragments than list_rows, in which case
+ * (and when list_rows = 0) it recomputes every pixel's ordered list into
+ * library scratch sized on the host, which costs a second synchronisation.
+ * Sums: float atomics by default (last bits vary between runs); with
+ * opts.deterministic = 1 at render time, 64-bit fixed-point sums whose
+ * result does not depend on the order of additions (identical bits on every
+ * run, about twice the gradient pass's time and 8 bytes per summed value of
+ * extra scratch). Every non-NULL gradient array is overwritten; drgb is zero
+ * in SH mode; dsh (SH mode) may be NULL, the position gradient still
+ * includes the colour's dependence on the view direction. ESTALE if `f` is not
+ * the soup the state was rendered with. */
 msp_status msp_render_backward(msp_ctx* ctx, msp_state* st, const msp_faces* f, const float* dimg,
                                msp_face_grads* grads);
+
+/* Capacity report of a state. Synchronises the stream, then returns MSP_OK if
+ * every bounded buffer of every render, backward and captured step made with
+ * `st` since its creation held what it was given, and MSP_EOVERFLOW if one
+ * fell short and the library recovered: stored fragment lists too short for
+ * some pixel (that backward recomputed the lists, and the state recomputes
+ * from then on), or a captured replay beyond the capacities of its capture
+ * (the step was re-run uncaptured and captured again). Results are complete
+ * in both cases; the status tells the caller that a capacity was short. */
+msp_status msp_state_status(msp_ctx* ctx, msp_state* st);
 
 /* ---- fine-tuning (fine-tuning section: loss, optimiser, pruning) ---------- */
 
@@ -452,7 +478,10 @@ msp_status msp_refiner_loss(msp_ctx* ctx, msp_refiner* r, const float* y, const 
  * then captures it with 1.5x those capacities. Later calls replay the graph
  * and synchronise once to read an overflow flag; if the scene grew past a
  * capacity, the step is re-run uncaptured and captured again, so the result is
- * always complete. Results are as with msp_render / msp_render_backward. */
+ * always complete. Results are as with msp_render / msp_render_backward.
+ * An uncaptured msp_render or msp_render_backward on the same state discards
+ * the captured graph (it may move the state's buffers and replaces its
+ * cameras), so the next msp_step_graph captures again. */
 msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
                           const msp_render_opts* opts, float* img, const float* dimg, msp_face_grads* grads,
                           msp_state* st);

@@ -142,10 +142,11 @@ class RenderOptions:
     bg: tuple = (0.0, 0.0, 0.0)
     color_mode: int = MSP_COLOR_RGB
     list_rows: int = 0     # > 0: the forward stores fragment lists for the backward (0: recomputed)
+    deterministic: int = 0  # 1: fixed-point gradient sums, identical bits on every run
 
     def struct(self) -> _lib.RenderOpts:
         return _lib.RenderOpts(self.tile_w, self.tile_h, self.kbuf, self.color_mode, self.t_eps,
-                               (C.c_float * 3)(*self.bg), self.list_rows)
+                               (C.c_float * 3)(*self.bg), self.list_rows, int(self.deterministic))
 
 
 class RenderState:
@@ -166,6 +167,11 @@ class RenderState:
                 self.h = None
         except Exception:
             pass
+
+    def status(self) -> int:
+        """MSP_OK (0), or MSP_EOVERFLOW (-4) when a bounded buffer of this state fell
+        short and the library recovered (results complete either way)."""
+        return int(self.ctx.lib.msp_state_status(self.ctx.h, self.h))
 
     def stats(self) -> dict:
         s = _lib.RenderStats()
@@ -324,7 +330,8 @@ def autotune(faces: dict, cams, base: "RenderOptions", dimg=None) -> "RenderOpti
                                    None if dimg is None else _dev_ptr(_need(dimg, torch.float32, "dimg")),
                                    C.byref(G), C.byref(out)), "msp_autotune")
     return RenderOptions(tile_w=out.tile_w, tile_h=out.tile_h, kbuf=out.kbuf, t_eps=out.t_eps,
-                         bg=tuple(out.bg), color_mode=out.color_mode, list_rows=out.list_rows)
+                         bg=tuple(out.bg), color_mode=out.color_mode, list_rows=out.list_rows,
+                         deterministic=out.deterministic)
 
 
 MSP_LOSS_MSE, MSP_LOSS_L1, MSP_LOSS_L1_DSSIM = 0, 1, 2

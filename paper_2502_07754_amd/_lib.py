@@ -44,7 +44,7 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("kbuf", C.c_int32), ("color_mode", C.c_int32),
-                ("t_eps", C.c_float), ("bg", C.c_float * 3), ("list_rows", C.c_int32)]
+                ("t_eps", C.c_float), ("bg", C.c_float * 3), ("list_rows", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class FaceGrads(C.Structure):
@@ -82,6 +82,7 @@ EXPORTS = {
     "msp_debug_nfrag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "msp_step_graph": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),
                                  C.c_void_p, C.c_void_p, C.POINTER(FaceGrads), C.c_void_p]),
+    "msp_state_status": (C.c_int, [C.c_void_p, C.c_void_p]),
     "msp_graph_info": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64)]),
     "msp_autotune": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.POINTER(Camera), C.c_int, C.POINTER(RenderOpts),

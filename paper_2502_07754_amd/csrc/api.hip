@@ -738,9 +738,11 @@ msp_status msp_state_free(msp_ctx* ctx, msp_state* st) {
   if (!ctx || !st) return MSP_EINVAL;
   DeviceGuard dg(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&st->cams, &st->geo, &st->attr, &st->tile_cnt, &st->tile_off, &st->cursor,
-                    &st->keys, &st->tmp, &st->nfrag, &st->counters, &st->scan_part, &st->blk_cap,
-                    &st->blk_off, &st->frag_list, &st->col4, &st->dcol, &st->fp_part};
+  DevBuf* bufs[] = {&st->cams,  &st->geo,     &st->attr,      &st->tile_cnt, &st->tile_off, &st->cursor,
+                    &st->keys,  &st->tmp,     &st->nfrag,     &st->counters, &st->scan_part, &st->blk_cap,
+                    &st->blk_off, &st->frag_list, &st->col4,  &st->dcol,     &st->fp_part,  &st->crec,
+                    &st->camd,  &st->acc64,   &st->accsh64,   &st->dcol64,
+                    &st->det,   &st->shgv};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   free_graph(ctx, st);
@@ -784,6 +786,23 @@ static void fill_args(msp_state* st, const msp_faces* f, RasterArgs& a) {
   a.counters = P<unsigned long long>(st->counters);
   a.ovf = reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5);
   a.fp_part = P<unsigned long long>(st->fp_part);
+  a.crec = st->color_mode == MSP_COLOR_RGB ? P<float4>(st->crec) : nullptr;
+  a.camd = P<double>(st->camd);
+}
+
+// Per view, in double: the camera centre -R^-1 t and R^-1 of the float32
+// world-to-camera matrix [R | t] (the exact inverse, not R^T, so that a ray
+// mapped to world space is the float64 image of the camera-space one).
+static void camera_doubles(const msp_camera& c, double* out) {
+  const float* w = c.world_to_cam;
+  const double a = w[0], b = w[1], cc = w[2], d = w[4], e = w[5], f = w[6], g = w[8], h = w[9], i = w[10];
+  const double det = a * (e * i - f * h) - b * (d * i - f * g) + cc * (d * h - e * g);
+  const double inv[9] = {(e * i - f * h) / det, (cc * h - b * i) / det, (b * f - cc * e) / det,
+                         (f * g - d * i) / det, (a * i - cc * g) / det, (cc * d - a * f) / det,
+                         (d * h - e * g) / det, (b * g - a * h) / det, (a * e - b * d) / det};
+  const double tx = w[3], ty = w[7], tz = w[11];
+  for (int r = 0; r < 3; ++r) out[r] = -(inv[3 * r] * tx + inv[3 * r + 1] * ty + inv[3 * r + 2] * tz);
+  for (int k = 0; k < 9; ++k) out[3 + k] = inv[k];
 }
 
 static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams, int n_views,
@@ -813,6 +832,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   if (f->n_faces < 0 || f->n_verts < 0 || f->n_faces >= (int64_t(1) << 31) || f->n_verts >= (int64_t(1) << 31))
     return bad("face or vertex count out of range");
   if (f->n_faces > 0 && (!f->pos || !f->opacity || !f->idx)) return bad("null face array");
+  if (f->n_faces > 0 && f->n_verts < 1) return bad("faces without vertices");
   const int W = cams[0].width, H = cams[0].height;
   if (W < 1 || H < 1 || W > 16384 || H > 16384) return bad("width/height outside [1, 16384]");
   for (int v = 0; v < n_views; ++v) {
@@ -830,8 +850,19 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   if (opts->color_mode == MSP_COLOR_SH3 && f->n_faces > 0 && !f->sh) return bad("SH mode needs f->sh");
   if (opts->color_mode == MSP_COLOR_SH3 && n_views > sh_max_views()) return bad("SH mode supports at most 64 views");
   if (opts->list_rows < 0 || opts->list_rows > 4096) return bad("list_rows must be in [0, 4096]");
+  if (opts->deterministic != 0 && opts->deterministic != 1) return bad("deterministic must be 0 or 1");
+  for (int v = 0; v < n_views; ++v) {
+    const float* w = cams[v].world_to_cam;
+    const double det = (double)w[0] * ((double)w[5] * w[10] - (double)w[6] * w[9]) -
+                       (double)w[1] * ((double)w[4] * w[10] - (double)w[6] * w[8]) +
+                       (double)w[2] * ((double)w[4] * w[9] - (double)w[5] * w[8]);
+    if (!(std::fabs(det) > 1e-12)) return bad("camera rotation is singular");
+  }
 
   DeviceGuard dg(ctx->device);
+  // an uncaptured render may move the state's buffers and changes its cameras:
+  // a graph captured before it must not be replayed
+  if (!graph) free_graph(ctx, st);
   st->n_views = n_views;
   st->W = W;
   st->H = H;
@@ -839,6 +870,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   st->tile_h = th;
   st->kbuf = kb;
   st->color_mode = opts->color_mode;
+  st->det_mode = opts->deterministic;
   st->ntx = (W + tw - 1) / tw;
   st->nty = (H + th - 1) / th;
   st->n_tiles = (int64_t)st->ntx * st->nty;
@@ -858,7 +890,9 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
       (rc = msp_ensure(ctx, st->tile_cnt, 4 * NT)) || (rc = msp_ensure(ctx, st->tile_off, 8 * (NT + 1))) ||
       (rc = msp_ensure(ctx, st->cursor, 4 * NT)) || (rc = msp_ensure(ctx, st->nfrag, 4 * npix)) ||
       (rc = msp_ensure(ctx, st->counters, 32 * 8)) || (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(NT))) ||
-      (rc = msp_ensure(ctx, st->fp_part, 8 * V * ((F + 255) / 256))))
+      (rc = msp_ensure(ctx, st->fp_part, 8 * V * ((F + 255) / 256))) ||
+      (rc = msp_ensure(ctx, st->camd, sizeof(double) * 12 * V)) ||
+      (opts->color_mode == MSP_COLOR_RGB && (rc = msp_ensure(ctx, st->crec, 48 * F))))
     return (msp_status)rc;
   st->fp_parts = F > 0 ? V * ((F + 255) / 256) : 0;
   if (st->h_cams_cap < n_views) {
@@ -867,8 +901,13 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
     st->h_cams_cap = n_views;
   }
   std::memcpy(st->h_cams, cams, sizeof(msp_camera) * n_views);
+  st->h_camd.resize(12 * (size_t)n_views);
+  for (int v = 0; v < n_views; ++v) camera_doubles(cams[v], st->h_camd.data() + 12 * v);
   hipStream_t s = ctx->stream;
-  if (!graph) MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
+  if (!graph) {
+    MSP_HIP(ctx, hipMemcpyAsync(st->cams.p, st->h_cams, sizeof(msp_camera) * V, hipMemcpyHostToDevice, s));
+    MSP_HIP(ctx, hipMemcpyAsync(st->camd.p, st->h_camd.data(), sizeof(double) * 12 * V, hipMemcpyHostToDevice, s));
+  }
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->tile_cnt), 0u, NT));
   MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->counters), 0u, 64));
 
@@ -922,87 +961,125 @@ static msp_status backward_impl(msp_ctx* ctx, msp_state* st, const msp_faces* f,
   if (!st->rendered) return bad("state has no render");
   if (f->pos != st->faces_pos || f->idx != st->faces_idx || f->n_faces != st->n_faces || f->n_verts != st->n_verts)
     return (msp_status)msp_fail(ctx, MSP_ESTALE, "msp_render_backward: faces differ from the rendered ones");
-  DeviceGuard dg(ctx->device);
-  hipStream_t s = ctx->stream;
-  const int64_t Vn = f->n_verts;
-  if (grads->dpos) MSP_HIP(ctx, launch_fill_f32(s, grads->dpos, 0.f, 3 * Vn));
-  if (grads->dopacity) MSP_HIP(ctx, launch_fill_f32(s, grads->dopacity, 0.f, Vn));
-  if (grads->drgb) MSP_HIP(ctx, launch_fill_f32(s, grads->drgb, 0.f, 3 * Vn));
   const bool shm = st->color_mode == MSP_COLOR_SH3;
-  // dsh needs no clearing: the SH adjoint at the end writes all 48 F values
-  if (f->n_faces == 0) return MSP_OK;
-  if (shm && !f->sh) return bad("SH render state needs f->sh");
-  const int64_t nb = (int64_t)st->n_views * ((st->W + 7) / 8) * ((st->H + 7) / 8);
+  if (shm && f->n_faces > 0 && !f->sh) return bad("SH render state needs f->sh");
+  DeviceGuard dg(ctx->device);
+  // an uncaptured backward may grow (move) the state's buffers
+  if (!graph) free_graph(ctx, st);
+  hipStream_t s = ctx->stream;
+  const int64_t Vn = f->n_verts, F = f->n_faces, NV = st->n_views;
+  const bool det = st->det_mode != 0;
+  const int64_t nb = NV * ((st->W + 7) / 8) * ((st->H + 7) / 8);
   int rc;
+  // gradient accumulators: float sums, or 64-bit fixed-point sums in deterministic mode
   if ((rc = msp_ensure(ctx, st->blk_cap, 4 * nb)) || (rc = msp_ensure(ctx, st->blk_off, 8 * (nb + 1))) ||
-      (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(nb))))
+      (rc = msp_ensure(ctx, st->scan_part, scan_scratch_bytes(nb))) ||
+      (det && (rc = msp_ensure(ctx, st->acc64, 7 * 8 * Vn))) ||
+      (det && (rc = msp_ensure(ctx, st->det, 256))) ||
+      (det && shm && (rc = msp_ensure(ctx, st->accsh64, 3 * 8 * Vn))) ||
+      (det && shm && (rc = msp_ensure(ctx, st->shgv, 16 * F))) ||
+      (shm && (rc = msp_ensure(ctx, st->dcol, 3 * 4 * NV * F))) ||
+      (det && shm && (rc = msp_ensure(ctx, st->dcol64, 3 * 8 * NV * F))))
     return (msp_status)rc;
   RasterArgs a;
   fill_args(st, f, a);
   a.blk_cap = P<uint32_t>(st->blk_cap);
   a.blk_off = P<int64_t>(st->blk_off);
-  bool stored = st->store_rows > 0;
-  if (stored && !graph) {
-    // lists stored by the forward are used unless a block overflowed them
-    MSP_HIP(ctx, hipMemcpyAsync(st->h_flag, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5),
-                                sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    MSP_HIP(ctx, hipStreamSynchronize(s));
-    if (*st->h_flag & 4u) {
-      stored = false;
-      st->lists_overflowed = true;
-      st->store_rows = 0;
+  a.dimg = dimg;
+  a.dcol = shm ? P<float>(st->dcol) : nullptr;
+  uint32_t* det_max = nullptr;
+  unsigned long long* det_cnt = nullptr;
+  double* det_scale = nullptr;
+  if (det) {
+    // det: [0, 64) maxima (DT_N + 1 words), [64, 128) counts, [128, 256) scales and inverses
+    det_max = P<uint32_t>(st->det);
+    det_cnt = reinterpret_cast<unsigned long long*>(P<unsigned char>(st->det) + 64);
+    det_scale = reinterpret_cast<double*>(P<unsigned char>(st->det) + 128);
+    a.acc64 = P<unsigned long long>(st->acc64);
+    a.dcol64 = shm ? P<unsigned long long>(st->dcol64) : nullptr;
+    a.det_max = det_max;
+    a.det_cnt = det_cnt;
+    a.det_scale = det_scale;
+    MSP_HIP(ctx, launch_fill_u32(s, P<uint32_t>(st->det), 0u, 32));
+    MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(a.acc64), 0u, 14 * Vn));
+    if (shm) {
+      MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->accsh64)), 0u, 6 * Vn));
+      MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(a.dcol64), 0u, 6 * NV * F));
     }
-  }
-  if (stored) {
-    a.dimg = dimg;
+  } else {
+    // float sums go straight into the caller's arrays
     a.dpos = grads->dpos;
     a.dop = grads->dopacity;
     a.drgb = shm ? nullptr : grads->drgb;
-    a.frag_list = P<uint2>(st->frag_list);
-    a.store_rows = st->store_rows;
-    if (shm) {
-      const int64_t nc = 3 * (int64_t)st->n_views * f->n_faces;
-      if ((rc = msp_ensure(ctx, st->dcol, sizeof(float) * nc))) return (msp_status)rc;
-      MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
-      a.dcol = P<float>(st->dcol);
+    if (grads->dpos) MSP_HIP(ctx, launch_fill_f32(s, grads->dpos, 0.f, 3 * Vn));
+    if (grads->dopacity) MSP_HIP(ctx, launch_fill_f32(s, grads->dopacity, 0.f, Vn));
+    if (grads->drgb) MSP_HIP(ctx, launch_fill_f32(s, grads->drgb, 0.f, 3 * Vn));
+  }
+  if (shm) MSP_HIP(ctx, launch_fill_f32(s, a.dcol, 0.f, 3 * NV * F));
+  // dsh needs no clearing: the SH adjoint at the end writes all 48 F values
+  if (F > 0) {
+    bool stored = st->store_rows > 0;
+    if (stored && !graph) {
+      // lists stored by the forward are used unless a block overflowed them
+      MSP_HIP(ctx, hipMemcpyAsync(st->h_flag, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 5),
+                                  sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      MSP_HIP(ctx, hipStreamSynchronize(s));
+      if (*st->h_flag & 4u) {
+        stored = false;
+        st->lists_overflowed = true;
+        st->store_rows = 0;
+      }
     }
-    MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 16), 0u, 32));
-    MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
-    if (shm && grads->dsh)
-      MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
-    return MSP_OK;
+    if (stored) {
+      a.frag_list = P<uint2>(st->frag_list);
+      a.store_rows = st->store_rows;
+    } else {
+      a.store_rows = 0;
+      MSP_TIMED(ctx, ST_BLOCK_MAX, launch_block_max(s, a));
+      MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
+      if (graph) {
+        MSP_HIP(ctx, launch_cap_guard(s, P<int64_t>(st->blk_off) + nb, (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE)),
+                                      a.ovf, 2u));
+      } else {
+        int64_t rows = 0;
+        MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MSP_HIP(ctx, hipStreamSynchronize(s));
+        if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * (rows > 0 ? rows : 1))))
+          return (msp_status)rc;
+        st->rows = rows;
+      }
+      a.frag_list = P<uint2>(st->frag_list);
+      a.frag_cap = (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE));
+      // reset the backward work queues (counters 16..31)
+      MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 16), 0u, 32));
+      MSP_TIMED(ctx, ST_BWD_LISTS, launch_bwd_lists(s, a, st->kbuf, ctx->n_cu));
+    }
+    uint32_t* gq = reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 24);
+    MSP_HIP(ctx, launch_fill_u32(s, gq, 0u, 16));
+    if (!det) {
+      MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu, 0));
+    } else {
+      // deterministic: maxima and counts, the scales, then the fixed-point sums
+      MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu, 1));
+      MSP_HIP(ctx, launch_det_scales(s, det_max, det_cnt, det_scale, DT_POS, DT_COL + 1));
+      MSP_HIP(ctx, launch_fill_u32(s, gq, 0u, 16));
+      MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu, 2));
+      if (shm) MSP_HIP(ctx, launch_dcol_finalize(s, a.dcol64, 3 * NV * F, det_scale, a.dcol));
+    }
+    if (shm) {
+      MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, a.dcol, grads->dsh, det ? nullptr : grads->dpos,
+                                              det ? P<float4>(st->shgv) : nullptr, det_max, det_cnt));
+      if (det) {
+        MSP_HIP(ctx, launch_det_scales(s, det_max, det_cnt, det_scale, DT_SHPOS, DT_SHPOS + 1));
+        MSP_HIP(ctx, launch_sh_fix(s, f, P<float4>(st->shgv), det_scale, P<unsigned long long>(st->accsh64)));
+      }
+    }
   }
-  a.store_rows = 0;
-  MSP_TIMED(ctx, ST_BLOCK_MAX, launch_block_max(s, a));
-  MSP_HIP(ctx, launch_scan_u32(s, a.blk_cap, P<int64_t>(st->blk_off), nb, st->scan_part.p));
-  if (graph) {
-    MSP_HIP(ctx, launch_cap_guard(s, P<int64_t>(st->blk_off) + nb, (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE)),
-                                  a.ovf, 2u));
-  } else {
-    int64_t rows = 0;
-    MSP_HIP(ctx, hipMemcpyAsync(&rows, P<int64_t>(st->blk_off) + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    MSP_HIP(ctx, hipStreamSynchronize(s));
-    if ((rc = msp_ensure(ctx, st->frag_list, sizeof(uint2) * MSP_WAVE * (rows > 0 ? rows : 1)))) return (msp_status)rc;
-    st->rows = rows;
-  }
-  a.frag_list = P<uint2>(st->frag_list);
-  a.frag_cap = (int64_t)(st->frag_list.bytes / (8 * MSP_WAVE));
-  a.dimg = dimg;
-  a.dpos = grads->dpos;
-  a.dop = grads->dopacity;
-  a.drgb = shm ? nullptr : grads->drgb;
-  if (shm) {
-    const int64_t nc = 3 * (int64_t)st->n_views * f->n_faces;
-    if ((rc = msp_ensure(ctx, st->dcol, sizeof(float) * nc))) return (msp_status)rc;
-    MSP_HIP(ctx, launch_fill_f32(s, P<float>(st->dcol), 0.f, nc));
-    a.dcol = P<float>(st->dcol);
-  }
-  // reset the backward work queues (counters 16..31)
-  MSP_HIP(ctx, launch_fill_u32(s, reinterpret_cast<uint32_t*>(P<unsigned long long>(st->counters) + 16), 0u, 32));
-  MSP_TIMED(ctx, ST_BWD_LISTS, launch_bwd_lists(s, a, st->kbuf, ctx->n_cu));
-  MSP_TIMED(ctx, ST_BWD_GRADS, launch_bwd_grads(s, a, ctx->n_cu));
-  if (shm && grads->dsh)
-    MSP_TIMED(ctx, ST_SH_BWD, launch_sh_bwd(s, f, st->h_cams, st->n_views, P<float>(st->dcol), grads->dsh, grads->dpos));
+  // deterministic mode: the fixed-point sums overwrite the caller's gradients in full
+  // (drgb is zero in SH mode); float mode has written them directly
+  if (det)
+    MSP_HIP(ctx, launch_det_finalize(s, a.acc64, shm && F > 0 ? P<unsigned long long>(st->accsh64) : nullptr,
+                                     det_scale, Vn, grads->dpos, grads->dopacity, grads->drgb));
   return MSP_OK;
 }
 
@@ -1188,6 +1265,13 @@ msp_status msp_autotune(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams
   ctx->tuned_tile_h = best_o.tile_h;
   ctx->tuned_kbuf = best_o.kbuf;
   return MSP_OK;
+}
+
+msp_status msp_state_status(msp_ctx* ctx, msp_state* st) {
+  if (!ctx || !st) return MSP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  MSP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return (st->lists_overflowed || st->graph_overflows > 0) ? MSP_EOVERFLOW : MSP_OK;
 }
 
 msp_status msp_graph_info(msp_ctx* ctx, msp_state* st, int64_t* captures, int64_t* replays, int64_t* overflows) {

@@ -52,6 +52,7 @@ struct msp_state {
   int64_t max_tile = 0;
   bool rendered = false;
   msp_camera* h_cams = nullptr;  // host copy
+  std::vector<double> h_camd;    // per view: camera centre and R^-1 in double (uploaded to camd)
   int h_cams_cap = 0;
   int64_t rows = 0;              // backward list rows of the last uncaptured run
   int64_t store_rows = 0;        // rows per block the forward stores lists into (0: none)
@@ -66,7 +67,8 @@ struct msp_state {
   std::vector<TimerRec> graph_timer;  // stage events captured into the graph (timing on at capture)
 
   DevBuf cams, geo, attr, tile_cnt, tile_off, cursor, keys, tmp, nfrag, counters,
-      scan_part, blk_cap, blk_off, frag_list, col4, dcol, fp_part;
+      scan_part, blk_cap, blk_off, frag_list, col4, dcol, fp_part, crec, camd, acc64, accsh64, dcol64, det, shgv;
+  int det_mode = 0;              // deterministic gradient sums requested by the last render's options
   int64_t fp_parts = 0;          // entries of fp_part written by the last render
 };
 
@@ -138,6 +140,9 @@ hipError_t launch_spatial_order(hipStream_t s, const float* mean, int64_t n, con
 size_t scan_scratch_bytes(int64_t n);
 hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, int64_t* out, int64_t n, void* scratch);
 
+// value classes of the deterministic (fixed-point) gradient sums
+enum : int { DT_POS = 0, DT_OP = 1, DT_RGB = 2, DT_COL = 3, DT_SHPOS = 4, DT_N = 5 };
+
 struct RasterArgs {
   const float* pos;
   const float* opacity;
@@ -148,7 +153,7 @@ struct RasterArgs {
   int n_views, W, H, tile_w, tile_h, ntx, nty;
   int64_t n_tiles;         // per view
   float4* geo;             // [V][F][3] per-view geometry records (setup)
-  float4* attr;            // [F][4] corner opacities, colours and vertex ids
+  float4* attr;            // [F][4] corner opacities, world corners and vertex ids
   uint32_t* tile_cnt;      // [V * n_tiles]
   int64_t* tile_off;       // [V * n_tiles + 1]
   uint32_t* cursor;        // [V * n_tiles]
@@ -171,16 +176,30 @@ struct RasterArgs {
   int64_t store_rows;      // rows per 8x8 block of lists stored by the forward (0: recompute in backward)
   int64_t frag_cap;
   uint32_t* blk_cap;       // [n_blocks]
-  float* dpos;
-  float* dop;
-  float* drgb;
-  float* dcol;             // SH mode: [V][3][F]
+  float4* crec;            // RGB mode: [F][3] corner colours (r0 g0 b0 r1)(g1 b1 r2 g2)(b2 - - -)
+  const double* camd;      // [n_views][12]: camera centre (world) and R^-1 (row-major), float64
+  float* dpos;             // [3][V] caller's gradients, summed with float atomics (NULL: not wanted)
+  float* dop;              // [V]
+  float* drgb;             // [3][V] (RGB mode)
+  float* dcol;             // SH mode: [n_views][3][F] colour gradient
+  // deterministic mode (fixed-point sums)
+  unsigned long long* acc64;   // [7][V]: planes dpos x, y, z, dop, drgb r, g, b
+  unsigned long long* dcol64;  // SH mode: [n_views][3][F]
+  uint32_t* det_max;           // [DT_N + 1]: largest |value| per class (float bits); [DT_N] bit 0: a non-finite value
+  unsigned long long* det_cnt; // [DT_N]: values added per class
+  const double* det_scale;     // [2 DT_N]: 2^s per class, then 2^-s
 };
 
 int sh_max_views();
 hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, float4* col4);
+// SH adjoint: dsh written (if not NULL); the position terms of the colour
+// direction are added into dpos [3][V] (float atomics) or, in deterministic mode
+// (gv != nullptr), written per face to gv ([F], value / 3 for each corner) with
+// their maxima and counts, and summed by launch_sh_fix into accsh64 [3][V]
 hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, const float* dcol,
-                         float* dsh, float* dpos);
+                         float* dsh, float* dpos, float4* gv, uint32_t* det_max, unsigned long long* det_cnt);
+hipError_t launch_sh_fix(hipStream_t s, const msp_faces* f, const float4* gv, const double* scale,
+                         unsigned long long* accsh64);
 
 size_t loss_scratch_bytes(int V, int H, int W, int kind);
 hipError_t launch_loss(hipStream_t s, int kind, float lambda, const float* img, const float* tgt, int V, int H, int W,
@@ -238,7 +257,15 @@ hipError_t launch_tile_sort(hipStream_t s, const RasterArgs& a);
 hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
 hipError_t launch_block_max(hipStream_t s, const RasterArgs& a);
 hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_cu);
-hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu);
+// mode 0: float atomics; 1: maxima and counts of the values (deterministic mode, first run);
+// 2: fixed-point sums (deterministic mode, second run)
+hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu, int mode);
+hipError_t launch_det_scales(hipStream_t s, const uint32_t* det_max, const unsigned long long* det_cnt, double* scale,
+                             int c0, int c1);
+hipError_t launch_dcol_finalize(hipStream_t s, const unsigned long long* dcol64, int64_t n, const double* scale,
+                                float* dcol);
+hipError_t launch_det_finalize(hipStream_t s, const unsigned long long* acc64, const unsigned long long* accsh64,
+                               const double* scale, int64_t V, float* dpos, float* dop, float* drgb);
 
 // ---- per-stage timing with HIP events on the context stream ----
 enum MspStage {

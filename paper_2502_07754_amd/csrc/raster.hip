@@ -228,7 +228,9 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
     if (tkey[i] >= 0) atomicAdd(&cnt[tkey[i]], tcnt[i]);
 }
 
-// attribute record (4 float4): (o0, o1, o2, id0) (r0, g0, b0, id1) (r1, g1, b1, id2) (r2, g2, b2, 0)
+// attribute record (4 float4, view independent): (o0, o1, o2, id0) (p0, id1) (p1, id2) (p2, 0),
+// the corner opacities, world positions and vertex ids; in RGB mode also the
+// corner colours (3 float4): (r0, g0, b0, r1) (g1, b1, r2, g2) (b2, 0, 0, 0)
 __global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
   const int64_t F = a.n_faces, V = a.n_verts;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,14 +241,14 @@ __global__ __launch_bounds__(256) void k_face_attr(RasterArgs a) {
     if ((uint64_t)id[k] >= (uint64_t)V) id[k] = 0;  // such faces are culled in setup and never drawn
   float4* r = a.attr + f * 4;
   r[0] = make_float4(a.opacity[id[0]], a.opacity[id[1]], a.opacity[id[2]], __int_as_float(id[0]));
-  if (a.rgb) {
-    r[1] = make_float4(a.rgb[id[0]], a.rgb[V + id[0]], a.rgb[2 * V + id[0]], __int_as_float(id[1]));
-    r[2] = make_float4(a.rgb[id[1]], a.rgb[V + id[1]], a.rgb[2 * V + id[1]], __int_as_float(id[2]));
-    r[3] = make_float4(a.rgb[id[2]], a.rgb[V + id[2]], a.rgb[2 * V + id[2]], 0.f);
-  } else {
-    r[1] = make_float4(0.f, 0.f, 0.f, __int_as_float(id[1]));
-    r[2] = make_float4(0.f, 0.f, 0.f, __int_as_float(id[2]));
-    r[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+  r[1] = make_float4(a.pos[id[0]], a.pos[V + id[0]], a.pos[2 * V + id[0]], __int_as_float(id[1]));
+  r[2] = make_float4(a.pos[id[1]], a.pos[V + id[1]], a.pos[2 * V + id[1]], __int_as_float(id[2]));
+  r[3] = make_float4(a.pos[id[2]], a.pos[V + id[2]], a.pos[2 * V + id[2]], 0.f);
+  if (a.rgb && a.crec) {
+    float4* c = a.crec + f * 3;
+    c[0] = make_float4(a.rgb[id[0]], a.rgb[V + id[0]], a.rgb[2 * V + id[0]], a.rgb[id[1]]);
+    c[1] = make_float4(a.rgb[V + id[1]], a.rgb[2 * V + id[1]], a.rgb[id[2]], a.rgb[V + id[2]]);
+    c[2] = make_float4(a.rgb[2 * V + id[2]], 0.f, 0.f, 0.f);
   }
 }
 
@@ -493,23 +495,10 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(RasterArgs a, int64_
 // Edge k is the one opposite corner k, oriented so that inside is >= 0 and
 // evaluated relative to the centre of the block's first pixel.
 struct Fetched {
-  float4 g0, g1, g2, a0, a1, a2, a3;
+  float4 g0, g1, g2;  // geometry record of the view
+  float4 a0;          // corner opacities (and vertex id 0)
+  float4 c0, c1, c2;  // colours: the corners' (RGB mode) or the face's for the view in c0 (SH mode)
 };
-
-__device__ __forceinline__ Fetched fetch_face(const RasterArgs& a, int view, int32_t f) {
-  Fetched q;
-  const float4* g = a.geo + ((int64_t)view * a.n_faces + f) * 3;
-  q.g0 = g[0];
-  q.g1 = g[1];
-  q.g2 = g[2];
-  const float4* r = a.attr + (int64_t)f * 4;
-  q.a0 = r[0];
-  const bool sh = a.col4 != nullptr;
-  q.a1 = sh ? a.col4[(int64_t)view * a.n_faces + f] : r[1];
-  q.a2 = sh ? make_float4(0.f, 0.f, 0.f, 0.f) : r[2];
-  q.a3 = sh ? make_float4(0.f, 0.f, 0.f, 0.f) : r[3];
-  return q;
-}
 
 __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float rx, float ry, float* R) {
 #pragma clang fp contract(off)
@@ -533,9 +522,9 @@ __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float
   R[14] = q.a0.y;
   R[15] = q.a0.z;
   R[16] = __uint_as_float(f);
-  R[17] = q.a1.x; R[18] = q.a1.y; R[19] = q.a1.z;
-  R[20] = q.a2.x; R[21] = q.a2.y; R[22] = q.a2.z;
-  R[23] = q.a3.x; R[24] = q.a3.y; R[25] = q.a3.z;
+  R[17] = q.c0.x; R[18] = q.c0.y; R[19] = q.c0.z;
+  R[20] = q.c0.w; R[21] = q.c1.x; R[22] = q.c1.y;
+  R[23] = q.c1.z; R[24] = q.c1.w; R[25] = q.c2.x;
   R[26] = 0.f;
   R[27] = 0.f;
   return true;
@@ -724,23 +713,6 @@ struct RegBuf {
   }
 };
 
-// Loads entry `e` of the tile list (key, records), used one chunk ahead of its use.
-struct Prefetch {
-  uint64_t key;
-  bool ok;
-  Fetched q;
-};
-
-__device__ __forceinline__ Prefetch prefetch_entry(const RasterArgs& a, const Item& it, int64_t beg, int64_t n,
-                                                   int64_t e) {
-  Prefetch p;
-  p.key = e < n ? a.keys[beg + e] : ~0ull;
-  const uint32_t f = (uint32_t)p.key;
-  p.ok = e < n && (uint64_t)f < (uint64_t)a.n_faces;
-  p.q = fetch_face(a, it.view, p.ok ? (int32_t)f : 0);
-  return p;
-}
-
 // Ordered traversal of one 8x8 block. MODE 0 composites into C/T; MODE 1
 // records each composited fragment (face id, transmittance before it) into the
 // block's list slab. Buf is the ordering buffer.
@@ -836,15 +808,15 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
         q.g0 = gp[0];
         q.g1 = gp[1];
         q.g2 = g2;
-        const float4* ap = a.attr + (int64_t)fk * 4;
-        q.a0 = ap[0];
+        q.a0 = a.attr[(int64_t)fk * 4];
         if (a.col4) {
-          q.a1 = a.col4[(int64_t)it.view * a.n_faces + fk];
-          q.a2 = q.a3 = make_float4(0.f, 0.f, 0.f, 0.f);
+          q.c0 = a.col4[(int64_t)it.view * a.n_faces + fk];
+          q.c1 = q.c2 = make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
-          q.a1 = ap[1];
-          q.a2 = ap[2];
-          q.a3 = ap[3];
+          const float4* cp = a.crec + (int64_t)fk * 3;
+          q.c0 = cp[0];
+          q.c1 = cp[1];
+          q.c2 = cp[2];
         }
         keep = build_record(q, fk, rx, ry, R);
       }
@@ -1012,8 +984,9 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
 }
 
 // backward pass 2: back-to-front walk with per-wave LDS reduction of the face gradients.
-// Table values per face: RGB mode: dop[3] | drgb[3 corners][3] | dpos_cam[3 corners][3]
-//                        SH mode:  dop[3] | dcol[3]            | dpos_cam[3 corners][3]
+// Table values per face: RGB mode: dop[3] | drgb[3 corners][3] | dpos[3 corners][3]
+//                        SH mode:  dop[3] | dcol[3]            | dpos[3 corners][3]
+// (positions in world space).
 template <bool SH>
 struct GradLayout {
   static constexpr int NV = SH ? 15 : 21;
@@ -1025,6 +998,82 @@ struct GradLayout {
   static constexpr int VBITS = 8;
   static constexpr int VFILL = VSLOTS * 3 / 4;
 };
+
+// How a wave's sums reach global memory. ACC_F32: float atomics (the order of
+// additions from different waves varies between runs). Deterministic mode runs
+// the kernel twice: ACC_MAX finds, per value class, the largest magnitude any
+// wave adds and how many values it adds; ACC_FIX then adds every value as a
+// 64-bit fixed-point integer with a per-class scale 2^s chosen so that no sum
+// can leave the integer range. Integer addition is associative, so the sums do
+// not depend on the order of the atomics, and the per-wave sums that feed them
+// are themselves computed in a fixed order (tables private to one wave).
+enum : int { ACC_F32 = 0, ACC_MAX = 1, ACC_FIX = 2 };
+
+struct DetTrack {
+  float mx[DT_N];
+  uint32_t n[DT_N];
+  bool bad;
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int c = 0; c < DT_N; ++c) {
+      mx[c] = 0.f;
+      n[c] = 0u;
+    }
+    bad = false;
+  }
+};
+
+// adds x to element kf of the float sums fp (ACC_F32; skipped when the caller
+// asked for no such output) or to element ki of the fixed-point sums ip (ACC_FIX)
+template <int ACC>
+__device__ __forceinline__ void gadd(float* fp, int64_t kf, unsigned long long* ip, int64_t ki, int cls, float x,
+                                     const RasterArgs& a, DetTrack& d) {
+  if constexpr (ACC == ACC_F32) {
+    if (fp) atomicAdd(fp + kf, x);
+  } else if constexpr (ACC == ACC_MAX) {
+    if (!isfinite(x)) d.bad = true;
+    else d.mx[cls] = fmaxf(d.mx[cls], fabsf(x));
+    d.n[cls] += 1u;
+  } else {
+    atomicAdd(ip + ki, (unsigned long long)__double2ll_rn((double)x * a.det_scale[cls]));
+  }
+}
+
+// wave-wide maxima and counts of ACC_MAX, one atomic per wave and class
+__device__ __forceinline__ void det_publish(const RasterArgs& a, DetTrack& d, int lane) {
+#pragma unroll
+  for (int c = 0; c < DT_N; ++c) {
+    float m = d.mx[c];
+    uint32_t n = d.n[c];
+    for (int o = 32; o >= 1; o >>= 1) {
+      m = fmaxf(m, __shfl_xor(m, o));
+      n += __shfl_xor(n, o);
+    }
+    if (lane == 0 && n) {
+      atomicMax(&a.det_max[c], __float_as_uint(m));
+      atomicAdd(&a.det_cnt[c], (unsigned long long)n);
+    }
+  }
+  if (__any(d.bad) && lane == 0) atomicOr(&a.det_max[DT_N], 1u);
+}
+
+// one vertex's values c[VW] into the global sums. Each value class is a plane of
+// its own (dpos x, y, z, dop, drgb r, g, b), so the atomics of one flush go to
+// separate cache lines and L2 channels instead of queueing on one line.
+template <bool SH, int ACC>
+__device__ __forceinline__ void vert_global(const RasterArgs& a, int32_t v, const float* c, DetTrack& d) {
+  using L = GradLayout<SH>;
+  const int64_t V = a.n_verts;
+  gadd<ACC>(a.dpos, v, a.acc64, v, DT_POS, c[L::VW - 3], a, d);
+  gadd<ACC>(a.dpos, V + v, a.acc64, V + v, DT_POS, c[L::VW - 2], a, d);
+  gadd<ACC>(a.dpos, 2 * V + v, a.acc64, 2 * V + v, DT_POS, c[L::VW - 1], a, d);
+  gadd<ACC>(a.dop, v, a.acc64, 3 * V + v, DT_OP, c[0], a, d);
+  if (!SH) {
+    gadd<ACC>(a.drgb, v, a.acc64, 4 * V + v, DT_RGB, c[1], a, d);
+    gadd<ACC>(a.drgb, V + v, a.acc64, 5 * V + v, DT_RGB, c[2], a, d);
+    gadd<ACC>(a.drgb, 2 * V + v, a.acc64, 6 * V + v, DT_RGB, c[3], a, d);
+  }
+}
 
 // Per-wave vertex table: the face table's flushes pour their three vertices'
 // opacity/colour/position gradients in here, so a vertex that several faces of
@@ -1055,8 +1104,9 @@ __device__ __forceinline__ int vert_slot(const VertTable<SH>& t, uint32_t v) {
 }
 
 // one vertex's contribution c[VW]: into the table, or straight to global memory if no slot
-template <bool SH>
-__device__ __forceinline__ void vert_add(const RasterArgs& a, const VertTable<SH>& t, int32_t v, const float* c) {
+template <bool SH, int ACC>
+__device__ __forceinline__ void vert_add(const RasterArgs& a, const VertTable<SH>& t, int32_t v, const float* c,
+                                         DetTrack& d) {
   using L = GradLayout<SH>;
   const int sl = vert_slot(t, (uint32_t)v);
   if (sl >= 0) {
@@ -1064,24 +1114,12 @@ __device__ __forceinline__ void vert_add(const RasterArgs& a, const VertTable<SH
     for (int q = 0; q < L::VW; ++q) atomicAdd(&t.vals[sl * L::VW + q], c[q]);
     return;
   }
-  const int64_t V = a.n_verts;
-  if (a.dop) atomicAdd(&a.dop[v], c[0]);
-  if (!SH && a.drgb) {
-    atomicAdd(&a.drgb[v], c[1]);
-    atomicAdd(&a.drgb[V + v], c[2]);
-    atomicAdd(&a.drgb[2 * V + v], c[3]);
-  }
-  if (a.dpos) {
-    atomicAdd(&a.dpos[v], c[L::VW - 3]);
-    atomicAdd(&a.dpos[V + v], c[L::VW - 2]);
-    atomicAdd(&a.dpos[2 * V + v], c[L::VW - 1]);
-  }
+  vert_global<SH, ACC>(a, v, c, d);
 }
 
-template <bool SH>
-__device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable<SH>& t, int lane) {
+template <bool SH, int ACC>
+__device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable<SH>& t, int lane, DetTrack& d) {
   using L = GradLayout<SH>;
-  const int64_t V = a.n_verts;
   for (int sl = lane; sl < L::VSLOTS; sl += MSP_WAVE) {
     const uint32_t v = t.keys[sl];
     if (v == kEmpty) continue;
@@ -1092,28 +1130,17 @@ __device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable
       t.vals[sl * L::VW + q] = 0.f;
     }
     t.keys[sl] = kEmpty;
-    if (a.dop) atomicAdd(&a.dop[v], c[0]);
-    if (!SH && a.drgb) {
-      atomicAdd(&a.drgb[v], c[1]);
-      atomicAdd(&a.drgb[V + v], c[2]);
-      atomicAdd(&a.drgb[2 * V + v], c[3]);
-    }
-    if (a.dpos) {
-      atomicAdd(&a.dpos[v], c[L::VW - 3]);
-      atomicAdd(&a.dpos[V + v], c[L::VW - 2]);
-      atomicAdd(&a.dpos[2 * V + v], c[L::VW - 1]);
-    }
+    vert_global<SH, ACC>(a, (int32_t)v, c, d);
   }
   if (lane == 0) *t.fill = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 }
 
-template <bool SH>
-__device__ __forceinline__ void flush_table(const RasterArgs& a, int view, const float (&Wc)[12], uint32_t* keys, float* vals,
-                            uint32_t* fill, const VertTable<SH>& vt, int lane) {
+template <bool SH, int ACC>
+__device__ __forceinline__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float* vals,
+                                            uint32_t* fill, const VertTable<SH>& vt, int lane, DetTrack& d) {
   using L = GradLayout<SH>;
-  const int64_t F = a.n_faces;
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) {
     const uint32_t f = keys[s];
     if (f == kEmpty) continue;
@@ -1126,11 +1153,12 @@ __device__ __forceinline__ void flush_table(const RasterArgs& a, int view, const
       vals[s * L::NV + q] = 0.f;
     }
     keys[s] = kEmpty;
-    if (SH && a.dcol) {
-      const int64_t cb = (int64_t)view * 3 * F;
-      atomicAdd(&a.dcol[cb + f], v[3]);
-      atomicAdd(&a.dcol[cb + F + f], v[4]);
-      atomicAdd(&a.dcol[cb + 2 * F + f], v[5]);
+    if (SH) {
+      // the view's colour gradient of the face, planes [view][channel][F]
+      const int64_t o = (int64_t)view * 3 * a.n_faces + f;
+      gadd<ACC>(a.dcol, o, a.dcol64, o, DT_COL, v[3], a, d);
+      gadd<ACC>(a.dcol, o + a.n_faces, a.dcol64, o + a.n_faces, DT_COL, v[4], a, d);
+      gadd<ACC>(a.dcol, o + 2 * a.n_faces, a.dcol64, o + 2 * a.n_faces, DT_COL, v[5], a, d);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -1141,18 +1169,16 @@ __device__ __forceinline__ void flush_table(const RasterArgs& a, int view, const
         c[2] = v[L::COL + 3 * k + 1];
         c[3] = v[L::COL + 3 * k + 2];
       }
-      // camera -> world: R^T g
-      const float w0 = v[L::POS + 3 * k], w1 = v[L::POS + 3 * k + 1], w2 = v[L::POS + 3 * k + 2];
-      c[L::VW - 3] = Wc[0] * w0 + Wc[4] * w1 + Wc[8] * w2;
-      c[L::VW - 2] = Wc[1] * w0 + Wc[5] * w1 + Wc[9] * w2;
-      c[L::VW - 1] = Wc[2] * w0 + Wc[6] * w1 + Wc[10] * w2;
-      vert_add<SH>(a, vt, id[k], c);
+      c[L::VW - 3] = v[L::POS + 3 * k];
+      c[L::VW - 2] = v[L::POS + 3 * k + 1];
+      c[L::VW - 1] = v[L::POS + 3 * k + 2];
+      vert_add<SH, ACC>(a, vt, id[k], c, d);
     }
   }
   if (lane == 0) *fill = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  if (*vt.fill > (uint32_t)L::VFILL) flush_verts<SH>(a, vt, lane);
+  if (*vt.fill > (uint32_t)L::VFILL) flush_verts<SH, ACC>(a, vt, lane, d);
 }
 
 // One step of a segmented merge across lanes: lane l and its DPP partner
@@ -1189,7 +1215,15 @@ __device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_
   return -1;
 }
 
-template <bool SH>
+// The adjoint's geometry is computed in float64 from the faces' float32 world
+// corners: the pixel ray (camera centre o, direction D = R^-1 d_cam, both from
+// the host in double) is intersected with the face plane by Moller-Trumbore,
+// giving the barycentrics b = (1 - u - v, u, v) and the Jacobian of (u, v)
+// with respect to the corners. A face seen nearly edge-on makes both
+// ill-conditioned (the determinant is proportional to the cosine between the
+// face normal and the ray); the float32 rounding of its corners' projections
+// would then be amplified by 1 / |cos|, double precision keeps it below 1e-12.
+template <bool SH, int ACC>
 __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_items) {
   using L = GradLayout<SH>;
   __shared__ uint32_t hkeys[kWavesPerWG][kHashSlots];
@@ -1204,6 +1238,8 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   float* vals = hvals[wid];
   uint32_t* fill = &hfill[wid];
   const VertTable<SH> vt{vkeys[wid], vvals[wid], &vfill[wid]};
+  DetTrack dt;
+  dt.init();
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
   for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
   for (int s = lane; s < L::VSLOTS; s += MSP_WAVE) vt.keys[s] = kEmpty;
@@ -1220,6 +1256,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   // queue groups: 4x4 regions (64x64 pixels) of one view, whose regions share face records
   const int nsx = (nrx + 3) / 4, nsy = (nry + 3) / 4;
   const int64_t n_groups = (int64_t)nsx * nsy * a.n_views;
+  const int64_t F = a.n_faces;
   uint32_t qi = 0;
   for (;;) {
     // work item: a 2x2 group of 8x8 blocks of one view; the tables persist over the group
@@ -1231,47 +1268,41 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
     const int rx = (gr % nsx) * 4 + (int)(sub16 & 3u), ry = (gr / nsx) * 4 + (int)(sub16 >> 2);
     if (view >= a.n_views || rx >= nrx || ry >= nry) continue;
     const msp_camera c = a.cams[view];
-    // world-to-camera rotation in registers: the flushes' global atomics could
-    // otherwise alias it and force a reload (and a wait) after every atomic
-    float Wc[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) Wc[q] = c.world_to_cam[q];
+    const double* cd = a.camd + (int64_t)view * 12;  // camera centre (3), R^-1 row-major (9)
+    const double Ox = cd[0], Oy = cd[1], Oz = cd[2];
     for (int sub = 0; sub < 4; ++sub) {
     const int bx = 2 * rx + (sub & 1), by = 2 * ry + (sub >> 1);
     if (bx >= nbx || by >= nby) continue;
-    Item it;
-    it.view = view;
-    it.bx0 = bx * 8;
-    it.by0 = by * 8;
-    it.seg = 0;
-    it.blk = ((int64_t)view * nby + by) * nbx + bx;
+    const int64_t blk = ((int64_t)view * nby + by) * nbx + bx;
     int64_t row0, rows;
     if (a.store_rows) {
-      row0 = it.blk * a.store_rows;
+      row0 = blk * a.store_rows;
       rows = a.store_rows;
     } else {
-      row0 = a.blk_off[it.blk];
-      rows = a.blk_off[it.blk + 1] - row0;
+      row0 = a.blk_off[blk];
+      rows = a.blk_off[blk + 1] - row0;
     }
     const uint2* list = a.frag_list + row0 * MSP_WAVE;
-    const int px = it.bx0 + (lane & 7), py = it.by0 + (lane >> 3);
+    const int px = bx * 8 + (lane & 7), py = by * 8 + (lane >> 3);
     const bool valid = px < a.W && py < a.H;
     const int64_t plane = (int64_t)a.H * a.W;
     int nf = 0;
-    float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
+    float gr_ = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
     if (valid) {
-      nf = a.nfrag[(int64_t)it.view * plane + (int64_t)py * a.W + px];
+      nf = a.nfrag[(int64_t)view * plane + (int64_t)py * a.W + px];
       if (nf > rows) nf = (int)rows;
-      const int64_t o = (int64_t)it.view * 4 * plane + (int64_t)py * a.W + px;
-      gr = a.dimg[o];
+      const int64_t o = (int64_t)view * 4 * plane + (int64_t)py * a.W + px;
+      gr_ = a.dimg[o];
       gg = a.dimg[o + plane];
       gb = a.dimg[o + 2 * plane];
       gA = a.dimg[o + 3 * plane];
     }
-    const float rx = (float)it.bx0 + 0.5f, ry = (float)it.by0 + 0.5f;
-    const float dx = (float)(lane & 7), dy = (float)(lane >> 3);
-    const float ifx = 1.f / c.fx, ify = 1.f / c.fy;
-    const float d0 = ((float)px + 0.5f - c.cx) * ifx, d1 = ((float)py + 0.5f - c.cy) * ify;
+    // this pixel's ray in world space: D = R^-1 ((px + 1/2 - cx) / fx, (py + 1/2 - cy) / fy, 1)
+    const double dcx = ((double)px + 0.5 - (double)c.cx) / (double)c.fx;
+    const double dcy = ((double)py + 0.5 - (double)c.cy) / (double)c.fy;
+    const double Dx = cd[3] * dcx + cd[4] * dcy + cd[5];
+    const double Dy = cd[6] * dcx + cd[7] * dcy + cd[8];
+    const double Dz = cd[9] * dcx + cd[10] * dcy + cd[11];
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, P = 1.f;
     int maxn = nf;
     for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d));
@@ -1290,17 +1321,55 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       if (act) {
         f = e.x;
         const float Ti = __uint_as_float(e.y);
-        act = (uint64_t)f < (uint64_t)a.n_faces;
-        float R[kRec];
-        float z, b0, b1, b2;
-        const Fetched q = fetch_face(a, it.view, act ? (int32_t)f : 0);
-        if (act) act = build_record(q, f, rx, ry, R) && pixel_eval(R, dx, dy, z, b0, b1, b2);
+        act = (uint64_t)f < (uint64_t)F;
+        const float4* r = a.attr + (int64_t)(act ? f : 0u) * 4;
+        const float4 A0 = r[0], P0 = r[1], P1 = r[2], P2 = r[3];
+        float4 C0, C1 = make_float4(0.f, 0.f, 0.f, 0.f), C2 = C1;
+        if (SH) {
+          C0 = a.col4[(int64_t)view * F + (act ? f : 0u)];
+        } else {
+          const float4* cp = a.crec + (int64_t)(act ? f : 0u) * 3;
+          C0 = cp[0];
+          C1 = cp[1];
+          C2 = cp[2];
+        }
+        // Moller-Trumbore in double: e1 = p1 - p0, e2 = p2 - p0, s = o - p0,
+        // pv = D x e2, det = e1 . pv, u = s . pv / det, v = D . (s x e1) / det
+        const double e1x = (double)P1.x - P0.x, e1y = (double)P1.y - P0.y, e1z = (double)P1.z - P0.z;
+        const double e2x = (double)P2.x - P0.x, e2y = (double)P2.y - P0.y, e2z = (double)P2.z - P0.z;
+        const double sx = Ox - P0.x, sy = Oy - P0.y, sz = Oz - P0.z;
+        const double pvx = Dy * e2z - Dz * e2y, pvy = Dz * e2x - Dx * e2z, pvz = Dx * e2y - Dy * e2x;
+        const double det = e1x * pvx + e1y * pvy + e1z * pvz;
+        // a zero determinant (the ray in the face's plane) cannot come from a drawn
+        // fragment of a non-degenerate face; such a fragment is left out
+        if (act) act = det != 0.0 && isfinite(det);
         if (act) {
+          // 1 / det: the hardware reciprocal refined by two Newton steps (relative error near 2^-52)
+          double inv = __builtin_amdgcn_rcp(det);
+          inv = fma(inv, fma(-det, inv, 1.0), inv);
+          inv = fma(inv, fma(-det, inv, 1.0), inv);
+          const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+          const double uu = (sx * pvx + sy * pvy + sz * pvz) * inv;
+          const double vv = (Dx * qx + Dy * qy + Dz * qz) * inv;
+          const float b0 = (float)(1.0 - uu - vv), b1 = (float)uu, b2 = (float)vv;
           float raw, al, cr, cg, cb;
-          frag_attr(R, SH, b0, b1, b2, raw, al, cr, cg, cb);
+          {
+#pragma clang fp contract(off)
+            raw = (b0 * A0.x + b1 * A0.y) + b2 * A0.z;
+            al = fminf(fmaxf(raw, 0.f), 1.f);
+            if (SH) {
+              cr = C0.x;
+              cg = C0.y;
+              cb = C0.z;
+            } else {
+              cr = (b0 * C0.x + b1 * C0.w) + b2 * C1.z;
+              cg = (b0 * C0.y + b1 * C1.x) + b2 * C1.w;
+              cb = (b0 * C0.z + b1 * C1.y) + b2 * C2.x;
+            }
+          }
           const float wgt = Ti * al;
-          const float dcr = gr * wgt, dcg = gg * wgt, dcb = gb * wgt;
-          const float dal = Ti * (gr * (cr - Sr) + gg * (cg - Sg) + gb * (cb - Sb)) + gA * Ti * P;
+          const float dcr = gr_ * wgt, dcg = gg * wgt, dcb = gb * wgt;
+          const float dal = Ti * (gr_ * (cr - Sr) + gg * (cg - Sg) + gb * (cb - Sb)) + gA * Ti * P;
           Sr = al * cr + (1.f - al) * Sr;
           Sg = al * cg + (1.f - al) * Sg;
           Sb = al * cb + (1.f - al) * Sb;
@@ -1308,12 +1377,16 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
           const float dalr = (raw > 0.f && raw < 1.f) ? dal : 0.f;
           const float bb[3] = {b0, b1, b2};
           float dLdb[3];
-#pragma unroll
-          for (int qq = 0; qq < 3; ++qq) {
-            dLdb[qq] = R[13 + qq] * dalr;
-            if (!SH) dLdb[qq] += R[17 + 3 * qq] * dcr + R[18 + 3 * qq] * dcg + R[19 + 3 * qq] * dcb;
-            val[qq] = bb[qq] * dalr;
+          dLdb[0] = A0.x * dalr;
+          dLdb[1] = A0.y * dalr;
+          dLdb[2] = A0.z * dalr;
+          if (!SH) {
+            dLdb[0] += C0.x * dcr + C0.y * dcg + C0.z * dcb;
+            dLdb[1] += C0.w * dcr + C1.x * dcg + C1.y * dcb;
+            dLdb[2] += C1.z * dcr + C1.w * dcg + C2.x * dcb;
           }
+#pragma unroll
+          for (int qq = 0; qq < 3; ++qq) val[qq] = bb[qq] * dalr;
           if (SH) {
             val[3] = dcr;
             val[4] = dcg;
@@ -1326,33 +1399,13 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
               val[L::COL + 3 * qq + 2] = bb[qq] * dcb;
             }
           }
-          // camera-space corners, from pixel coordinates and depths
-          const float u[3] = {q.g0.x, q.g0.z, q.g1.x}, v[3] = {q.g0.y, q.g0.w, q.g1.y};
-          const float zz[3] = {q.g1.z, q.g1.w, q.g2.x};
-          float X[3][3];
-#pragma unroll
-          for (int qq = 0; qq < 3; ++qq) {
-            X[qq][0] = (u[qq] - c.cx) * ifx * zz[qq];
-            X[qq][1] = (v[qq] - c.cy) * ify * zz[qq];
-            X[qq][2] = zz[qq];
-          }
-          const float e1[3] = {X[1][0] - X[0][0], X[1][1] - X[0][1], X[1][2] - X[0][2]};
-          const float e2[3] = {X[2][0] - X[0][0], X[2][1] - X[0][1], X[2][2] - X[0][2]};
-          const float n0 = e1[1] * e2[2] - e1[2] * e2[1];
-          const float n1 = e1[2] * e2[0] - e1[0] * e2[2];
-          const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
-          const float det = -(d0 * n0 + d1 * n1 + n2);
-          float w0 = 0.f, w1 = 0.f, w2 = 0.f;
-          if (det != 0.f && isfinite(det)) {
-            const float gu = dLdb[1] - dLdb[0], gv = dLdb[2] - dLdb[0];
-            // (d x e2) and (e1 x d), d = (d0, d1, 1)
-            const float a0 = d1 * e2[2] - e2[1], a1 = e2[0] - d0 * e2[2], a2 = d0 * e2[1] - d1 * e2[0];
-            const float c0 = e1[1] - e1[2] * d1, c1 = e1[2] * d0 - e1[0], c2 = e1[0] * d1 - e1[1] * d0;
-            const float idt = 1.f / det;
-            w0 = (gu * a0 + gv * c0) * idt;
-            w1 = (gu * a1 + gv * c1) * idt;
-            w2 = (gu * a2 + gv * c2) * idt;
-          }
+          // dL/dp_k = -b_k y with y = (g_u (D x e2) + g_v (e1 x D)) / det, the
+          // solution of [-D, e1, e2]^T y = (0, g_u, g_v)
+          const double gu = (double)dLdb[1] - dLdb[0], gv = (double)dLdb[2] - dLdb[0];
+          const double cxx = e1y * Dz - e1z * Dy, cxy = e1z * Dx - e1x * Dz, cxz = e1x * Dy - e1y * Dx;
+          const float w0 = (float)((gu * pvx + gv * cxx) * inv);
+          const float w1 = (float)((gu * pvy + gv * cxy) * inv);
+          const float w2 = (float)((gu * pvz + gv * cxz) * inv);
 #pragma unroll
           for (int qq = 0; qq < 3; ++qq) {
             val[L::POS + 3 * qq] = -bb[qq] * w0;
@@ -1364,7 +1417,7 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       // Accumulate into the wave's table. LDS float atomics cost per lane, so
       // lanes of neighbouring pixels that hold the same face first merge their
       // values through DPP moves (x neighbours, then x+2, then y neighbours).
-      if (*fill > (uint32_t)kHashFill) flush_table<SH>(a, it.view, Wc, keys, vals, fill, vt, lane);
+      if (*fill > (uint32_t)kHashFill) flush_table<SH, ACC>(a, view, keys, vals, fill, vt, lane, dt);
       if (!act) {
 #pragma unroll
         for (int qq = 0; qq < L::NV; ++qq) val[qq] = 0.f;
@@ -1391,8 +1444,8 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
 #pragma unroll
           for (int b = 0; b < kHashBits; ++b) {
             const bool bit = todo && ((slot >> b) & 1);
-            const uint64_t bb = __ballot(bit);
-            same &= bit ? bb : ~bb;
+            const uint64_t bbm = __ballot(bit);
+            same &= bit ? bbm : ~bbm;
           }
           if (todo && (same & lanemask_lt(lane)) == 0) {
 #pragma unroll
@@ -1404,13 +1457,78 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
         }
         pend = pend && !got;
         if (!__any(pend)) break;
-        flush_table<SH>(a, view, Wc, keys, vals, fill, vt, lane);
+        flush_table<SH, ACC>(a, view, keys, vals, fill, vt, lane, dt);
         probes = kHashSlots;
       }
     }
     }  // sub-block
-    flush_table<SH>(a, view, Wc, keys, vals, fill, vt, lane);
-    flush_verts<SH>(a, vt, lane);
+    flush_table<SH, ACC>(a, view, keys, vals, fill, vt, lane, dt);
+    flush_verts<SH, ACC>(a, vt, lane, dt);
+  }
+  if constexpr (ACC == ACC_MAX) det_publish(a, dt, lane);
+}
+
+// Deterministic mode: per class c the scale 2^s with max |value| <= 2^e_M and
+// count <= 2^e_N, s = 62 - e_M - e_N, so every partial sum stays below 2^62 in
+// magnitude. Classes with a non-finite value get scale 0 (their outputs become NaN).
+__global__ void k_det_scales(const uint32_t* det_max, const unsigned long long* det_cnt, double* scale, int c0, int c1) {
+  const int c = c0 + (int)threadIdx.x;
+  if (c >= c1) return;
+  if (det_max[DT_N] & 1u) {
+    scale[c] = 0.0;
+    scale[DT_N + c] = __longlong_as_double(0x7ff8000000000000ll);
+    return;
+  }
+  const float M = __uint_as_float(det_max[c]);
+  const unsigned long long N = det_cnt[c];
+  if (!(M > 0.f) || N == 0) {
+    scale[c] = 1.0;
+    scale[DT_N + c] = 1.0;
+    return;
+  }
+  int eM = 0;
+  (void)frexpf(M, &eM);  // M < 2^eM
+  int eN = 0;
+  while (eN < 63 && (1ull << eN) < N) ++eN;  // N <= 2^eN
+  const int s = 62 - eM - eN;
+  scale[c] = ldexp(1.0, s);
+  scale[DT_N + c] = ldexp(1.0, -s);
+}
+
+__device__ __forceinline__ float det_value(unsigned long long x, double inv) {
+  return (float)((double)(long long)x * inv);
+}
+
+// SH mode: the fixed-point colour gradients -> float [views][3][F] for the SH adjoint
+__global__ __launch_bounds__(256) void k_dcol_finalize(const unsigned long long* __restrict__ dcol64, int64_t n,
+                                                       const double* __restrict__ scale, float* dcol) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dcol[i] = det_value(dcol64[i], scale[DT_N + DT_COL]);
+}
+
+// Deterministic mode: fixed-point vertex sums (planes dpos x, y, z, dop, drgb r, g, b)
+// -> the caller's gradients; the SH adjoint's position terms (their own class and
+// planes) are added last.
+__global__ __launch_bounds__(256) void k_det_finalize(const unsigned long long* __restrict__ acc64,
+                                                      const unsigned long long* __restrict__ accsh64,
+                                                      const double* __restrict__ scale, int64_t V, float* dpos,
+                                                      float* dop, float* drgb) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const double ip = scale[DT_N + DT_POS], io = scale[DT_N + DT_OP], ir = scale[DT_N + DT_RGB];
+  if (dpos) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float x = det_value(acc64[c * V + v], ip);
+      if (accsh64) x += det_value(accsh64[c * V + v], scale[DT_N + DT_SHPOS]);
+      dpos[c * V + v] = x;
+    }
+  }
+  if (dop) dop[v] = det_value(acc64[3 * V + v], io);
+  if (drgb) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) drgb[c * V + v] = det_value(acc64[(4 + c) * V + v], ir);
   }
 }
 
@@ -1508,15 +1626,43 @@ hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu) {
+template <int ACC>
+static void launch_grads_mode(hipStream_t s, const RasterArgs& a, int n_cu, uint32_t n_items) {
+  if (a.col4) {
+    const int g = persistent_grid(k_bwd_grads<true, ACC>, n_cu, n_items);
+    hipLaunchKernelGGL((k_bwd_grads<true, ACC>), dim3(g), dim3(256), 0, s, a, n_items);
+  } else {
+    const int g = persistent_grid(k_bwd_grads<false, ACC>, n_cu, n_items);
+    hipLaunchKernelGGL((k_bwd_grads<false, ACC>), dim3(g), dim3(256), 0, s, a, n_items);
+  }
+}
+
+hipError_t launch_bwd_grads(hipStream_t s, const RasterArgs& a, int n_cu, int mode) {
   const uint32_t nbx = (uint32_t)((a.W + 7) / 8), nby = (uint32_t)((a.H + 7) / 8);
   const uint32_t n_items = ((nbx + 1) / 2) * ((nby + 1) / 2) * (uint32_t)a.n_views;
-  if (a.col4) {
-    const int g = persistent_grid(k_bwd_grads<true>, n_cu, n_items);
-    hipLaunchKernelGGL(k_bwd_grads<true>, dim3(g), dim3(256), 0, s, a, n_items);
-  } else {
-    const int g = persistent_grid(k_bwd_grads<false>, n_cu, n_items);
-    hipLaunchKernelGGL(k_bwd_grads<false>, dim3(g), dim3(256), 0, s, a, n_items);
-  }
+  if (mode == 0) launch_grads_mode<ACC_F32>(s, a, n_cu, n_items);
+  else if (mode == 1) launch_grads_mode<ACC_MAX>(s, a, n_cu, n_items);
+  else launch_grads_mode<ACC_FIX>(s, a, n_cu, n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_scales(hipStream_t s, const uint32_t* det_max, const unsigned long long* det_cnt, double* scale,
+                             int c0, int c1) {
+  hipLaunchKernelGGL(k_det_scales, dim3(1), dim3(64), 0, s, det_max, det_cnt, scale, c0, c1);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcol_finalize(hipStream_t s, const unsigned long long* dcol64, int64_t n, const double* scale,
+                                float* dcol) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dcol_finalize, dim3(grid_for(n, 256)), dim3(256), 0, s, dcol64, n, scale, dcol);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_finalize(hipStream_t s, const unsigned long long* acc64, const unsigned long long* accsh64,
+                               const double* scale, int64_t V, float* dpos, float* dop, float* drgb) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_det_finalize, dim3(grid_for(V, 256)), dim3(256), 0, s, acc64, accsh64, scale, V, dpos, dop,
+                     drgb);
   return hipGetLastError();
 }

@@ -36,13 +36,25 @@ __device__ __forceinline__ void wpow(float x, float y, float re[4], float im[4])
 __device__ __forceinline__ float polyval(const float* p, float z) { return ((p[3] * z + p[2]) * z + p[1]) * z + p[0]; }
 __device__ __forceinline__ float polyder(const float* p, float z) { return (3.f * p[3] * z + 2.f * p[2]) * z + p[1]; }
 
-__device__ __forceinline__ void face_dir(const float* __restrict__ pos, int64_t V, const int32_t* __restrict__ idx,
-                                         int64_t F, int64_t f, const float* eye, float& dx, float& dy, float& dz,
-                                         float& inv_len) {
+// face centroid (read once per face for all views); false for a face with a
+// vertex id out of range, which is never drawn and whose colour is not used
+__device__ __forceinline__ bool face_centroid(const float* __restrict__ pos, int64_t V,
+                                              const int32_t* __restrict__ idx, int64_t F, int64_t f, float& cx,
+                                              float& cy, float& cz) {
   const int32_t i0 = idx[f], i1 = idx[F + f], i2 = idx[2 * F + f];
-  const float cx = (pos[i0] + pos[i1] + pos[i2]) * (1.f / 3.f);
-  const float cy = (pos[V + i0] + pos[V + i1] + pos[V + i2]) * (1.f / 3.f);
-  const float cz = (pos[2 * V + i0] + pos[2 * V + i1] + pos[2 * V + i2]) * (1.f / 3.f);
+  if ((uint64_t)i0 >= (uint64_t)V || (uint64_t)i1 >= (uint64_t)V || (uint64_t)i2 >= (uint64_t)V) {
+    cx = cy = cz = 0.f;
+    return false;
+  }
+  cx = (pos[i0] + pos[i1] + pos[i2]) * (1.f / 3.f);
+  cy = (pos[V + i0] + pos[V + i1] + pos[V + i2]) * (1.f / 3.f);
+  cz = (pos[2 * V + i0] + pos[2 * V + i1] + pos[2 * V + i2]) * (1.f / 3.f);
+  return true;
+}
+
+// unit direction from the eye to the centroid and the inverse distance
+__device__ __forceinline__ void face_dir(float cx, float cy, float cz, const float* eye, float& dx, float& dy,
+                                         float& dz, float& inv_len) {
   const float vx = cx - eye[0], vy = cy - eye[1], vz = cz - eye[2];
   inv_len = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
   dx = vx * inv_len;
@@ -58,9 +70,14 @@ __global__ __launch_bounds__(256) void k_sh_eval(const float* __restrict__ sh, c
   float k[48];
 #pragma unroll
   for (int r = 0; r < 48; ++r) k[r] = sh[r * F + f];
+  float ccx, ccy, ccz;
+  if (!face_centroid(pos, V, idx, F, f, ccx, ccy, ccz)) {
+    for (int v = 0; v < n_views; ++v) col4[(int64_t)v * F + f] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   for (int v = 0; v < n_views; ++v) {
     float x, y, z, il;
-    face_dir(pos, V, idx, F, f, t.eye[v], x, y, z, il);
+    face_dir(ccx, ccy, ccz, t.eye[v], x, y, z, il);
     float re[4], im[4];
     wpow(x, y, re, im);
     float cr = 0.5f, cg = 0.5f, cb = 0.5f;
@@ -80,77 +97,127 @@ __global__ __launch_bounds__(256) void k_sh_eval(const float* __restrict__ sh, c
 __global__ __launch_bounds__(256) void k_sh_bwd(const float* __restrict__ sh, const float* __restrict__ pos,
                                                 int64_t V, const int32_t* __restrict__ idx, int64_t F, int n_views,
                                                 ShArgs t, const float* __restrict__ dcol, float* __restrict__ dsh,
-                                                float* __restrict__ dpos) {
+                                                float* dpos, float4* gvout, uint32_t* det_max,
+                                                unsigned long long* det_cnt) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F) return;
-  float k[48], dk[48];
-#pragma unroll
-  for (int r = 0; r < 48; ++r) {
-    k[r] = sh[r * F + f];
-    dk[r] = 0.f;
-  }
   float gvx = 0.f, gvy = 0.f, gvz = 0.f;  // d L / d (centroid), summed over views
-  for (int v = 0; v < n_views; ++v) {
-    const int64_t o = (int64_t)v * 3 * F + f;
-    const float g0 = dcol[o], g1 = dcol[o + F], g2 = dcol[o + 2 * F];
-    if (g0 == 0.f && g1 == 0.f && g2 == 0.f) continue;
-    float x, y, z, il;
-    face_dir(pos, V, idx, F, f, t.eye[v], x, y, z, il);
-    float re[4], im[4];
-    wpow(x, y, re, im);
-    float Y[16], pre0 = 0.5f, pre1 = 0.5f, pre2 = 0.5f;
+  if (f < F) {
+    float k[48], dk[48];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      const int m = t.m[b];
-      const float q = m == 0 ? 1.f : (m > 0 ? re[m] : im[-m]);
-      Y[b] = polyval(t.poly[b], z) * q;
-      pre0 = fmaf(k[3 * b], Y[b], pre0);
-      pre1 = fmaf(k[3 * b + 1], Y[b], pre1);
-      pre2 = fmaf(k[3 * b + 2], Y[b], pre2);
+    for (int r = 0; r < 48; ++r) {
+      k[r] = sh[r * F + f];
+      dk[r] = 0.f;
     }
-    const float h0 = pre0 > 0.f ? g0 : 0.f, h1 = pre1 > 0.f ? g1 : 0.f, h2 = pre2 > 0.f ? g2 : 0.f;
-    float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+    float ccx, ccy, ccz;
+    const bool drawn = face_centroid(pos, V, idx, F, f, ccx, ccy, ccz);
+    for (int v = 0; v < n_views && drawn; ++v) {
+      const int64_t o = (int64_t)v * 3 * F + f;
+      const float g0 = dcol[o], g1 = dcol[o + F], g2 = dcol[o + 2 * F];
+      if (g0 == 0.f && g1 == 0.f && g2 == 0.f) continue;
+      float x, y, z, il;
+      face_dir(ccx, ccy, ccz, t.eye[v], x, y, z, il);
+      float re[4], im[4];
+      wpow(x, y, re, im);
+      float Y[16], pre0 = 0.5f, pre1 = 0.5f, pre2 = 0.5f;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      dk[3 * b] = fmaf(Y[b], h0, dk[3 * b]);
-      dk[3 * b + 1] = fmaf(Y[b], h1, dk[3 * b + 1]);
-      dk[3 * b + 2] = fmaf(Y[b], h2, dk[3 * b + 2]);
-      const float s = k[3 * b] * h0 + k[3 * b + 1] * h1 + k[3 * b + 2] * h2;
-      const int m = t.m[b];
-      const int am = m < 0 ? -m : m;
-      const float p = polyval(t.poly[b], z), dp = polyder(t.poly[b], z);
-      float yx, yy, yz;
-      if (m == 0) {
-        yx = 0.f; yy = 0.f; yz = dp;
-      } else if (m > 0) {
-        yx = p * am * re[am - 1];
-        yy = -p * am * im[am - 1];
-        yz = dp * re[am];
-      } else {
-        yx = p * am * im[am - 1];
-        yy = p * am * re[am - 1];
-        yz = dp * im[am];
+      for (int b = 0; b < 16; ++b) {
+        const int m = t.m[b];
+        const float q = m == 0 ? 1.f : (m > 0 ? re[m] : im[-m]);
+        Y[b] = polyval(t.poly[b], z) * q;
+        pre0 = fmaf(k[3 * b], Y[b], pre0);
+        pre1 = fmaf(k[3 * b + 1], Y[b], pre1);
+        pre2 = fmaf(k[3 * b + 2], Y[b], pre2);
       }
-      ddx = fmaf(s, yx, ddx);
-      ddy = fmaf(s, yy, ddy);
-      ddz = fmaf(s, yz, ddz);
-    }
-    // through d = v / |v|: (I - d d^T) dd / |v|
-    const float dot = ddx * x + ddy * y + ddz * z;
-    gvx += (ddx - dot * x) * il;
-    gvy += (ddy - dot * y) * il;
-    gvz += (ddz - dot * z) * il;
-  }
+      const float h0 = pre0 > 0.f ? g0 : 0.f, h1 = pre1 > 0.f ? g1 : 0.f, h2 = pre2 > 0.f ? g2 : 0.f;
+      float ddx = 0.f, ddy = 0.f, ddz = 0.f;
 #pragma unroll
-  for (int r = 0; r < 48; ++r) dsh[r * F + f] = dk[r];
-  if (dpos && (gvx != 0.f || gvy != 0.f || gvz != 0.f)) {
+      for (int b = 0; b < 16; ++b) {
+        dk[3 * b] = fmaf(Y[b], h0, dk[3 * b]);
+        dk[3 * b + 1] = fmaf(Y[b], h1, dk[3 * b + 1]);
+        dk[3 * b + 2] = fmaf(Y[b], h2, dk[3 * b + 2]);
+        const float s = k[3 * b] * h0 + k[3 * b + 1] * h1 + k[3 * b + 2] * h2;
+        const int m = t.m[b];
+        const int am = m < 0 ? -m : m;
+        const float p = polyval(t.poly[b], z), dp = polyder(t.poly[b], z);
+        float yx, yy, yz;
+        if (m == 0) {
+          yx = 0.f; yy = 0.f; yz = dp;
+        } else if (m > 0) {
+          yx = p * am * re[am - 1];
+          yy = -p * am * im[am - 1];
+          yz = dp * re[am];
+        } else {
+          yx = p * am * im[am - 1];
+          yy = p * am * re[am - 1];
+          yz = dp * im[am];
+        }
+        ddx = fmaf(s, yx, ddx);
+        ddy = fmaf(s, yy, ddy);
+        ddz = fmaf(s, yz, ddz);
+      }
+      // through d = v / |v|: (I - d d^T) dd / |v|
+      const float dot = ddx * x + ddy * y + ddz * z;
+      gvx += (ddx - dot * x) * il;
+      gvy += (ddy - dot * y) * il;
+      gvz += (ddz - dot * z) * il;
+    }
+    if (dsh) {
+#pragma unroll
+      for (int r = 0; r < 48; ++r) dsh[r * F + f] = dk[r];
+    }
+  }
+  // each corner moves the centroid by a third of its own motion
+  const float tx = gvx * (1.f / 3.f), ty = gvy * (1.f / 3.f), tz = gvz * (1.f / 3.f);
+  if (gvout) {
+    // deterministic mode: per-face terms, their largest magnitude and count (one atomic per wave)
+    if (f < F) gvout[f] = make_float4(tx, ty, tz, 0.f);
+    const bool fin = isfinite(tx) && isfinite(ty) && isfinite(tz);
+    float m = (f < F && fin) ? fmaxf(fmaxf(fabsf(tx), fabsf(ty)), fabsf(tz)) : 0.f;
+    uint32_t n = f < F ? 9u : 0u;
+    for (int o = 32; o >= 1; o >>= 1) {
+      m = fmaxf(m, __shfl_xor(m, o));
+      n += __shfl_xor(n, o);
+    }
+    const bool bad = __any(f < F && !fin);
+    if ((threadIdx.x & 63) == 0) {
+      if (n) {
+        atomicMax(&det_max[DT_SHPOS], __float_as_uint(m));
+        atomicAdd(&det_cnt[DT_SHPOS], (unsigned long long)n);
+      }
+      if (bad) atomicOr(&det_max[DT_N], 1u);
+    }
+    return;
+  }
+  if (f < F && dpos && (gvx != 0.f || gvy != 0.f || gvz != 0.f)) {
     const int32_t id[3] = {idx[f], idx[F + f], idx[2 * F + f]};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      atomicAdd(&dpos[id[q]], gvx * (1.f / 3.f));
-      atomicAdd(&dpos[V + id[q]], gvy * (1.f / 3.f));
-      atomicAdd(&dpos[2 * V + id[q]], gvz * (1.f / 3.f));
+      if ((uint64_t)id[q] >= (uint64_t)V) continue;
+      atomicAdd(&dpos[id[q]], tx);
+      atomicAdd(&dpos[V + id[q]], ty);
+      atomicAdd(&dpos[2 * V + id[q]], tz);
     }
+  }
+}
+
+// deterministic mode: the per-face position terms as fixed-point sums per vertex
+__global__ __launch_bounds__(256) void k_sh_fix(const int32_t* __restrict__ idx, int64_t F, int64_t V,
+                                                const float4* __restrict__ gv, const double* __restrict__ scale,
+                                                unsigned long long* accsh64) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const float4 g = gv[f];
+  if (g.x == 0.f && g.y == 0.f && g.z == 0.f) return;
+  const double sc = scale[DT_SHPOS];
+  const long long x = __double2ll_rn((double)g.x * sc), y = __double2ll_rn((double)g.y * sc),
+                  z = __double2ll_rn((double)g.z * sc);
+  const int32_t id[3] = {idx[f], idx[F + f], idx[2 * F + f]};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if ((uint64_t)id[q] >= (uint64_t)V) continue;
+    atomicAdd(&accsh64[id[q]], (unsigned long long)x);
+    atomicAdd(&accsh64[V + id[q]], (unsigned long long)y);
+    atomicAdd(&accsh64[2 * V + id[q]], (unsigned long long)z);
   }
 }
 
@@ -210,11 +277,19 @@ hipError_t launch_sh_eval(hipStream_t s, const msp_faces* f, const msp_camera* h
 }
 
 hipError_t launch_sh_bwd(hipStream_t s, const msp_faces* f, const msp_camera* h_cams, int n_views, const float* dcol,
-                         float* dsh, float* dpos) {
+                         float* dsh, float* dpos, float4* gv, uint32_t* det_max, unsigned long long* det_cnt) {
   if (f->n_faces == 0) return hipSuccess;
   ShArgs t;
   if (!make_table(h_cams, n_views, t)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sh_bwd, dim3(grid_for(f->n_faces)), dim3(256), 0, s, f->sh, f->pos, f->n_verts, f->idx,
-                     f->n_faces, n_views, t, dcol, dsh, dpos);
+                     f->n_faces, n_views, t, dcol, dsh, dpos, gv, det_max, det_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_sh_fix(hipStream_t s, const msp_faces* f, const float4* gv, const double* scale,
+                         unsigned long long* accsh64) {
+  if (f->n_faces == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sh_fix, dim3(grid_for(f->n_faces)), dim3(256), 0, s, f->idx, f->n_faces, f->n_verts, gv, scale,
+                     accsh64);
   return hipGetLastError();
 }

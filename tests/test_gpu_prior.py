@@ -139,18 +139,13 @@ def test_prior_render_backward_parity(gpu):
     gr = gpu.render_backward(st, fg, torch.from_numpy(dimg).cuda())
     ref = orr.render_backward_pixels(f64, cam, keep, [dimg[0, :, j, i] for i, j in keep])
     _say("prior backward", len(bad), "pixels left out")
-    # A face seen obliquely is ill-conditioned in float32: the adjoint rebuilds
-    # its corners from projected coordinates and depth, so its edges carry a
-    # relative error of about 2^-24 |X| / |e| (about 1e-5 here) that the
-    # determinant amplifies by 1 / |cos| (cos between the face normal and the
-    # view ray), and a vertex whose per-pixel terms cancel shows it against a
-    # small total (uniform opacities and random upstream gradients make such
-    # sums common here). At most 0.5% of the vertices may miss the strict bar;
-    # each must belong to a face with |cos| < 0.2 and is held to 1e-2 relative
-    # with a floor of 1e-4 of the largest gradient.
+    # Faces at the sphere's silhouette are seen nearly edge-on; the adjoint's
+    # ray/triangle geometry is computed in float64 from the world corners, so
+    # every vertex is held to the strict bar (cos between the face normal and
+    # the view ray is printed for any vertex that misses it).
     P, I = f64["pos"], f64["idx"]
     Wm = np.asarray(cam.world_to_cam, np.float64)
-    centre = -Wm[:, :3].T @ Wm[:, 3]
+    centre = -np.linalg.solve(Wm[:, :3], Wm[:, 3])
     p0, p1, p2 = P[:, I[0]], P[:, I[1]], P[:, I[2]]
     nrm = np.cross(p1 - p0, p2 - p0, axis=0)
     view = (p0 + p1 + p2) / 3 - centre[:, None]
@@ -166,12 +161,10 @@ def test_prior_render_backward_parity(gpu):
         _say(k, "vertices outside the strict bar", len(bad_v), "cos", cos_v[bad_v], "floor", floor)
         for v in bad_v[:8]:
             _say("   vertex", v, "gpu", gk[:, v], "oracle", rkv[:, v])
-        assert len(bad_v) <= 0.005 * len(cos_v)
-        assert np.all(cos_v[bad_v] < 0.2), (k, cos_v[bad_v])
-        assert np.all(np.abs(gk[:, bad_v] - rkv[:, bad_v]) <= 1e-2 * np.abs(rkv[:, bad_v]) + 100 * floor), k
+        assert len(bad_v) == 0, k
         assert np.count_nonzero(rkv) > 1000
         scale[k] = float(np.abs(rkv).max())
-    _say("gradient scales", scale)
+    _say("gradient scales", scale, "smallest |cos| of a drawn face", float(cos_f.min()))
 
 
 def test_prior_finetune_lowers_error(gpu):
