@@ -251,6 +251,25 @@ enum { MSP_LOSS_MSE = 0, MSP_LOSS_L1 = 1, MSP_LOSS_L1_DSSIM = 2 };
 msp_status msp_loss(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views, int height,
                     int width, float* loss_out, float* dimg);
 
+/* Size in bytes of the fixed device scratch msp_loss_noalloc uses (one per GPU). */
+#define MSP_LOSS_NOALLOC_MAX_BYTES (48ll << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * msp_loss with the same arguments and results, computed in a fixed device
+ * buffer of MSP_LOSS_NOALLOC_MAX_BYTES per GPU that the library holds from the
+ * first msp_create on that GPU until the process ends, instead of context
+ * scratch. It never allocates or frees memory. The MSE and L1 losses fit at
+ * any size; L1 + (1 - SSIM) needs 64 KiB + 1 KiB + 12 V (5 H W' + 3 H' W' +
+ * 3 H W') bytes with W' = W - 10 and H' = H - 10 (about 132 bytes per pixel of
+ * all views: 4 views of 256 x 256 fit), and larger sizes are rejected with
+ * MSP_EINVAL and a message naming the bytes needed. Every call on a
+ * GPU shares that GPU's buffer, which keeps the last call's contents (each
+ * call writes every byte it reads, so nothing needs clearing): calls that
+ * overlap in time on one GPU (other streams, other contexts) race. */
+msp_status msp_loss_noalloc(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views,
+                            int height, int width, float* loss_out, float* dimg);
+
 /* One parameter group of an Adam step (Kingma & Ba 2015, with bias correction):
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), then p is clamped

@@ -337,19 +337,24 @@ def autotune(faces: dict, cams, base: "RenderOptions", dimg=None) -> "RenderOpti
 MSP_LOSS_MSE, MSP_LOSS_L1, MSP_LOSS_L1_DSSIM = 0, 1, 2
 
 
-def loss(img, tgt, kind=MSP_LOSS_MSE, lam=0.6, want_grad=True):
-    """msp_loss: (loss as a 1-element GPU tensor, dL/dimg [V,4,H,W] or None)."""
+def loss(img, tgt, kind=MSP_LOSS_MSE, lam=0.6, want_grad=True, noalloc=False, out=None, dimg=None):
+    """msp_loss (or msp_loss_noalloc, which uses the library's fixed per-GPU
+    scratch and allocates nothing): (loss as a 1-element GPU tensor, dL/dimg
+    [V,4,H,W] or None). `out` and `dimg` may be given to write into."""
     import torch
     _need(img, torch.float32, "img")
     _need(tgt, torch.float32, "tgt")
     ctx = _ctx(img)
     ctx.bind_stream()
     V, _, H, W = img.shape
-    out = torch.empty((1,), dtype=torch.float32, device=img.device)
-    dimg = torch.empty_like(img) if want_grad else None
-    ctx.check(ctx.lib.msp_loss(ctx.h, kind, float(lam), _dev_ptr(img), _dev_ptr(tgt), V, H, W, _dev_ptr(out),
-                               _dev_ptr(dimg)), "msp_loss")
-    return out, dimg
+    if out is None:
+        out = torch.empty((1,), dtype=torch.float32, device=img.device)
+    if dimg is None and want_grad:
+        dimg = torch.empty_like(img)
+    fn = ctx.lib.msp_loss_noalloc if noalloc else ctx.lib.msp_loss
+    ctx.check(fn(ctx.h, kind, float(lam), _dev_ptr(img), _dev_ptr(tgt), V, H, W, _dev_ptr(out),
+                 _dev_ptr(dimg if want_grad else None)), "msp_loss_noalloc" if noalloc else "msp_loss")
+    return out, (dimg if want_grad else None)
 
 
 def adam_step(groups: list, step: int, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -89,6 +89,8 @@ EXPORTS = {
                                C.c_void_p, C.c_void_p, C.POINTER(FaceGrads), C.POINTER(RenderOpts)]),
     "msp_loss": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
                            C.c_void_p, C.c_void_p]),
+    "msp_loss_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                   C.c_int, C.c_void_p, C.c_void_p]),
     "msp_adam_step": (C.c_int, [C.c_void_p, C.POINTER(AdamGroup), C.c_int, C.c_int, C.c_float, C.c_float,
                                 C.c_float]),
     "msp_prune": (C.c_int, [C.c_void_p, C.POINTER(Faces), C.c_float, C.POINTER(C.c_void_p), C.POINTER(C.c_int),

@@ -3,11 +3,38 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 
+// Device scratch of msp_loss_noalloc: one fixed array per GPU, held until the
+// process ends, so that call never allocates. Host code never passes this
+// symbol to a kernel (on the host it is only a stand-in, not a device
+// address): it uses the address hipGetSymbolAddress returns for the current
+// device, resolved once per device when a context is created there.
+static __device__ __align__(256) unsigned char scratch[MSP_LOSS_NOALLOC_MAX_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `device` (which must be current); nullptr on failure
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
 
 constexpr int kVersion = 10000;
 
@@ -146,6 +173,11 @@ msp_status msp_create(int device, void* hip_stream, msp_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
     c->n_cu = 1;
+  c->noalloc_scratch = scratch_address(device);
+  if (!c->noalloc_scratch) {
+    delete c;
+    return MSP_EHIP;
+  }
   *out = c;
   return MSP_OK;
 }
@@ -281,6 +313,26 @@ msp_status msp_loss(msp_ctx* ctx, int kind, float lambda, const float* img, cons
   if ((rc = msp_ensure(ctx, ctx->loss_scratch, loss_scratch_bytes(n_views, height, width, kind)))) return (msp_status)rc;
   MSP_TIMED(ctx, ST_OTHER, launch_loss(ctx->stream, kind, lambda, img, tgt, n_views, height, width, loss_out, dimg,
                                       ctx->loss_scratch.p));
+  return MSP_OK;
+}
+
+msp_status msp_loss_noalloc(msp_ctx* ctx, int kind, float lambda, const float* img, const float* tgt, int n_views,
+                            int height, int width, float* loss_out, float* dimg) {
+  if (!ctx) return MSP_EINVAL;
+  if (!img || !tgt || !loss_out || n_views < 1 || height < 1 || width < 1 ||
+      (kind != MSP_LOSS_MSE && kind != MSP_LOSS_L1 && kind != MSP_LOSS_L1_DSSIM) || !std::isfinite(lambda))
+    return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_loss_noalloc: bad argument");
+  const size_t need = loss_scratch_bytes(n_views, height, width, kind);
+  if (need > (size_t)MSP_LOSS_NOALLOC_MAX_BYTES)
+    return (msp_status)msp_fail(ctx, MSP_EINVAL,
+                                "msp_loss_noalloc: these sizes need " + std::to_string(need) +
+                                    " bytes of scratch, more than the fixed " +
+                                    std::to_string((long long)MSP_LOSS_NOALLOC_MAX_BYTES) + " (use msp_loss)");
+  if (!ctx->noalloc_scratch) return (msp_status)msp_fail(ctx, MSP_EHIP, "msp_loss_noalloc: no device scratch");
+  DeviceGuard dg(ctx->device);
+  // every scratch byte the kernels read is written earlier in the same call: nothing to clear
+  MSP_TIMED(ctx, ST_OTHER, launch_loss(ctx->stream, kind, lambda, img, tgt, n_views, height, width, loss_out, dimg,
+                                      ctx->noalloc_scratch));
   return MSP_OK;
 }
 

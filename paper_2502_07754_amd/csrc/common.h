@@ -38,6 +38,7 @@ struct msp_ctx {
   DevBuf ord_part, ord_boxes, ord_keys0, ord_keys1, ord_vals1, ord_counts, ord_offs, ord_scan;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  void* noalloc_scratch = nullptr;   // this device's copy of the fixed scratch of msp_loss_noalloc
 };
 
 struct msp_state {
