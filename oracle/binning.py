@@ -96,3 +96,26 @@ def tile_lists(pos, idx, cam, tile_w, tile_h):
         keys.extend(lst)
         offsets[t + 1] = offsets[t] + len(lst)
     return offsets, np.asarray(keys, dtype=np.uint64)
+
+
+def tile_lists_fast(pos, idx, cam, tile_w, tile_h):
+    """tile_lists for large scenes: the same statement with the (face, tile)
+    pairs enumerated by array operations instead of Python loops (pinned equal
+    to tile_lists); the lists are ordered by sorting (tile, key) pairs."""
+    ok, (px0, px1, py0, py1), zmin = face_ranges(pos, idx, cam)
+    ntx = -(-int(cam.width) // tile_w)
+    nty = -(-int(cam.height) // tile_h)
+    f = np.flatnonzero(ok)
+    tx0, tx1 = px0[f] // tile_w, px1[f] // tile_w
+    ty0, ty1 = py0[f] // tile_h, py1[f] // tile_h
+    nx = tx1 - tx0 + 1
+    cnt = nx * (ty1 - ty0 + 1)
+    owner = np.repeat(np.arange(len(f)), cnt)                     # which drawn face each pair belongs to
+    first = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    k = np.arange(int(cnt.sum())) - first[owner]                  # the pair's rank within its face
+    tile = (ty0[owner] + k // nx[owner]) * ntx + (tx0[owner] + k % nx[owner])
+    key = (zmin.view(np.uint32).astype(np.uint64)[f[owner]] << np.uint64(32)) | f[owner].astype(np.uint64)
+    order = np.lexsort((key, tile))
+    counts = np.bincount(tile, minlength=ntx * nty)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return offsets, key[order]

@@ -76,6 +76,17 @@ def forward(p, x, rounding=True):
     return y, (x, h1, h2)
 
 
+def preactivations(p, x, rounding=True):
+    """The two hidden layers before their ReLU, z1 and z2, as forward computes
+    them (h1 = max(z1, 0), h2 = max(z2, 0)). A unit whose z lies within float32
+    rounding of 0 may be on the other side of its ReLU in a float32 evaluation."""
+    r = bf16_round if rounding else (lambda a: np.asarray(a, np.float64))
+    x = np.asarray(x, np.float64)
+    z1 = r(x) @ r(p["W1"]).T + p["b1"]
+    z2 = r(np.maximum(z1, 0.0)) @ r(p["W2"]).T + p["b2"]
+    return z1, z2
+
+
 def backward(p, cache, dy, rounding=True):
     """Gradients of sum(y * dy) w.r.t. W1, b1, W2, b2, W3, b3 and the input x."""
     r = bf16_round if rounding else (lambda a: np.asarray(a, np.float64))

@@ -141,6 +141,21 @@ def early_stop(alpha, t_eps):
     return len(alpha)
 
 
+def stop_ambiguous(alpha, t_eps, rel=1e-5):
+    """Whether the early stop of a pixel may fall on another fragment in float32:
+    some transmittance before a fragment, T_k = prod_{j<k} (1 - a_j), lies within
+    rel * t_eps of t_eps (the float32 running product carries a relative error of
+    a few 1e-7 per fragment, so the test T_k >= t_eps can go either way)."""
+    if t_eps <= 0:
+        return False
+    T = 1.0
+    for a in alpha:
+        if abs(T - t_eps) <= rel * t_eps:
+            return True
+        T *= 1.0 - a
+    return abs(T - t_eps) <= rel * t_eps
+
+
 def _head(frags, n):
     return {k: (None if v is None else v[:n]) for k, v in frags.items()}
 
@@ -317,23 +332,40 @@ def projected_corners(faces, cam):
 
 
 def ambiguous_pixels(faces, cam, pixels, tol=1e-4, edge_px=None, ztol=1e-6, bg=(0.0, 0.0, 0.0),
-                     view_col=None):
+                     view_col=None, candidates=None, t_eps=0.0, geom=None, proj=None):
     """Flags pixels whose value depends on float32 rounding of coverage or order.
 
     A pixel is flagged when (i) some face has a screen-space edge within
     `edge_px` pixels of the pixel centre and toggling that face changes the
     pixel by more than `tol`, or (ii) two of its fragments have depths within
     `ztol` relative and swapping them changes the pixel by more than `tol`.
+    The pixel's value is composited with the early stop t_eps (0: every
+    fragment), so with tol = 0 a pixel is flagged exactly when its fragment set
+    or order before the stop may differ in float32 (what the frozen-fragment
+    gradient depends on). `candidates` optionally limits the faces examined
+    (used only where the caller can prove that no other face comes within
+    edge_px of the pixels). `geom` (face_geometry) and `proj`
+    (projected_corners) may be passed to reuse them across calls.
     """
     c = cam_arrays(cam)
     if edge_px is None:
         edge_px = 16.0 * float(np.spacing(np.float32(max(c["W"], c["H"]))))
-    uv, keep = projected_corners(faces, cam)
-    geom = face_geometry(faces["pos"], faces["idx"], cam)
+    uv_all, keep_all = proj if proj is not None else projected_corners(faces, cam)
+    sub = np.flatnonzero(keep_all) if candidates is None else np.asarray(candidates, np.int64)
+    sub = sub[keep_all[sub]]
+    uv = uv_all[sub]
+    if geom is None:
+        geom = face_geometry(faces["pos"], faces["idx"], cam)
+
+    def value(a, co):
+        m = early_stop(a, t_eps)
+        v, _ = composite(a[:m], co[:m], bg)
+        return v
+
     flags = np.zeros(len(pixels), dtype=bool)
     for n, (i, j) in enumerate(pixels):
         p = np.array([i + 0.5, j + 0.5])
-        near = np.zeros(uv.shape[0], dtype=bool)
+        near = np.zeros(len(sub), dtype=bool)
         for a, b in ((0, 1), (1, 2), (2, 0)):
             A = uv[:, a]
             B = uv[:, b]
@@ -343,12 +375,11 @@ def ambiguous_pixels(faces, cam, pixels, tol=1e-4, edge_px=None, ztol=1e-6, bg=(
             Q = A + tt[:, None] * AB
             dist = np.linalg.norm(p - Q, axis=1)
             near |= dist <= edge_px
-        near &= keep
-        fr = pixel_fragments(faces, cam, i, j, geom)
+        fr = pixel_fragments(faces, cam, i, j, geom, candidates=candidates)
         al, _, co = fragment_attributes(faces, fr, view_col)
-        base, _ = composite(al, co, bg)
+        base = value(al, co)
         bad = False
-        for f in np.flatnonzero(near):
+        for f in sub[near]:
             if f in set(fr["fid"].tolist()):
                 m = fr["fid"] != f
                 fr2 = dict(fid=fr["fid"][m], z=fr["z"][m], b=fr["b"][m])
@@ -364,8 +395,7 @@ def ambiguous_pixels(faces, cam, pixels, tol=1e-4, edge_px=None, ztol=1e-6, bg=(
                 o = np.lexsort((fid, z))
                 fr2 = dict(fid=fid[o], z=z[o], b=b[o])
             a2, _, c2 = fragment_attributes(faces, fr2, view_col)
-            val, _ = composite(a2, c2, bg)
-            if np.max(np.abs(val - base)) > tol:
+            if np.max(np.abs(value(a2, c2) - base)) > tol:
                 bad = True
                 break
         if not bad and len(fr["z"]) > 1:
@@ -374,8 +404,7 @@ def ambiguous_pixels(faces, cam, pixels, tol=1e-4, edge_px=None, ztol=1e-6, bg=(
             for k in close:
                 o = np.arange(len(z))
                 o[k], o[k + 1] = k + 1, k
-                val, _ = composite(al[o], co[o], bg)
-                if np.max(np.abs(val - base)) > tol:
+                if np.max(np.abs(value(al[o], co[o]) - base)) > tol:
                     bad = True
                     break
         flags[n] = bad

@@ -1,7 +1,9 @@
 """Face-level fine-tuning loop (fine-tuning section of the paper).
 
 Each step renders every training view, takes the image loss against the
-targets, runs the recomputing adjoint, and applies Adam with the paper's two
+targets (by default the paper's Eq. loss, 0.6 L1 + 0.4 (1 - SSIM); the
+progress metric `mse()` stays the image MSE), runs the adjoint, and applies
+Adam with the paper's two
 learning rates (colours and opacities at lr_color, positions at
 exp(-3) lr_color; opacities projected to [0, 1]). Every `prune_every` steps
 (one step = one epoch over all views) faces whose vertex opacities are all
@@ -13,7 +15,7 @@ from __future__ import annotations
 import dataclasses
 import math
 
-from . import (MSP_LOSS_MSE, RenderOptions, RenderState, adam_step, loss as msp_loss, prior_backward, prior_init,
+from . import (MSP_LOSS_L1_DSSIM, MSP_LOSS_MSE, RenderOptions, RenderState, adam_step, loss as msp_loss, prior_backward, prior_init,
                prior_vertices, prune as msp_prune, render, render_backward)
 from . import _lib
 
@@ -21,7 +23,7 @@ from . import _lib
 @dataclasses.dataclass
 class FineTuneConfig:
     lr_color: float = 1e-2
-    loss_kind: int = MSP_LOSS_MSE
+    loss_kind: int = MSP_LOSS_L1_DSSIM     # Eq. loss: lam L1 + (1 - lam) (1 - SSIM)
     lam: float = 0.6
     prune_every: int = 10
     prune_thresh: float = math.exp(-4.0)
@@ -109,7 +111,7 @@ class FineTuner:
 class PriorTuneConfig:
     lr_color: float = 1e-2
     lr_logits: float = math.exp(-3.0) * 1e-2   # the paper's position rate, exp(-3) lr_color
-    loss_kind: int = MSP_LOSS_MSE
+    loss_kind: int = MSP_LOSS_L1_DSSIM
     lam: float = 0.6
     beta1: float = 0.9
     beta2: float = 0.999

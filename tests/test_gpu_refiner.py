@@ -66,8 +66,11 @@ def test_forward_rejects_unaligned_input(gpu):
         r.forward(buf[1:1 + 64 * 16].view(64, 16))
 
 
-@pytest.mark.parametrize("N", [50, 2048, 5000])
+@pytest.mark.parametrize("N", [50, 2048, 5000, 250_000])
 def test_backward_parity(gpu, N):
+    """Weight, bias and input gradients against the oracle at matching bfloat16
+    rounding points; N = 250,000 is the training batch of the refiner workload
+    (one epoch of the pair-training scenes)."""
     import torch
     p = om.init_params(28, seed=7 + N, zero_last=False)
     rng = np.random.default_rng(N)
@@ -82,11 +85,24 @@ def test_backward_parity(gpu, N):
     dx = g.pop("x").cpu().numpy()
     assert dx.shape == (N, 16) and np.all(dx[:, 15] == 0)
     g["x"] = dx[:, :15]
-    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "x"):
-        a = g[k] if k == "x" else g[k].cpu().numpy()
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a = g[k].cpu().numpy()
         err = np.abs(a - ref[k]).max()
         print(k, "max err", err, "max |g|", np.abs(ref[k]).max(), flush=True)
         assert err <= 1e-3 * np.abs(ref[k]).max(), k
+    # the input gradient row by row: a row may miss the bar only where a hidden
+    # unit's pre-activation sits within float32 rounding of its ReLU's kink (the
+    # float32 sums may then take the other side, which switches that unit's whole
+    # contribution); at most 0.5% of the rows may be such rows
+    scale = np.abs(ref["x"]).max()
+    row_err = np.abs(g["x"] - ref["x"]).max(axis=1)
+    miss = np.flatnonzero(row_err > 1e-3 * scale)
+    z1, z2 = om.preactivations(p, x.astype(np.float64))
+    near = (np.abs(z1) <= 1e-5 * np.abs(z1).max()).any(axis=1) | (np.abs(z2) <= 1e-5 * np.abs(z2).max()).any(axis=1)
+    print("x max err", row_err.max(), "max |g|", scale, "rows beyond the bar", len(miss),
+          "rows with a unit at its kink", int(near.sum()), flush=True)
+    assert np.all(near[miss]), miss[~near[miss]][:10]
+    assert len(miss) <= 0.005 * N
 
 
 def test_backward_reuses_its_buffers(gpu):

@@ -169,3 +169,63 @@ def test_edge_band_and_interval_ends():
     t1 = np.array([np.inf, np.inf, 1.0 + 1e-6, 0.9])
     fl = ory.near_boundary(one_face(), O, D, t0, t1)
     assert [len(x) for x in fl] == [0, 1, 1, 0]
+
+
+def test_candidate_restriction_changes_nothing_when_it_covers_the_pixel():
+    # a random soup in front of the camera plus the shared-edge pair: restricting
+    # each pixel to the faces whose projected box comes near it leaves its flag as it was
+    from oracle import convert as oc
+    g = scenes.gaussians(200, 9, 0.05, 0.4, flat=True)
+    mean = g.mean + np.array([[0.0], [0.0], [3.0]])
+    r = oc.convert_fan(mean, g.scale, g.quat, g.opacity, g.rgb, 8, 2.0)
+    e = soup(left_right(8.5, 2.0, 3.0), [[0.6] * 3, [0.6] * 3], [[[1, 0, 0]] * 3, [[0, 0, 1]] * 3])
+    nv = r["pos"].shape[1]
+    f = dict(pos=np.concatenate([r["pos"], e["pos"]], 1), opacity=np.concatenate([r["opacity"], e["opacity"]]),
+             rgb=np.concatenate([r["rgb"], e["rgb"]], 1), idx=np.concatenate([r["idx"], e["idx"] + nv], 1))
+    c = cam()
+    px = [(8, 8)] + [(i, j) for j in range(0, 16, 3) for i in range(0, 16, 3)]
+    full = orr.ambiguous_pixels(f, c, px)
+    uv, keep = orr.projected_corners(f, c)
+    lo, hi = uv.min(axis=1), uv.max(axis=1)
+    for n, (i, j) in enumerate(px):
+        cand = np.flatnonzero(keep & (lo[:, 0] <= i + 1.5) & (hi[:, 0] >= i - 0.5) & (lo[:, 1] <= j + 1.5)
+                              & (hi[:, 1] >= j - 0.5))
+        assert orr.ambiguous_pixels(f, c, [(i, j)], candidates=cand)[0] == full[n]
+    assert full[0] and not full.all()
+
+
+def test_stop_ambiguity():
+    # three layers of alpha 0.9: T = 1, 0.1, 0.01, 0.001 before/after them
+    a = [0.9, 0.9, 0.9]
+    assert orr.stop_ambiguous(a, 0.01)            # T before the third layer is exactly t_eps
+    assert orr.stop_ambiguous(a, 0.01 * (1 + 5e-6))
+    assert not orr.stop_ambiguous(a, 0.01 * (1 + 5e-5))
+    assert not orr.stop_ambiguous(a, 0.003)
+    assert orr.stop_ambiguous(a, 0.001)           # the transmittance after the last layer
+    assert not orr.stop_ambiguous(a, 0.0)
+    # the early stop it guards: at t_eps just above 0.01 the third layer is dropped, just below it is kept
+    assert orr.early_stop(a, 0.01 * (1 + 1e-9)) == 2 and orr.early_stop(a, 0.01 * (1 - 1e-9)) == 3
+
+
+def test_with_an_early_stop_only_what_comes_before_it_counts():
+    # an opaque front face (alpha 1) ends every pixel at once; a face sharing an edge
+    # with the pixel centre behind it changes nothing once the composite stops there,
+    # in front of it everything
+    front = big(2.0, [0.2, 0.4, 0.6], 1.0)
+    pair = left_right(8.5, 3.0, 3.5)
+    f = soup([front[0]] + pair, [front[1], [0.6] * 3, [0.6] * 3], [front[2], [[1, 0, 0]] * 3, [[0, 0, 1]] * 3])
+    assert not orr.ambiguous_pixels(f, cam(), [(8, 8)], tol=0.0, t_eps=1e-6)[0]
+    # without the stop the faces behind still change the (untruncated) value by 0: T = 0 after alpha 1
+    assert not orr.ambiguous_pixels(f, cam(), [(8, 8)], tol=0.0)[0]
+    # a translucent front face: the edge behind it now shows
+    front = big(2.0, [0.2, 0.4, 0.6], 0.5)
+    f = soup([front[0]] + pair, [front[1], [0.6] * 3, [0.6] * 3], [front[2], [[1, 0, 0]] * 3, [[0, 0, 1]] * 3])
+    assert orr.ambiguous_pixels(f, cam(), [(8, 8)], tol=0.0, t_eps=1e-6)[0]
+    # the stop reached before the edge (t_eps above the transmittance behind the front face)
+    assert not orr.ambiguous_pixels(f, cam(), [(8, 8)], tol=0.0, t_eps=0.6)[0]
+    # with tol = 0, any tie among composited fragments with different attributes counts
+    t0, o0, c0 = big(2.0, [0.5, 0.5, 0.5], 0.5)
+    t1, o1, c1 = big(2.0, [0.5 + 1e-7, 0.5, 0.5], 0.5)
+    f = soup([t0, t1], [o0, o1], [c0, c1])
+    assert orr.ambiguous_pixels(f, cam(), [(8, 8)], tol=0.0)[0]
+    assert not orr.ambiguous_pixels(f, cam(), [(8, 8)])[0]

@@ -70,3 +70,18 @@ def test_near_cull_and_offscreen():
     ok, _, _ = ob.face_ranges(pos, idx, cam)
     assert not ok[0]          # one corner at z = znear
     assert not ok[1]          # projects far right of the image
+
+
+@pytest.mark.parametrize("n,seed,tile,W,H", [(1000, 5, (8, 8), 48, 40), (3000, 6, (32, 16), 100, 70),
+                                             (500, 7, (16, 16), 33, 65), (0, 8, (16, 16), 32, 32)])
+def test_fast_tile_lists_equal_the_loop_statement(n, seed, tile, W, H):
+    g = scenes.gaussians(max(n, 1), seed, 0.01, 0.3, flat=True)
+    cam = scenes.ring_cameras(3, W, H)[seed % 3]
+    f32 = _faces32(g, 8, 2.0)
+    if n == 0:
+        f32["idx"] = f32["idx"][:, :0]
+    a_off, a_keys = ob.tile_lists(f32["pos"], f32["idx"], cam, *tile)
+    b_off, b_keys = ob.tile_lists_fast(f32["pos"], f32["idx"], cam, *tile)
+    assert np.array_equal(a_off, b_off)
+    assert np.array_equal(a_keys, b_keys)
+    assert n == 0 or len(a_keys) > n

@@ -176,3 +176,19 @@ def test_refined_fan_backward_matches_finite_differences():
             ym[i, j] -= h
             fd = (L(yp) - L(ym)) / (2 * h)
             assert abs(fd - dy[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, dy[i, j])
+
+
+def test_preactivations_are_what_forward_clamps():
+    p = om.init_params(28, seed=5, zero_last=False)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(300, 15))
+    y, (_, h1, h2) = om.forward(p, x)
+    z1, z2 = om.preactivations(p, x)
+    assert np.array_equal(np.maximum(z1, 0.0), h1) and np.array_equal(np.maximum(z2, 0.0), h2)
+    assert (z1 < 0).any() and (z1 > 0).any() and (z2 < 0).any()
+    # a unit placed exactly on its ReLU's kink: z = 0 there
+    q = dict(p)
+    q["b1"] = p["b1"].copy()
+    q["b1"][0] = -z1[0, 0] + q["b1"][0]
+    z1b, _ = om.preactivations(q, x[:1])
+    assert abs(z1b[0, 0]) < 1e-12
