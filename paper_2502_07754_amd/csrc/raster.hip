@@ -530,6 +530,22 @@ __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float
   return true;
 }
 
+// False when one edge function is negative at every pixel centre of the 8x8
+// block (the face covers none of them). The largest value of a linear function
+// over the block is at a corner; the test allows a relative 2^-20 of the
+// terms' magnitudes for the rounding of the per-pixel evaluation, so it never
+// drops a face that covers a pixel.
+__device__ __forceinline__ bool meets_block(const float* R) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float e0 = R[1 + 3 * k], ex = R[2 + 3 * k], ey = R[3 + 3 * k];
+    const float mx = e0 + fmaxf(ex, 0.f) * 7.f + fmaxf(ey, 0.f) * 7.f;
+    const float tol = (fabsf(e0) + 7.f * fabsf(ex) + 7.f * fabsf(ey)) * 0x1p-20f;
+    if (mx < -tol) return false;
+  }
+  return true;
+}
+
 // Edge functions of the pixel at block offset (dx, dy).
 __device__ __forceinline__ void edges(const float* R, float dx, float dy, float& E0, float& E1, float& E2) {
   E0 = fmaf(R[3], dy, fmaf(R[2], dx, R[1]));
@@ -733,6 +749,10 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
   T = 1.f;
   Cr = Cg = Cb = 0.f;
   nf = 0;
+  // SH colours are fetched when a fragment is composited and added one pop later,
+  // so the load overlaps the work up to the next pop instead of stalling this one
+  float pw = 0.f;
+  float4 pc = make_float4(0.f, 0.f, 0.f, 0.f);
   uint64_t lo = 0, drop = ~0ull, last = 0;
   int state = valid ? ACTIVE : DONE;
 
@@ -745,11 +765,11 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
     if (MODE == 0) {
       const float w = T * al0;
       if (SHP) {
-        // per-face colour of this view, fetched when the fragment is composited
-        const float4 c = a.col4[(int64_t)it.view * a.n_faces + f0];
-        Cr = fmaf(w, c.x, Cr);
-        Cg = fmaf(w, c.y, Cg);
-        Cb = fmaf(w, c.z, Cb);
+        Cr = fmaf(pw, pc.x, Cr);
+        Cg = fmaf(pw, pc.y, Cg);
+        Cb = fmaf(pw, pc.z, Cb);
+        pw = w;
+        pc = a.col4[(int64_t)it.view * a.n_faces + f0];
       } else {
         float r, g, b;
         kb.front_col(r, g, b);
@@ -818,7 +838,7 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
           q.c1 = cp[1];
           q.c2 = cp[2];
         }
-        keep = build_record(q, fk, rx, ry, R);
+        keep = build_record(q, fk, rx, ry, R) && meets_block(R);
       }
       const uint64_t m = __ballot(keep);
       const int cnt = __popcll(m);
@@ -875,6 +895,11 @@ __device__ void trace_block(const RasterArgs& a, const Item& it, float* slab, Bu
     } else if (state == RESTART && T < eps) {
       state = DONE;
     }
+  }
+  if (MODE == 0 && SHP) {
+    Cr = fmaf(pw, pc.x, Cr);
+    Cg = fmaf(pw, pc.y, Cg);
+    Cb = fmaf(pw, pc.z, Cb);
   }
 }
 
