@@ -37,8 +37,9 @@
 //              pass 2 walks it back to front with S_i = a_i c_i +
 //              (1 - a_i) S_{i+1} and P_i = (1 - a_i) P_{i+1} (no division by
 //              1 - a), takes d position through the ray/triangle Jacobian,
-//              and sums per-face gradients in a per-wave LDS hash table
-//              before one set of global atomics per (block, face).
+//              and sums per-face gradients in a per-wave LDS hash table; a
+//              flush combines the vertices neighbouring lanes share and adds
+//              each face's and vertex's sums to global memory once.
 #include "common.h"
 
 namespace {
@@ -46,11 +47,10 @@ namespace {
 constexpr float kMargin = 0.00390625f;  // 2^-8 pixel
 constexpr int kRec = 28;                // floats per staged face record
 constexpr int kWavesPerWG = 4;
-constexpr int kHashSlots = 128;         // per-wave gradient table
+constexpr int kHashSlots = 128;         // per-wave gradient table (8 blocks of 16 slots)
 constexpr int kHashBits = 7;            // log2(kHashSlots)
-constexpr int kHashFill = 64;           // flushed once it holds more faces than this (short probe chains)
-constexpr int kHashProbes = 16;
-static_assert(kHashSlots >= 2 * MSP_WAVE, "a flushed table must hold one row's faces after a full table");
+constexpr int kHashFill = 64;           // flushed once it holds more faces than this (free slots stay likely)
+static_assert(kHashSlots == 2 * MSP_WAVE, "a flush takes two slots per lane");
 static_assert((1 << kHashBits) == kHashSlots, "slot bits");
 constexpr uint32_t kEmpty = 0xffffffffu;
 
@@ -1015,14 +1015,18 @@ __global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_item
 template <bool SH>
 struct GradLayout {
   static constexpr int NV = SH ? 15 : 21;
+  static constexpr int NS = SH ? 16 : 24;  // floats per face slot (whole float4s)
   static constexpr int COL = 3;
   static constexpr int POS = SH ? 6 : 12;
   // per-vertex entry: dop | (RGB: drgb[3]) | dpos world[3]
   static constexpr int VW = SH ? 4 : 7;
-  static constexpr int VSLOTS = 256;
-  static constexpr int VBITS = 8;
+  static constexpr int VS = SH ? 4 : 8;   // floats per vertex slot (whole float4s)
+  // vertex table slots (a wave's two tables fit three workgroups per CU in SH
+  // mode, two in RGB mode), flushed above three quarters full
+  static constexpr int VSLOTS = SH ? 224 : 160;
   static constexpr int VFILL = VSLOTS * 3 / 4;
 };
+constexpr int kVertBits = 8;  // slot bits of a vertex table index (VSLOTS <= 256)
 
 // How a wave's sums reach global memory. ACC_F32: float atomics (the order of
 // additions from different waves varies between runs). Deterministic mode runs
@@ -1100,135 +1104,19 @@ __device__ __forceinline__ void vert_global(const RasterArgs& a, int32_t v, cons
   }
 }
 
-// Per-wave vertex table: the face table's flushes pour their three vertices'
-// opacity/colour/position gradients in here, so a vertex that several faces of
-// a region share (the centre of a fan above all) costs one set of global
-// atomics per region instead of one per face and flush.
-template <bool SH>
-struct VertTable {
-  uint32_t* keys;
-  float* vals;
-  uint32_t* fill;
-};
-
-template <bool SH>
-__device__ __forceinline__ int vert_slot(const VertTable<SH>& t, uint32_t v) {
-  using L = GradLayout<SH>;
-  const uint32_t h = (v * 0x9E3779B1u) >> (32 - L::VBITS);
-  for (int p = 0; p < kHashProbes; ++p) {
-    const uint32_t sl = (h + p) & (L::VSLOTS - 1);
-    const uint32_t k = t.keys[sl];
-    if (k == v) return (int)sl;
-    if (k == kEmpty) {
-      const uint32_t prev = atomicCAS(&t.keys[sl], kEmpty, v);
-      if (prev == kEmpty) atomicAdd(t.fill, 1u);
-      if (prev == kEmpty || prev == v) return (int)sl;
-    }
-  }
-  return -1;
-}
-
-// one vertex's contribution c[VW]: into the table, or straight to global memory if no slot
-template <bool SH, int ACC>
-__device__ __forceinline__ void vert_add(const RasterArgs& a, const VertTable<SH>& t, int32_t v, const float* c,
-                                         DetTrack& d) {
-  using L = GradLayout<SH>;
-  const int sl = vert_slot(t, (uint32_t)v);
-  if (sl >= 0) {
-#pragma unroll
-    for (int q = 0; q < L::VW; ++q) atomicAdd(&t.vals[sl * L::VW + q], c[q]);
-    return;
-  }
-  vert_global<SH, ACC>(a, v, c, d);
-}
-
-template <bool SH, int ACC>
-__device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable<SH>& t, int lane, DetTrack& d) {
-  using L = GradLayout<SH>;
-  for (int sl = lane; sl < L::VSLOTS; sl += MSP_WAVE) {
-    const uint32_t v = t.keys[sl];
-    if (v == kEmpty) continue;
-    float c[L::VW];
-#pragma unroll
-    for (int q = 0; q < L::VW; ++q) {
-      c[q] = t.vals[sl * L::VW + q];
-      t.vals[sl * L::VW + q] = 0.f;
-    }
-    t.keys[sl] = kEmpty;
-    vert_global<SH, ACC>(a, (int32_t)v, c, d);
-  }
-  if (lane == 0) *t.fill = 0;
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-}
-
-template <bool SH, int ACC>
-__device__ __forceinline__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float* vals,
-                                            uint32_t* fill, const VertTable<SH>& vt, int lane, DetTrack& d) {
-  using L = GradLayout<SH>;
-  for (int s = lane; s < kHashSlots; s += MSP_WAVE) {
-    const uint32_t f = keys[s];
-    if (f == kEmpty) continue;
-    const float4* r = a.attr + (int64_t)f * 4;
-    const int32_t id[3] = {__float_as_int(r[0].w), __float_as_int(r[1].w), __float_as_int(r[2].w)};
-    float v[L::NV];
-#pragma unroll
-    for (int q = 0; q < L::NV; ++q) {
-      v[q] = vals[s * L::NV + q];
-      vals[s * L::NV + q] = 0.f;
-    }
-    keys[s] = kEmpty;
-    if (SH) {
-      // the view's colour gradient of the face, planes [view][channel][F]
-      const int64_t o = (int64_t)view * 3 * a.n_faces + f;
-      gadd<ACC>(a.dcol, o, a.dcol64, o, DT_COL, v[3], a, d);
-      gadd<ACC>(a.dcol, o + a.n_faces, a.dcol64, o + a.n_faces, DT_COL, v[4], a, d);
-      gadd<ACC>(a.dcol, o + 2 * a.n_faces, a.dcol64, o + 2 * a.n_faces, DT_COL, v[5], a, d);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float c[L::VW];
-      c[0] = v[k];
-      if (!SH) {
-        c[1] = v[L::COL + 3 * k];
-        c[2] = v[L::COL + 3 * k + 1];
-        c[3] = v[L::COL + 3 * k + 2];
-      }
-      c[L::VW - 3] = v[L::POS + 3 * k];
-      c[L::VW - 2] = v[L::POS + 3 * k + 1];
-      c[L::VW - 1] = v[L::POS + 3 * k + 2];
-      vert_add<SH, ACC>(a, vt, id[k], c, d);
-    }
-  }
-  if (lane == 0) *fill = 0;
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  if (*vt.fill > (uint32_t)L::VFILL) flush_verts<SH, ACC>(a, vt, lane, d);
-}
-
-// One step of a segmented merge across lanes: lane l and its DPP partner
-// (l ^ D for the given control) that both still hold values of the same face
-// combine them in the lane with bit D clear; the other lane drops out. Must be
-// executed by the whole wave (DPP reads the partner's registers).
-template <int CTRL, int D, int NV>
-__device__ __forceinline__ void merge_step(uint32_t f, bool& alive, float (&val)[NV], int lane) {
-  const uint32_t fp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, CTRL, 0xf, 0xf, false);
-  const int ap = __builtin_amdgcn_mov_dpp(alive ? 1 : 0, CTRL, 0xf, 0xf, false);
-  const bool same = alive && ap != 0 && fp == f;
-  const bool take = same && (lane & D) == 0;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const float vp = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(val[q]), CTRL, 0xf, 0xf, false));
-    val[q] = take ? val[q] + vp : val[q];
-  }
-  if (same && (lane & D) != 0) alive = false;
-}
+// A wave's face table has kHashSlots slots in blocks of 16; face f may sit only
+// at offset f & 15 of a block (the first free one of its eight blocks, starting
+// at a hash of f >> 4). The faces of a fan have consecutive ids, so those of one
+// fan usually share a block and sit at neighbouring offsets: at a flush their
+// shared vertices are then held by neighbouring lanes.
+constexpr int kSlotBlocks = kHashSlots / 16;
 
 // slot of face f in the wave's table (inserted if absent; the fill count grows), -1 if none
-__device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_t f, int probes) {
-  const uint32_t h = (f * 0x9E3779B1u) >> 25;  // 7 bits = log2(kHashSlots)
-  for (int p = 0; p < probes; ++p) {
-    const uint32_t s = (h + p) & (kHashSlots - 1);
+__device__ __forceinline__ int face_slot(uint32_t* keys, uint32_t* fill, uint32_t f) {
+  const uint32_t b0 = ((f >> 4) * 0x9E3779B1u) >> (32 - 3);  // 3 bits: kSlotBlocks = 8
+  static_assert(kSlotBlocks == 8, "block hash bits");
+  for (int p = 0; p < kSlotBlocks; ++p) {
+    const uint32_t s = (((b0 + p) & (kSlotBlocks - 1)) << 4) | (f & 15u);
     const uint32_t k = keys[s];
     if (k == f) return (int)s;
     if (k == kEmpty) {
@@ -1238,6 +1126,229 @@ __device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_
     }
   }
   return -1;
+}
+
+// Per-wave vertex table: a flush of the face table pours its faces' vertex
+// entries in here, so a vertex that faces flushed at different times share
+// (the centre of a fan above all) costs one set of global atomics per table
+// lifetime instead of one per face.
+template <bool SH>
+struct VertTable {
+  uint32_t* keys;
+  float* vals;
+  uint32_t* fill;
+};
+
+// slot of vertex v (inserted if absent; the fill count grows), -1 if none within the probe limit
+template <bool SH>
+__device__ __forceinline__ int vert_slot(const VertTable<SH>& t, uint32_t v) {
+  using L = GradLayout<SH>;
+  uint32_t s = (uint32_t)(((uint64_t)(v * 0x9E3779B1u) * (uint32_t)L::VSLOTS) >> 32);
+  for (int p = 0; p < 16; ++p) {
+    const uint32_t k = t.keys[s];
+    if (k == v) return (int)s;
+    if (k == kEmpty) {
+      const uint32_t prev = atomicCAS(&t.keys[s], kEmpty, v);
+      if (prev == kEmpty) atomicAdd(t.fill, 1u);
+      if (prev == kEmpty || prev == v) return (int)s;
+    }
+    s = s + 1 == (uint32_t)L::VSLOTS ? 0u : s + 1;
+  }
+  return -1;
+}
+
+// rank of this lane among the lanes of the wave that hold the same slot (got),
+// lower lanes first; -1 without a slot. Whole wave.
+template <int BITS>
+__device__ __forceinline__ int slot_rank(bool got, int slot, int lane) {
+  uint64_t same = __ballot(got);
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = got && ((slot >> b) & 1);
+    const uint64_t bbm = __ballot(bit);
+    same &= bit ? bbm : ~bbm;
+  }
+  return got ? (int)__popcll(same & lanemask_lt(lane)) : -1;
+}
+
+// adds the vertex entries c of the lanes with `want` set to vertex v in the
+// wave's vertex table: lanes that share a slot update it in turn, by rank (plain
+// reads and writes, no LDS float atomics); a lane that finds no slot adds its
+// entry to global memory. Whole wave.
+template <bool SH, int ACC>
+__device__ __forceinline__ void vert_put(const RasterArgs& a, const VertTable<SH>& t, bool want, int32_t v,
+                                         const float* c, int lane, DetTrack& d) {
+  using L = GradLayout<SH>;
+  const int slot = want ? vert_slot(t, (uint32_t)v) : -1;
+  const bool got = slot >= 0;
+  if (want && !got) vert_global<SH, ACC>(a, v, c, d);
+  const int rank = slot_rank<kVertBits>(got, slot, lane);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  for (int r = 0; __any(rank >= r); ++r) {
+    if (rank == r) {
+      float4* p4 = reinterpret_cast<float4*>(t.vals + slot * L::VS);
+#pragma unroll
+      for (int q = 0; q < L::VS / 4; ++q) {
+        float4 x = p4[q];
+        if (4 * q < L::VW) x.x += c[4 * q];
+        if (4 * q + 1 < L::VW) x.y += c[4 * q + 1];
+        if (4 * q + 2 < L::VW) x.z += c[4 * q + 2];
+        if (4 * q + 3 < L::VW) x.w += c[4 * q + 3];
+        p4[q] = x;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+}
+
+// empties the wave's vertex table into the global sums
+template <bool SH, int ACC>
+__device__ __forceinline__ void flush_verts(const RasterArgs& a, const VertTable<SH>& t, int lane, DetTrack& d) {
+  using L = GradLayout<SH>;
+  for (int sl = lane; sl < L::VSLOTS; sl += MSP_WAVE) {
+    const uint32_t v = t.keys[sl];
+    if (v == kEmpty) continue;
+    float c[L::VS];
+    float4* p4 = reinterpret_cast<float4*>(t.vals + sl * L::VS);
+#pragma unroll
+    for (int q = 0; q < L::VS / 4; ++q) {
+      const float4 x = p4[q];
+      c[4 * q] = x.x;
+      c[4 * q + 1] = x.y;
+      c[4 * q + 2] = x.z;
+      c[4 * q + 3] = x.w;
+      p4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    t.keys[sl] = kEmpty;
+    vert_global<SH, ACC>(a, (int32_t)v, c, d);
+  }
+  if (lane == 0) *t.fill = 0;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+// lane i receives lane i - d's value (lanes below d: their own)
+__device__ __forceinline__ float lane_up(float x, int d) { return __shfl_up(x, d); }
+__device__ __forceinline__ int lane_up(int x, int d) { return __shfl_up(x, d); }
+__device__ __forceinline__ int lane_down(int x, int d) { return __shfl_down(x, d); }
+
+// Empties the wave's face table: per face its view's colour gradient (SH) to
+// global memory and three vertex entries to the vertex table. Lane l takes slots
+// l and l + 64.
+// Vertex entries of neighbouring lanes that name the same vertex are combined
+// first: the second corner of lane l - 1 into the first corner of lane l (the
+// boundary vertex two neighbouring fan faces share), and the centres by a
+// segmented scan over runs of equal centre ids; each run adds its centre once.
+// The combination order is fixed, so the sums are the same on every run.
+template <bool SH, int ACC>
+__device__ __forceinline__ void flush_table(const RasterArgs& a, int view, uint32_t* keys, float* vals,
+                                            uint32_t* fill, const VertTable<SH>& vt, int lane, DetTrack& d) {
+  using L = GradLayout<SH>;
+  for (int it = 0; it < kHashSlots / MSP_WAVE; ++it) {
+    const int s = it * MSP_WAVE + lane;
+    const uint32_t f = keys[s];
+    float v[L::NS];
+    float4* v4 = reinterpret_cast<float4*>(vals + s * L::NS);
+#pragma unroll
+    for (int q = 0; q < L::NS / 4; ++q) {
+      const float4 x = v4[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+      v4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    keys[s] = kEmpty;
+    int id[3] = {-1, -1, -1};
+    if (f != kEmpty) {
+      const float4* r = a.attr + (int64_t)f * 4;
+      id[0] = __float_as_int(r[0].w);
+      id[1] = __float_as_int(r[1].w);
+      id[2] = __float_as_int(r[2].w);
+      if (SH) {
+        // the view's colour gradient of the face, planes [view][channel][F]
+        const int64_t o = (int64_t)view * 3 * a.n_faces + f;
+        gadd<ACC>(a.dcol, o, a.dcol64, o, DT_COL, v[3], a, d);
+        gadd<ACC>(a.dcol, o + a.n_faces, a.dcol64, o + a.n_faces, DT_COL, v[4], a, d);
+        gadd<ACC>(a.dcol, o + 2 * a.n_faces, a.dcol64, o + 2 * a.n_faces, DT_COL, v[5], a, d);
+      }
+    }
+    // corner entries: dop | (RGB: drgb[3]) | dpos[3]; an empty slot holds zeros
+    float c[3][L::VW];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c[k][0] = v[k];
+      if (!SH) {
+        c[k][1] = v[L::COL + 3 * k];
+        c[k][2] = v[L::COL + 3 * k + 1];
+        c[k][3] = v[L::COL + 3 * k + 2];
+      }
+      c[k][L::VW - 3] = v[L::POS + 3 * k];
+      c[k][L::VW - 2] = v[L::POS + 3 * k + 1];
+      c[k][L::VW - 1] = v[L::POS + 3 * k + 2];
+    }
+    // Every lane exchange runs with all lanes active: a shuffle inside a
+    // short-circuited condition would execute under a partial exec mask, and
+    // reads from inactive lanes return 0.
+    const int id2p = lane_up(id[2], 1);
+    const int id1n = lane_down(id[1], 1);
+    const int id0p = lane_up(id[0], 1);
+    const int id0n = lane_down(id[0], 1);
+    // boundary: the previous lane's second corner joins this lane's first corner
+    const bool take = lane > 0 && id[1] >= 0 && id2p == id[1];
+    const bool gave = lane < MSP_WAVE - 1 && id[2] >= 0 && id1n == id[2];
+#pragma unroll
+    for (int q = 0; q < L::VW; ++q) {
+      const float x = lane_up(c[2][q], 1);
+      if (take) c[1][q] += x;
+    }
+    // centres: inclusive scan within runs of equal centre ids (head = first lane of a run)
+    int head = (lane == 0 || id0p != id[0]) ? 1 : 0;
+    const bool tail = lane == MSP_WAVE - 1 || id0n != id[0];
+#pragma unroll
+    for (int dd = 1; dd < MSP_WAVE; dd <<= 1) {
+      const int hp = lane_up(head, dd);
+      float xp[L::VW];
+#pragma unroll
+      for (int q = 0; q < L::VW; ++q) xp[q] = lane_up(c[0][q], dd);
+      if (lane >= dd) {
+        if (!head) {
+#pragma unroll
+          for (int q = 0; q < L::VW; ++q) c[0][q] = xp[q] + c[0][q];
+        }
+        head |= hp;
+      }
+    }
+    vert_put<SH, ACC>(a, vt, id[0] >= 0 && tail, id[0], c[0], lane, d);
+    vert_put<SH, ACC>(a, vt, id[1] >= 0, id[1], c[1], lane, d);
+    vert_put<SH, ACC>(a, vt, id[2] >= 0 && !gave, id[2], c[2], lane, d);
+    if (*vt.fill > (uint32_t)L::VFILL) flush_verts<SH, ACC>(a, vt, lane, d);
+  }
+  if (lane == 0) *fill = 0;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+// One step of a segmented merge across lanes: lane l and its DPP partner
+// (l ^ D for the given control) that both still hold values of the same face
+// combine them in the lane with bit D clear; the other lane drops out. Must be
+// executed by the whole wave (DPP reads the partner's registers); the values
+// move only if some pair matches.
+template <int CTRL, int D, int NV>
+__device__ __forceinline__ void merge_step(uint32_t f, bool& alive, float (&val)[NV], int lane) {
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, CTRL, 0xf, 0xf, false);
+  const int ap = __builtin_amdgcn_mov_dpp(alive ? 1 : 0, CTRL, 0xf, 0xf, false);
+  const bool same = alive && ap != 0 && fp == f;
+  if (!__any(same)) return;
+  const bool take = same && (lane & D) == 0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const float vp = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(val[q]), CTRL, 0xf, 0xf, false));
+    val[q] = take ? val[q] + vp : val[q];
+  }
+  if (same && (lane & D) != 0) alive = false;
 }
 
 // The adjoint's geometry is computed in float64 from the faces' float32 world
@@ -1251,11 +1362,12 @@ __device__ __forceinline__ int hash_slot(uint32_t* keys, uint32_t* fill, uint32_
 template <bool SH, int ACC>
 __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_items) {
   using L = GradLayout<SH>;
+  // [slot][value]: one face's values side by side, NS floats apart (16-byte aligned slots)
+  __shared__ __align__(16) float hvals[kWavesPerWG][L::NS * kHashSlots];
+  __shared__ __align__(16) float vvals[kWavesPerWG][L::VS * L::VSLOTS];
   __shared__ uint32_t hkeys[kWavesPerWG][kHashSlots];
-  __shared__ float hvals[kWavesPerWG][L::NV * kHashSlots];  // [slot][value]: one face's values side by side
-  __shared__ uint32_t hfill[kWavesPerWG];
   __shared__ uint32_t vkeys[kWavesPerWG][L::VSLOTS];
-  __shared__ float vvals[kWavesPerWG][L::VW * L::VSLOTS];
+  __shared__ uint32_t hfill[kWavesPerWG];
   __shared__ uint32_t vfill[kWavesPerWG];
   const int lane = lane_id();
   const int wid = threadIdx.x / MSP_WAVE;
@@ -1266,9 +1378,9 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
   DetTrack dt;
   dt.init();
   for (int s = lane; s < kHashSlots; s += MSP_WAVE) keys[s] = kEmpty;
-  for (int s = lane; s < L::NV * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
+  for (int s = lane; s < L::NS * kHashSlots; s += MSP_WAVE) vals[s] = 0.f;
   for (int s = lane; s < L::VSLOTS; s += MSP_WAVE) vt.keys[s] = kEmpty;
-  for (int s = lane; s < L::VW * L::VSLOTS; s += MSP_WAVE) vt.vals[s] = 0.f;
+  for (int s = lane; s < L::VS * L::VSLOTS; s += MSP_WAVE) vt.vals[s] = 0.f;
   if (lane == 0) {
     *fill = 0;
     *vt.fill = 0;
@@ -1439,9 +1551,9 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
           }
         }
       }
-      // Accumulate into the wave's table. LDS float atomics cost per lane, so
-      // lanes of neighbouring pixels that hold the same face first merge their
-      // values through DPP moves (x neighbours, then x+2, then y neighbours).
+      // Accumulate into the wave's table. LDS float atomics run one lane at a
+      // time, so lanes of neighbouring pixels that hold the same face first merge
+      // their values through DPP moves (x neighbours, then x+2, then y neighbours).
       if (*fill > (uint32_t)kHashFill) flush_table<SH, ACC>(a, view, keys, vals, fill, vt, lane, dt);
       if (!act) {
 #pragma unroll
@@ -1451,31 +1563,29 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
       merge_step<0x4E, 2, L::NV>(f, act, val, lane);   // quad_perm [2,3,0,1]: lane ^ 2
       merge_step<0x128, 8, L::NV>(f, act, val, lane);  // row_ror:8: lane ^ 8 within 16 lanes
       // Slots for the remaining lanes, then plain read-add-write instead of LDS
-      // float atomics (which run one lane at a time): in each round the lowest
-      // lane of every group of lanes sharing a slot (found with one ballot per
-      // slot bit) updates it, so a round retires at least one lane per slot.
-      // Lanes that found no slot retry after a flush; the emptied table then
-      // holds at most 64 keys in kHashSlots = 128 slots and a full probe finds one.
+      // float atomics: the lanes that share a slot are ranked once (one ballot
+      // per slot bit; lower lanes first) and update it in rounds, rank r in
+      // round r. Lanes that found no slot retry after a flush, which empties the
+      // table so that every face finds a slot.
       bool pend = act;
-      int probes = kHashProbes;
       for (;;) {
-        const int slot = pend ? hash_slot(keys, fill, f, probes) : -1;
+        const int slot = pend ? face_slot(keys, fill, f) : -1;
         const bool got = pend && slot >= 0;
+        const int rank = slot_rank<kHashBits>(got, slot, lane);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        bool todo = got;
-        while (__any(todo)) {
-          uint64_t same = __ballot(todo);
+        for (int r = 0; __any(rank >= r); ++r) {
+          if (rank == r) {
+            float4* p4 = reinterpret_cast<float4*>(vals + slot * L::NS);
 #pragma unroll
-          for (int b = 0; b < kHashBits; ++b) {
-            const bool bit = todo && ((slot >> b) & 1);
-            const uint64_t bbm = __ballot(bit);
-            same &= bit ? bbm : ~bbm;
-          }
-          if (todo && (same & lanemask_lt(lane)) == 0) {
-#pragma unroll
-            for (int qq = 0; qq < L::NV; ++qq) vals[slot * L::NV + qq] += val[qq];
-            todo = false;
+            for (int q = 0; q < L::NS / 4; ++q) {
+              float4 x = p4[q];
+              if (4 * q < L::NV) x.x += val[4 * q];
+              if (4 * q + 1 < L::NV) x.y += val[4 * q + 1];
+              if (4 * q + 2 < L::NV) x.z += val[4 * q + 2];
+              if (4 * q + 3 < L::NV) x.w += val[4 * q + 3];
+              p4[q] = x;
+            }
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1483,7 +1593,6 @@ __global__ __launch_bounds__(256) void k_bwd_grads(RasterArgs a, uint32_t n_item
         pend = pend && !got;
         if (!__any(pend)) break;
         flush_table<SH, ACC>(a, view, keys, vals, fill, vt, lane, dt);
-        probes = kHashSlots;
       }
     }
     }  // sub-block
