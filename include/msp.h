@@ -436,10 +436,10 @@ msp_status msp_refiner_forward(msp_ctx* ctx, const msp_refiner* r, const float* 
 /* Gradients of sum(y * dy) over the n samples (forward recomputed from x):
  * dW1 [256][15], db1 [256], dW2 [256][256], db2 [256], dW3 [n_out][256],
  * db3 [n_out] (DEVICE, overwritten). dy, dh2 and dh1 are rounded to bfloat16
- * before each product; bias gradients sum the unrounded values. Weight
- * gradients are summed in a fixed order (identical on every run); bias
- * gradients are added per wavefront with float atomics (last-bit differences
- * between runs). dx [n][16] (DEVICE, overwritten; NULL = not computed): the
+ * before each product; bias gradients sum the unrounded values. All
+ * gradients are summed in a fixed order (per-block and per-wavefront partial
+ * sums added in block and wave order, no float atomics), so two identical
+ * calls give identical bits. dx [n][16] (DEVICE, overwritten; NULL = not computed): the
  * gradient with respect to the inputs, dh1 W1 with dh1 and W1 rounded to
  * bfloat16, in the layout of x (column 15 zero). Calls on one refiner share
  * its scratch: do not overlap them. */

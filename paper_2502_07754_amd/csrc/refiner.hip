@@ -80,7 +80,7 @@ struct TrainBufs {
   const float* dy;  // [N][n_out]
   uint16_t *xt, *h1t, *h2t, *dyt, *dh2t, *dh1t;  // feature-major, row length n_pad
   int64_t n_pad;
-  float *db1, *db2, *db3;  // accumulated with atomics (zeroed by the caller)
+  float* bpart;            // [waves][2 HID + 32] per-wave bias-gradient sums (db1 | db2 | db3)
   float* dx;               // [N][16] input gradient (column 15 zero), or null
 };
 
@@ -314,13 +314,23 @@ __global__ __launch_bounds__(64 * WPB) void k_mlp_train(const float* __restrict_
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
   }
-  if (g0 < groups) {
-    for (int i = lane; i < 2 * HID + 32; i += 64) {
-      if (i < HID) atomicAdd(&tb.db1[i], dbw[i]);
-      else if (i < 2 * HID) atomicAdd(&tb.db2[i - HID], dbw[i]);
-      else if (i - 2 * HID < m.n_out) atomicAdd(&tb.db3[i - 2 * HID], dbw[i]);
-    }
-  }
+  // every wave writes its partial sums (zeros if it had no group); k_bias_sum adds
+  // them in wave order, so the bias gradients are the same on every run
+  float* bp = tb.bpart + ((int64_t)blockIdx.x * WPB + wid) * (2 * HID + 32);
+  for (int i = lane; i < 2 * HID + 32; i += 64) bp[i] = dbw[i];
+}
+
+// bias gradients: the per-wave partial sums added in wave order
+__global__ __launch_bounds__(256) void k_bias_sum(const float* __restrict__ bpart, int n_waves, int n_out,
+                                                  float* __restrict__ db1, float* __restrict__ db2,
+                                                  float* __restrict__ db3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * HID + 32) return;
+  float acc = 0.f;
+  for (int w = 0; w < n_waves; ++w) acc += bpart[(int64_t)w * (2 * HID + 32) + i];
+  if (i < HID) db1[i] = acc;
+  else if (i < 2 * HID) db2[i - HID] = acc;
+  else if (i - 2 * HID < n_out) db3[i - 2 * HID] = acc;
 }
 
 // Weight gradients C = A B^T, C[m][n] = sum_s A[m][s] B[n][s] over all samples
@@ -970,9 +980,7 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   tb.dyt = tb.h2t + 256 * np;
   tb.dh2t = tb.dyt + 32 * np;
   tb.dh1t = tb.dh2t + 256 * np;
-  tb.db1 = db1;
-  tb.db2 = db2;
-  tb.db3 = db3;
+  tb.bpart = (float*)r->wpart.p;  // before the weight-gradient kernels reuse the buffer
   tb.dx = dx;
   hipError_t e;
   // k_mlp_train writes every column (its groups end at np, padded
@@ -980,9 +988,11 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
   // zero) of every row except the input feature rows 16..31 of xt, which must
   // read as zero
   if ((e = hipMemsetAsync(tb.xt + 16 * np, 0, 2 * 16 * np, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(db1, 0, 4 * HID, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(db2, 0, 4 * HID, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(db3, 0, 4 * r->n_out, s)) != hipSuccess) return e;
+  if (N == 0) {  // no samples: zero bias gradients
+    if ((e = hipMemsetAsync(db1, 0, 4 * HID, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(db2, 0, 4 * HID, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(db3, 0, 4 * r->n_out, s)) != hipSuccess) return e;
+  }
   float* g1 = (float*)r->grads.p;  // [256][32]
   float* g3 = g1 + HID * 32;       // [32][256]
   if (N == 0) {  // no samples: zero weight gradients
@@ -995,6 +1005,9 @@ hipError_t launch_refiner_backward(hipStream_t s, msp_refiner* r, const float* x
     int64_t gb = (groups + WPB - 1) / WPB;
     gb = gb > (int64_t)n_cu * 8 ? (int64_t)n_cu * 8 : gb;
     hipLaunchKernelGGL(k_mlp_train<kTrainRT>, dim3((unsigned)gb), dim3(64 * WPB), 0, s, x, N, margs(r), tb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bias_sum, dim3(gfor(2 * HID + 32)), dim3(256), 0, s, tb.bpart, (int)(gb * WPB), r->n_out,
+                       db1, db2, db3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // dW3 = dY^T H2 : [32][256];  dW2 = dH2^T H1 : [256][256];  dW1 = dH1^T X : [256][32]
     // each over nbk sample ranges of `span` samples, then the partials summed

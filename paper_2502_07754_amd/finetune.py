@@ -36,9 +36,13 @@ class FineTuner:
     """Adam over per-vertex positions, colours and opacities of a face soup."""
 
     def __init__(self, faces: dict, cams, targets, cfg: FineTuneConfig | None = None,
-                 opts: RenderOptions | None = None):
+                 opts: RenderOptions | None = None, track_mse: bool = False):
         import torch
         self.cfg = cfg or FineTuneConfig()
+        # track_mse: also take the image MSE of every step's render (before its
+        # update) into `last_mse`, whatever the training loss is
+        self.track_mse = track_mse
+        self.last_mse = None
         self.opts = opts or RenderOptions()
         self.cams = cams
         self.targets = targets
@@ -59,6 +63,9 @@ class FineTuner:
         """One epoch: render all views, loss, adjoint, Adam, prune on schedule. Returns the loss tensor."""
         img, st = render(self.faces, self.cams, self.opts, state=self.state)
         L, dimg = msp_loss(img, self.targets, self.cfg.loss_kind, self.cfg.lam)
+        if self.track_mse:
+            self.last_mse = L if self.cfg.loss_kind == MSP_LOSS_MSE else \
+                msp_loss(img, self.targets, MSP_LOSS_MSE, want_grad=False)[0]
         g = render_backward(st, self.faces, dimg, need=("dpos", "dopacity", "drgb"))
         self.t += 1
         lr = self.lr()

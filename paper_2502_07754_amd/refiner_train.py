@@ -135,7 +135,7 @@ def scene_data(seeds, n=12_500, K=8, res=256, perturb=False):
     return out
 
 
-def train_image(data, K=8, sigma=2.0, steps=1000, lr=1e-3, seed=0, log=print):
+def train_image(data, K=8, sigma=2.0, steps=1000, lr=1e-3, seed=0, log=print, deterministic=0):
     """Trains the refiner on the fine-tuning objective itself: each step renders
     the refined fans of one training scene, takes the image MSE against its
     targets, and brings dL/dimage back through msp_render_backward, the adjoint
@@ -150,7 +150,7 @@ def train_image(data, K=8, sigma=2.0, steps=1000, lr=1e-3, seed=0, log=print):
     v = {k: torch.zeros_like(t) for k, t in p.items()}
     R.set_weights(p)
     state = RenderState(_lib.Context.get(torch.cuda.current_device()))
-    opts = RenderOptions()
+    opts = RenderOptions(deterministic=deterministic)
     hist = []
     for t in range(1, steps + 1):
         gg, cams, tgt, x = data[(t - 1) % len(data)]
@@ -193,7 +193,12 @@ def evaluate(R, seeds, n=12_500, K=8, sigma=2.0, res=256, perturb=False):
 def time_to_mse(g: scenes.Gaussians, cams, tgt, K=8, sigma=2.0, steps=1000, R=None, target=None, lr_color=1e-2,
                 prune_every=10, opts=None, log=None):
     """Wall-clock seconds of conversion (+ refiner inference) + fine-tuning until the
-    training MSE reaches `target` (or `steps` steps when target is None)."""
+    image MSE (of the render a step starts from, mean over all views) reaches
+    `target`, or `steps` steps when target is None. The fine-tuning loss is the
+    FineTuner's (the paper's Eq. loss by default); the stopping measure is the
+    MSE. Every step synchronises once (the MSE is read back) in both modes.
+    Also returned: seconds per step, and at every prune the face and vertex
+    counts after it and the fragments the last render composited."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -202,22 +207,34 @@ def time_to_mse(g: scenes.Gaussians, cams, tgt, K=8, sigma=2.0, steps=1000, R=No
         faces = convert(gg, K, sigma)
     else:
         faces = refiner_apply(gg, K, sigma, R.forward(refiner_features(gg, K)))
-    ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=prune_every), opts)
-    curve = []
-    reached = None
-    for i in range(steps):
-        L = ft.step()
-        if target is not None or i == steps - 1 or i % 10 == 0:
-            lv = float(L.item())          # the MSE of the render this step started from
-            curve.append((i, lv))
-            if log is not None and i % 50 == 0:
-                log(f"  step {i}: MSE {lv:.6f} at {time.perf_counter() - t0:.1f} s")
-            if target is not None and lv <= target:
-                reached = i
-                break
+    ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=prune_every), opts,
+                   track_mse=True)
     torch.cuda.synchronize()
-    return dict(seconds=time.perf_counter() - t0, steps=(reached if reached is not None else steps),
-                reached=reached is not None or target is None, final_mse=curve[-1][1], curve=curve[::max(1, len(curve) // 20)])
+    t_start = time.perf_counter() - t0
+    curve, prunes = [], []
+    reached = None
+    n_done = 0
+    for i in range(steps):
+        ft.step()
+        n_done = i + 1
+        lv = float(ft.last_mse.item())  # the MSE of the render this step started from
+        if i % 10 == 0 or i == steps - 1:
+            curve.append((i, lv, time.perf_counter() - t0))
+        if prune_every and (i + 1) % prune_every == 0:
+            st = ft.state.stats()
+            prunes.append(dict(step=i + 1, faces=int(ft.faces["idx"].shape[1]), verts=int(ft.faces["pos"].shape[1]),
+                               fragments=int(st["fragments"]), mse=lv, seconds=time.perf_counter() - t0))
+        if log is not None and i % 50 == 0:
+            log(f"  step {i}: MSE {lv:.6f} at {time.perf_counter() - t0:.1f} s, faces {int(ft.faces['idx'].shape[1])}")
+        if target is not None and lv <= target:
+            reached = i
+            break
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return dict(seconds=secs, setup_seconds=t_start, steps=(reached if reached is not None else steps),
+                steps_run=n_done, seconds_per_step=(secs - t_start) / max(1, n_done),
+                reached=reached is not None or target is None, final_mse=lv,
+                curve=curve, prunes=prunes)
 
 
 def save_params(p: dict, path: str):
@@ -262,6 +279,12 @@ def main():
     ap.add_argument("--ft-target", type=float, default=0.0, help="target MSE of a refined-only run")
     ap.add_argument("--ft-list-rows", type=int, default=0,
                     help="fragment-list rows per pixel the forward stores for the backward (0: recompute)")
+    ap.add_argument("--ft-seed", type=int, default=0, help="scene seed of the time-to-MSE run (targets: seed + 1)")
+    ap.add_argument("--ft-tile", type=int, nargs=2, default=(0, 0), help="tile w h (0 0: autotuned once)")
+    ap.add_argument("--ft-kbuf", type=int, default=0, help="ordering-buffer depth (0: autotuned)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fixed-point gradient sums in the renders of training and fine-tuning (repeatable runs)")
+    ap.add_argument("--skip-eval", action="store_true", help="no held-out evaluation after training")
     args = ap.parse_args()
     import statistics as st
 
@@ -293,12 +316,13 @@ def main():
             del x, ys, w
         t = time.perf_counter()
         data = scene_data(range(1000, 1000 + args.train_seeds), n=args.n, res=args.res)
-        R, p, hist = train_image(data, steps=args.image_steps, lr=args.image_lr, log=log)
+        R, p, hist = train_image(data, steps=args.image_steps, lr=args.image_lr, log=log,
+                                 deterministic=1 if args.deterministic else 0)
         torch.cuda.synchronize()
         res["train_on_objective"] = dict(seconds=time.perf_counter() - t, loss=hist)
         del data
         nets = [("objective", R)] + ([] if args.skip_pairs else [("pairs", Rs)])
-        for key, pert in (("heldout", False), ("heldout_perturbed_targets", True)):
+        for key, pert in (() if args.skip_eval else (("heldout", False), ("heldout_perturbed_targets", True))):
             for name, net in nets:
                 ev = evaluate(net, range(2000, 2005), n=args.n, res=args.res, perturb=pert)
                 gain = [e["plain"] / e["refined"] for e in ev]
@@ -358,34 +382,44 @@ def main():
         log(json.dumps(res["training"]))
         del xt, dy
     if args.ft_n:
-        g = scenes.gaussians(args.ft_n, 0, 0.01, 0.1, flat=True)
+        g = scenes.gaussians(args.ft_n, args.ft_seed, 0.01, 0.1, flat=True)
         cams = scenes.ring_cameras(args.ft_views, args.ft_res[0], args.ft_res[1])
         t = time.perf_counter()
-        tgt = target_images(g, cams, 1, views_per_call=2)
+        tgt = target_images(g, cams, args.ft_seed + 1, views_per_call=2)
         torch.cuda.synchronize()
         log(f"targets: {args.ft_views} views {args.ft_res[0]}x{args.ft_res[1]} in {time.perf_counter() - t:.1f} s")
         # the same render options for both runs: fragment lists recomputed by the backward (the
         # workload's setting; --ft-list-rows > 0 stores them instead), the tile size and
-        # ordering-buffer depth autotuned once on this scene and view set
-        f0 = convert(to_gpu(g), 8, 2.0)
-        d0 = torch.zeros((args.ft_views, 4, args.ft_res[1], args.ft_res[0]), dtype=torch.float32, device="cuda")
-        opts = autotune(f0, cams, RenderOptions(list_rows=args.ft_list_rows), d0)
-        opts = RenderOptions(tile_w=opts.tile_w, tile_h=opts.tile_h, kbuf=opts.kbuf, list_rows=args.ft_list_rows)
-        del f0, d0
+        # ordering-buffer depth given or autotuned once on this scene and view set
+        det = 1 if args.deterministic else 0
+        if args.ft_tile[0] and args.ft_kbuf:
+            opts = RenderOptions(tile_w=args.ft_tile[0], tile_h=args.ft_tile[1], kbuf=args.ft_kbuf,
+                                 list_rows=args.ft_list_rows, deterministic=det)
+        else:
+            f0 = convert(to_gpu(g), 8, 2.0)
+            d0 = torch.zeros((args.ft_views, 4, args.ft_res[1], args.ft_res[0]), dtype=torch.float32, device="cuda")
+            opts = autotune(f0, cams, RenderOptions(list_rows=args.ft_list_rows), d0)
+            opts = RenderOptions(tile_w=opts.tile_w, tile_h=opts.tile_h, kbuf=opts.kbuf, list_rows=args.ft_list_rows,
+                                 deterministic=det)
+            del f0, d0
         log(f"render options: tile {opts.tile_w}x{opts.tile_h}, ordering buffer {opts.kbuf}, "
-            f"stored list rows {opts.list_rows} (0: recomputed)")
-        out = dict(n=args.ft_n, views=args.ft_views, res=list(args.ft_res), steps=args.ft_steps,
-                   tile=[opts.tile_w, opts.tile_h], kbuf=opts.kbuf, list_rows=opts.list_rows)
+            f"stored list rows {opts.list_rows} (0: recomputed), deterministic {det}")
+        out = dict(n=args.ft_n, seed=args.ft_seed, views=args.ft_views, res=list(args.ft_res), steps=args.ft_steps,
+                   tile=[opts.tile_w, opts.tile_h], kbuf=opts.kbuf, list_rows=opts.list_rows, deterministic=det,
+                   loss="0.6 L1 + 0.4 (1 - SSIM)", stop="image MSE of the render a step starts from")
         target = args.ft_target or None
         if args.ft_mode in ("both", "plain"):
             plain = time_to_mse(g, cams, tgt, steps=args.ft_steps, opts=opts, log=log)
-            log(f"plain: {plain['seconds']:.1f} s, final MSE {plain['final_mse']:.6f}")
+            log(f"plain: {plain['seconds']:.1f} s, final MSE {plain['final_mse']:.6f}, "
+                f"{plain['seconds_per_step']:.4f} s/step")
             out["plain"] = plain
             target = plain["final_mse"]
         if args.ft_mode in ("both", "refined"):
             refined = time_to_mse(g, cams, tgt, steps=args.ft_steps, R=R, target=target, opts=opts, log=log)
-            log(f"refined: {refined['seconds']:.1f} s to MSE {target} ({refined['steps']} steps)")
+            log(f"refined: {refined['seconds']:.1f} s to MSE {target} ({refined['steps']} steps, "
+                f"{refined['seconds_per_step']:.4f} s/step)")
             out["refined"] = refined
+            out["target_mse"] = target
         res["time_to_mse"] = out
     print(json.dumps(res))
 
