@@ -89,7 +89,7 @@ enum { MSP_COLOR_RGB = 0, MSP_COLOR_SH3 = 1 };   /* colour source of a render */
 
 typedef struct msp_render_opts {
   int32_t tile_w, tile_h; /* binning tile in pixels; multiples of 8 in [8, 64]; 0 = autotuned/default */
-  int32_t kbuf;           /* depth of the per-pixel ordering buffer: 8 or 16; 0 = default */
+  int32_t kbuf;           /* depth of the per-pixel ordering buffer: 8, 12 or 16; 0 = default */
   int32_t color_mode;     /* MSP_COLOR_RGB or MSP_COLOR_SH3 */
   float t_eps;            /* a pixel stops once its transmittance falls below t_eps (>= 0) */
   float bg[3];            /* background colour */
@@ -508,7 +508,7 @@ msp_status msp_step_graph(msp_ctx* ctx, const msp_faces* f, const msp_camera* ca
 msp_status msp_graph_info(msp_ctx* ctx, msp_state* st, int64_t* captures, int64_t* replays, int64_t* overflows);
 
 /* Times one render (and one backward when dimg is not NULL) for each candidate
- * tile size (8x8, 16x16, 32x16, 32x32) and ordering-buffer depth (8, 16),
+ * tile size (8x8, 16x16, 32x16, 32x32) and ordering-buffer depth (8, 12, 16),
  * keeping the other fields of `base`; writes the fastest options to `out` and
  * makes them the context's defaults for tile_w = tile_h = kbuf = 0. img and
  * grads are scratch outputs sized as for msp_render / msp_render_backward.

@@ -895,7 +895,7 @@ static msp_status render_impl(msp_ctx* ctx, const msp_faces* f, const msp_camera
   int th = opts->tile_h ? opts->tile_h : (ctx->tuned_tile_h ? ctx->tuned_tile_h : 16);
   if (tw < 8 || th < 8 || tw > 64 || th > 64 || tw % 8 || th % 8) return bad("tile sizes must be multiples of 8 in [8, 64]");
   int kb = opts->kbuf ? opts->kbuf : (ctx->tuned_kbuf ? ctx->tuned_kbuf : 16);
-  if (kb != 8 && kb != 16) return bad("kbuf must be 8 or 16");
+  if (kb != 8 && kb != 12 && kb != 16) return bad("kbuf must be 8, 12 or 16");
   if (!(opts->t_eps >= 0.f) || !std::isfinite(opts->t_eps)) return bad("t_eps must be finite and >= 0");
   if (opts->color_mode != MSP_COLOR_RGB && opts->color_mode != MSP_COLOR_SH3) return bad("unknown color_mode");
   if (opts->color_mode == MSP_COLOR_RGB && f->n_faces > 0 && !f->rgb) return bad("RGB mode needs f->rgb");
@@ -1274,7 +1274,8 @@ msp_status msp_autotune(msp_ctx* ctx, const msp_faces* f, const msp_camera* cams
   if (!f || !cams || !base || !img || !out || n_views < 1 || (dimg && !grads))
     return (msp_status)msp_fail(ctx, MSP_EINVAL, "msp_autotune: null argument or n_views < 1");
   DeviceGuard dg(ctx->device);
-  static const int cand[][3] = {{8, 8, 16}, {16, 16, 16}, {32, 16, 16}, {32, 32, 16}, {16, 16, 8}, {32, 16, 8}};
+  static const int cand[][3] = {{8, 8, 16},  {16, 16, 16}, {32, 16, 16}, {32, 32, 16},
+                                {16, 16, 8}, {32, 16, 8},  {16, 16, 12}, {32, 16, 12}};
   msp_state* st = nullptr;
   msp_status r = msp_state_create(ctx, &st);
   if (r != MSP_OK) return r;

@@ -135,7 +135,7 @@ __device__ __forceinline__ TileRect tile_rect(const RasterArgs& a, const float4&
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-// geometry record (3 float4): (u0, v0, u1, v1) (u2, v2, z0, z1) (z2, xr, yr, zbits)
+// geometry record (3 float4): (u0, v0, u1, v1) (u2, v2, 1/z0, 1/z1) (1/z2, xr, yr, zbits)
 // with xr = px0 | px1 << 16, yr = py0 | py1 << 16; a culled face has px0 > px1.
 __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
   const int view = blockIdx.y;
@@ -179,8 +179,10 @@ __global__ __launch_bounds__(256) void k_setup(RasterArgs a) {
           ty1 = py1 / a.tile_h;
           ok = true;
           g0 = make_float4(p0.u, p0.v, p1.u, p1.v);
-          g1 = make_float4(p2.u, p2.v, p0.zc, p1.zc);
-          g2 = make_float4(p2.zc, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
+          // reciprocal depths (the perspective weights of the barycentrics), divided
+          // once per (view, face) here instead of in every block that stages the face
+          g1 = make_float4(p2.u, p2.v, 1.f / p0.zc, 1.f / p1.zc);
+          g2 = make_float4(1.f / p2.zc, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
                            __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)), __uint_as_float(__float_as_uint(zmin)));
         }
       }
@@ -504,7 +506,7 @@ __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float
 #pragma clang fp contract(off)
   const float u[3] = {q.g0.x, q.g0.z, q.g1.x};
   const float v[3] = {q.g0.y, q.g0.w, q.g1.y};
-  const float z[3] = {q.g1.z, q.g1.w, q.g2.x};
+  const float iz[3] = {q.g1.z, q.g1.w, q.g2.x};  // 1 / z of the corners
   const float area2 = (u[1] - u[0]) * (v[2] - v[0]) - (v[1] - v[0]) * (u[2] - u[0]);
   if (!(area2 != 0.f) || !isfinite(area2)) return false;
   const float sg = area2 > 0.f ? 1.f : -1.f;
@@ -516,7 +518,7 @@ __device__ __forceinline__ bool build_record(const Fetched& q, uint32_t f, float
     R[1 + 3 * k] = sg * (du * (ry - v[ia]) - dv * (rx - u[ia]));
     R[2 + 3 * k] = -sg * dv;
     R[3 + 3 * k] = sg * du;
-    R[10 + k] = 1.f / z[k];
+    R[10 + k] = iz[k];
   }
   R[13] = q.a0.x;
   R[14] = q.a0.y;
@@ -1088,7 +1090,8 @@ __device__ __forceinline__ void det_publish(const RasterArgs& a, DetTrack& d, in
 
 // one vertex's values c[VW] into the global sums. Each value class is a plane of
 // its own (dpos x, y, z, dop, drgb r, g, b), so the atomics of one flush go to
-// separate cache lines and L2 channels instead of queueing on one line.
+// separate cache lines instead of queueing on one line (putting a vertex's
+// values side by side was measured slower).
 template <bool SH, int ACC>
 __device__ __forceinline__ void vert_global(const RasterArgs& a, int32_t v, const float* c, DetTrack& d) {
   using L = GradLayout<SH>;
@@ -1735,6 +1738,9 @@ hipError_t launch_composite(hipStream_t s, const RasterArgs& a, int kbuf, int n_
   if (kbuf == 8) {
     if (sh) launch_comp<8, true>(s, a, n_cu, n_items);
     else launch_comp<8, false>(s, a, n_cu, n_items);
+  } else if (kbuf == 12) {
+    if (sh) launch_comp<12, true>(s, a, n_cu, n_items);
+    else launch_comp<12, false>(s, a, n_cu, n_items);
   } else {
     if (sh) launch_comp<16, true>(s, a, n_cu, n_items);
     else launch_comp<16, false>(s, a, n_cu, n_items);
@@ -1753,6 +1759,9 @@ hipError_t launch_bwd_lists(hipStream_t s, const RasterArgs& a, int kbuf, int n_
   if (kbuf == 8) {
     const int g = persistent_grid(k_bwd_lists<8>, n_cu, n_items);
     hipLaunchKernelGGL(k_bwd_lists<8>, dim3(g), dim3(256), 0, s, a, n_items);
+  } else if (kbuf == 12) {
+    const int g = persistent_grid(k_bwd_lists<12>, n_cu, n_items);
+    hipLaunchKernelGGL(k_bwd_lists<12>, dim3(g), dim3(256), 0, s, a, n_items);
   } else {
     const int g = persistent_grid(k_bwd_lists<16>, n_cu, n_items);
     hipLaunchKernelGGL(k_bwd_lists<16>, dim3(g), dim3(256), 0, s, a, n_items);

@@ -64,7 +64,7 @@ def target_images(g: scenes.Gaussians, cams, seed: int, ring_k=16, rings=3, pert
 
 
 def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-2, log=print, ref_len=0.1,
-               perturb=False):
+               perturb=False, deterministic=0):
     """(features, targets, loss weights) of every Gaussian of the seeded scenes."""
     import torch
     xs, ys, ws = [], [], []
@@ -74,7 +74,8 @@ def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-
         tgt = target_images(g, cams, s + 1, perturb=perturb)
         gg = to_gpu(g)
         faces = convert(gg, K, sigma)
-        ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=0))
+        ft = FineTuner(faces, cams, tgt, FineTuneConfig(lr_color=lr_color, prune_every=0),
+                       RenderOptions(deterministic=deterministic))
         l0 = None
         for i in range(steps):
             L = ft.step()
@@ -83,7 +84,7 @@ def make_pairs(seeds, n=12_500, K=8, sigma=2.0, steps=500, res=256, lr_color=1e-
         xs.append(refiner_features(gg, K))
         ys.append(refiner_targets(gg, K, sigma, ft.faces))
         ws.append(refiner_weights(gg, K, sigma, ref_len))
-        log(f"pairs: scene {s}: fine-tune MSE {l0:.5f} -> {float(L.item()):.5f}")
+        log(f"pairs: scene {s}: fine-tune loss {l0:.5f} -> {float(L.item()):.5f}")
     return torch.cat(xs), torch.cat(ys), torch.cat(ws)
 
 
@@ -307,7 +308,7 @@ def main():
         if not args.skip_pairs:
             t = time.perf_counter()
             x, ys, w = make_pairs(range(1000, 1000 + args.train_seeds), n=args.n, steps=args.pair_steps, res=args.res,
-                                  log=log)
+                                  log=log, deterministic=1 if args.deterministic else 0)
             res["pairs"] = dict(samples=int(x.shape[0]), faces=int(x.shape[0]) * 8, seconds=time.perf_counter() - t)
             t = time.perf_counter()
             Rs, _, hist = train(x, ys, None if args.unweighted else w, steps=args.train_steps, lr=args.lr, log=log)

@@ -202,3 +202,22 @@ def test_finetune_step_matches_oracle_chain(gpu):
     for k, rk in (("dpos", "dpos"), ("dopacity", "dop"), ("drgb", "drgb")):
         ok, ex = grad_close(gr[k].cpu().numpy(), ref[rk])
         assert ok, (k, ex)
+
+
+def test_finetune_tracks_mse_of_each_step(gpu):
+    """FineTuner(track_mse=True) records, at every step, the image MSE of the
+    render that step starts from (the training loss stays the paper's loss):
+    it equals msp_loss's MSE of the same faces rendered before the step."""
+    from paper_2502_07754_amd.finetune import FineTuneConfig, FineTuner
+    g = scenes.gaussians(400, 32, 0.02, 0.12, flat=True)
+    cams = scenes.ring_cameras(3, 48, 40)
+    tf = gpu.convert_rings(gaussians_gpu(scenes.perturbed(g, 33)), 16, 3, 3.0)
+    timg, _ = gpu.render(tf, cams, gpu.RenderOptions())
+    targets = timg[:, :3].contiguous()
+    faces = gpu.convert(gaussians_gpu(g), 8, 2.0)
+    ftn = FineTuner(faces, cams, targets, FineTuneConfig(prune_every=0), gpu.RenderOptions(), track_mse=True)
+    for _ in range(3):
+        before = ftn.mse()
+        L = ftn.step()
+        assert float(ftn.last_mse.item()) == before
+        assert float(L.item()) != before  # the step's loss is the L1 + (1 - SSIM) mix, not the MSE

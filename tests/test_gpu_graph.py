@@ -73,7 +73,7 @@ def test_autotune_choice_renders_identically(gpu):
     base = gpu.RenderOptions()
     dimg = torch.from_numpy(scenes.upstream_grad(2, 96, 128, seed=2)).cuda()
     best = gpu.autotune(f, cams, base, dimg)
-    assert (best.tile_w, best.tile_h) in [(8, 8), (16, 16), (32, 16), (32, 32)] and best.kbuf in (8, 16)
+    assert (best.tile_w, best.tile_h) in [(8, 8), (16, 16), (32, 16), (32, 32)] and best.kbuf in (8, 12, 16)
     a, _ = gpu.render(f, cams, best)
     b, _ = gpu.render(f, cams, gpu.RenderOptions(tile_w=8, tile_h=8, kbuf=8))
     c, _ = gpu.render(f, cams, gpu.RenderOptions())  # context default is now the tuned choice

@@ -175,7 +175,7 @@ def _check_image(gpu_img, f, cam, pixels, bg=(0.0, 0.0, 0.0), view_col=None, pro
     return unexplained, int(flagged.sum()), covered, float(err.max()) if len(err) else 0.0
 
 
-@pytest.mark.parametrize("tile,kbuf", [((16, 16), 16), ((8, 8), 8), ((32, 16), 16)])
+@pytest.mark.parametrize("tile,kbuf", [((16, 16), 16), ((8, 8), 8), ((32, 16), 16), ((32, 16), 12)])
 def test_image_config1_all_pixels(gpu, tile, kbuf):
     g, cams, p = scenes.config1()
     f = _oracle_faces(g, p["K"], p["sigma"])
