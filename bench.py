@@ -41,10 +41,10 @@ FP32_VECTOR_UNPACKED_TFLOPS = 78.6        # what this build can reach: it never 
 # They describe the kernel sources they were measured on: with any other
 # source (hash below) or configuration the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "bd9af8df1e48891c4b17603c72e10ca3e9e9e0cbf6280286a589108f30e791ff",
+    "sources_sha256": "5f608e2c82e9f14c41980bb9cf6b4b6601f845ddf8bd70b69c8e0affc8c57362",
     "tile": [32, 16], "kbuf": 16,
-    "composite": (17365484573, 8530735360),
-    "bwd_grads": (18585274369, 9183313152),
+    "composite": (17977091456, 9171863360),
+    "bwd_grads": (9149229824, 9270458464),
 }
 
 
