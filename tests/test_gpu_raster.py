@@ -470,8 +470,10 @@ def test_sh_backward_multiview(gpu):
 
 @pytest.mark.parametrize("sh", [False, True])
 def test_stored_lists_backward_matches_recompute(gpu, sh):
-    """Lists stored by the forward give the same gradients as recomputed ones; a
-    row budget too small for the scene falls back to recomputation."""
+    """Lists stored by the forward give the same gradients as recomputed ones,
+    also with row budgets that are not a multiple of the 8-row groups the lists
+    are laid out in (the scene's longest list exactly, and 5 rows more); a row
+    budget too small for the scene falls back to recomputation."""
     import torch
     f = to_gpu(_sh_scene(n=500, K=8, seed=40) if sh else _oracle_faces(scenes.gaussians(500, 40, 0.02, 0.15, True), 8, 2.0))
     cams = scenes.ring_cameras(2, 80, 64)
@@ -480,11 +482,15 @@ def test_stored_lists_backward_matches_recompute(gpu, sh):
     base = gpu.RenderOptions(color_mode=cm)
     i0, s0 = gpu.render(f, cams, base)
     g0 = gpu.render_backward(s0, f, dimg)
-    for rows in (64, 1):
+    mx = int(s0.nfrag().max())
+    assert mx > 8
+    for rows in (64, mx, mx + 5, 1):
         o = gpu.RenderOptions(color_mode=cm, list_rows=rows)
         i1, s1 = gpu.render(f, cams, o)
         g1 = gpu.render_backward(s1, f, dimg)
         torch.cuda.synchronize()
+        if rows >= mx:
+            assert s1.status() == 0, rows     # the stored lists were used
         assert torch.equal(i0, i1)
         for k in g0:
             assert torch.allclose(g0[k], g1[k], rtol=1e-4, atol=1e-6 * float(g0[k].abs().max())), (rows, k)
