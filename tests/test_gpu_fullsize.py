@@ -243,3 +243,125 @@ def test_crops_of_every_view_and_their_gradients(c3):
         assert ok, (k, ex)
         assert np.count_nonzero(ref[rk]) > 1000, k
     assert step.info()["overflows"] == 0
+
+
+# ---------------------------------------------------------------------------
+# The fine-tuning workload at full size: 3M flat Gaussians, K = 8 (24M faces),
+# sixteen 1920x1080 views, RGB composite, with the render options of the
+# time-to-MSE runs (tile 32x16, ordering buffer 16, fragment lists recomputed by
+# the backward, deterministic gradient sums).
+# ---------------------------------------------------------------------------
+
+C5_VIEWS = (0, 9)   # the views whose crops the oracle checks (about 70 s of oracle time each)
+
+
+@pytest.fixture(scope="module")
+def c5(gpu):
+    """Faces from the oracle's conversion (float32), in the Gaussians' own order
+    as the fine-tuning runs convert them; one eager render of all sixteen views."""
+    import torch
+    g, cams, p = scenes.config5()
+    _say("c5: convert (oracle)")
+    f = faces_f32(oc.convert_fan(g.mean, g.scale, g.quat, g.opacity, g.rgb, p["K"], p["sigma"]))
+    del g
+    faces = to_gpu({k: v for k, v in f.items() if k in ("pos", "opacity", "rgb", "idx", "gid")})
+    opts = gpu.RenderOptions(tile_w=TILE[0], tile_h=TILE[1], kbuf=16, t_eps=T_EPS, color_mode=gpu.MSP_COLOR_RGB,
+                             list_rows=0, deterministic=1)
+    img, st = gpu.render(faces, cams, opts)
+    torch.cuda.synchronize()
+    _say("c5: rendered", st.stats())
+    return dict(state=st, img=img.cpu().numpy(), cams=cams, f32=f, faces=faces, V=len(cams), H=cams[0].height,
+                W=cams[0].width)
+
+
+def test_c5_tile_lists_bit_exact_full_view(c5):
+    """View 0's tile lists of the 24M-face soup against the float32 binning statement."""
+    f, cam = c5["f32"], c5["cams"][0]
+    off, keys = c5["state"].tiles(0)
+    r_off, r_keys = ob.tile_lists_fast(f["pos"], f["idx"], cam, *TILE)
+    _say("c5: tile entries", len(keys), "longest list", int(np.diff(r_off).max()))
+    assert np.array_equal(off, r_off)
+    assert np.array_equal(keys, r_keys)
+
+
+def _backward_chunk_rgb(args):
+    px, gs = args
+    vid, dpos, dop, drgb = [], [], [], []
+    for (i, j), g in zip(px, gs):
+        r = orr.pixel_backward(_W["f64"], _W["cam"], i, j, g, _pixel_frags(i, j), geom=_W["geom"], t_eps=T_EPS)
+        vid.append(r["vid"])
+        dpos.append(r["dpos"])
+        dop.append(r["dop"])
+        drgb.append(r["drgb"])
+    cat = lambda x, s: np.concatenate(x) if x else np.zeros(s)
+    return cat(vid, (0,)).astype(np.int64), cat(dpos, (0, 3)), cat(dop, (0,)), cat(drgb, (0, 3))
+
+
+def test_c5_crops_and_their_gradients(gpu, c5):
+    """A 32x32 crop of two of the sixteen views: RGBA at the image bar (misses
+    only on pixels the oracle flags as ambiguous), then the deterministic
+    backward of an upstream gradient non-zero on the crops' unflagged pixels
+    against the oracle's per-pixel adjoint: positions, opacities and colours
+    of every vertex, at the gradient bar."""
+    import torch
+    f32, cams, V, H, W = c5["f32"], c5["cams"], c5["V"], c5["H"], c5["W"]
+    f64 = {k: v.astype(np.float64) if v.dtype == np.float32 else v for k, v in f32.items()}
+    Vn = f64["pos"].shape[1]
+    rng = np.random.default_rng(17)
+    full = scenes.upstream_grad(V, H, W, 5, 1e-3)
+    dimg = np.zeros_like(full)
+    ref = dict(dpos=np.zeros((3, Vn)), dop=np.zeros(Vn), drgb=np.zeros((3, Vn)))
+    procs = max(1, min(16, len(__import__("os").sched_getaffinity(0))))
+    covered = flagged = checked = stopped = 0
+    ctx = mp.get_context("fork")
+    for v in C5_VIEWS:
+        cam = cams[v]
+        x0 = int(rng.integers(W // 4, 3 * W // 4 - CROP))
+        y0 = int(rng.integers(H // 4, 3 * H // 4 - CROP))
+        cand, ntx = _tile_candidates(f32, cam, x0, y0)
+        _W.update(f64=f64, cam=cam, geom=orr.face_geometry(f64["pos"], f64["idx"], cam), cand=cand, ntx=ntx, col=None,
+                  proj=orr.projected_corners(f64, cam))
+        px = [(x0 + a, y0 + b) for b in range(CROP) for a in range(CROP)]
+        with ctx.Pool(procs) as pool:
+            want = np.concatenate(pool.map(_forward_chunk, _chunks(px, 32)))
+        amb = (want[:, 4] > 0) | (want[:, 5] > 0)
+        want = want[:, :4]
+        got = np.stack([c5["img"][v][:, j, i] for i, j in px]).astype(np.float64)
+        err = np.max(np.abs(got - want), axis=1)
+        cov = want[:, 3] > 0
+        covered += int(cov.sum())
+        bad = np.flatnonzero(err > IMG_TOL)
+        keep = np.ones(len(px), dtype=bool)
+        for b in bad:
+            i, j = px[b]
+            t = (j // TILE[1]) * ntx + i // TILE[0]
+            assert orr.ambiguous_pixels(f64, cam, [(i, j)], candidates=cand[t], geom=_W["geom"],
+                                        proj=_W["proj"])[0], (v, i, j, err[b])
+            keep[b] = False
+        flagged += len(bad)
+        checked += int(keep.sum())
+        n_amb = int((keep & amb).sum())
+        stopped += n_amb
+        keep &= ~amb
+        kp = [q for q, k in zip(px, keep) if k]
+        for i, j in kp:
+            dimg[v, :, j, i] = full[v, :, j, i]
+        with ctx.Pool(procs) as pool:
+            parts = pool.map(_backward_chunk_rgb, [(c, [dimg[v, :, j, i] for i, j in c]) for c in _chunks(kp, 32)])
+        for vid, dp, do, dc in parts:
+            np.add.at(ref["dpos"].T, vid, dp)
+            np.add.at(ref["dop"], vid, do)
+            np.add.at(ref["drgb"].T, vid, dc)
+        _say(f"c5: view {v} crop ({x0}, {y0}) covered {int(cov.sum())} flagged {len(bad)} "
+             f"left out of the gradient check {n_amb} worst {float(err[keep].max()) if keep.any() else 0.0:.2e}")
+    n_px = len(C5_VIEWS) * CROP * CROP
+    assert covered > 0.5 * n_px and checked > 0.9 * n_px
+    assert flagged <= 0.02 * covered and stopped <= 0.15 * covered
+    grads = gpu.render_backward(c5["state"], c5["faces"], torch.from_numpy(dimg).cuda(),
+                                need=("dpos", "dopacity", "drgb"))
+    for k, rk in (("dpos", "dpos"), ("dopacity", "dop"), ("drgb", "drgb")):
+        got = grads[k].cpu().numpy().astype(np.float64)
+        ok, ex = grad_close(got, ref[rk])
+        assert ok, (k, ex)
+        assert np.count_nonzero(ref[rk]) > 1000, k
+    assert c5["state"].status() == 0
