@@ -364,13 +364,14 @@ __device__ __forceinline__ void merge_lds(const uint64_t* s, int oa, int na, int
   }
 }
 
-// sorts p[0, m) in place, m <= kSortChunk (all threads of the workgroup call it)
-__device__ void sort_chunk(uint64_t* p, int m, uint64_t* s) {
+// out[0, m) = in[0, m) sorted, m <= kSortChunk; in and out may be the same (all
+// threads of the workgroup call it)
+__device__ void sort_chunk(const uint64_t* in, uint64_t* out, int m, uint64_t* s) {
   const int t = threadIdx.x;
   int P = 1;  // threads in use: a power of two with P * kSortItems >= m
   while (P * kSortItems < m) P <<= 1;
   const int n = P * kSortItems;
-  for (int j = t; j < n; j += kSortThreads) s[spad(j)] = j < m ? p[j] : kSentinel;
+  for (int j = t; j < n; j += kSortThreads) s[spad(j)] = j < m ? in[j] : kSentinel;
   __syncthreads();
   uint64_t x[kSortItems];
   if (t < P) {
@@ -397,7 +398,7 @@ __device__ void sort_chunk(uint64_t* p, int m, uint64_t* s) {
     for (int i = 0; i < kSortItems; ++i) s[spad(t * kSortItems + i)] = x[i];
   }
   __syncthreads();
-  for (int j = t; j < m; j += kSortThreads) p[j] = s[spad(j)];
+  for (int j = t; j < m; j += kSortThreads) out[j] = s[spad(j)];
   __syncthreads();
 }
 
@@ -459,10 +460,16 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(RasterArgs a, int64_
   const int64_t beg = a.tile_off[seg];
   const int64_t n = a.tile_off[seg + 1] - beg;
   if (n <= 1) return;
-  uint64_t* src = a.keys + beg;
-  for (int64_t c0 = 0; c0 < n; c0 += kSortChunk) sort_chunk(src + c0, (int)(n - c0 < kSortChunk ? n - c0 : kSortChunk), s);
+  // the merge passes alternate between the keys and tmp; with an odd number of
+  // them the sorted chunks go to tmp, so that the last pass writes the keys
+  int passes = 0;
+  for (int64_t w = kSortChunk; w < n; w <<= 1) ++passes;
+  uint64_t* const keys = a.keys + beg;
+  uint64_t* src = (passes & 1) ? a.tmp + beg : keys;
+  for (int64_t c0 = 0; c0 < n; c0 += kSortChunk)
+    sort_chunk(keys + c0, src + c0, (int)(n - c0 < kSortChunk ? n - c0 : kSortChunk), s);
   if (n <= kSortChunk) return;
-  uint64_t* dst = a.tmp + beg;
+  uint64_t* dst = src == keys ? a.tmp + beg : keys;
   for (int64_t w = kSortChunk; w < n; w <<= 1) {
     for (int64_t s0 = 0; s0 < n; s0 += 2 * w) {
       const int64_t na = n - s0 < w ? n - s0 : w;
@@ -481,9 +488,6 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(RasterArgs a, int64_
     uint64_t* tswap = src;
     src = dst;
     dst = tswap;
-  }
-  if (src != a.keys + beg) {
-    for (int64_t i = threadIdx.x; i < n; i += kSortThreads) a.keys[beg + i] = src[i];
   }
 }
 
