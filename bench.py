@@ -41,10 +41,10 @@ FP32_VECTOR_UNPACKED_TFLOPS = 78.6        # what this build can reach: it never 
 # They describe the kernel sources they were measured on: with any other
 # source (hash below) or configuration the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "5f608e2c82e9f14c41980bb9cf6b4b6601f845ddf8bd70b69c8e0affc8c57362",
+    "sources_sha256": "024ff7e3edbf5280e81152d52124c63fa349d23c928092d79c763c7934047f04",
     "tile": [32, 16], "kbuf": 16,
-    "composite": (17977091456, 9171863360),
-    "bwd_grads": (9149229824, 9270458464),
+    "composite": (17993719552, 9169607488),
+    "bwd_grads": (9141888896, 9270458464),
 }
 
 
