@@ -29,7 +29,7 @@ import time
 
 from . import (MSP_LOSS_MSE, Refiner, RenderOptions, RenderState, adam_step, autotune, convert, convert_rings, loss,
                refiner_apply, refiner_apply_backward, refiner_features, refiner_loss, refiner_targets,
-               refiner_weights, render, render_backward, scenes)
+               refiner_weights, render, render_backward, scenes, spatial_order)
 from . import _lib
 from .finetune import FineTuneConfig, FineTuner
 
@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--ft-seed", type=int, default=0, help="scene seed of the time-to-MSE run (targets: seed + 1)")
     ap.add_argument("--ft-tile", type=int, nargs=2, default=(0, 0), help="tile w h (0 0: autotuned once)")
     ap.add_argument("--ft-kbuf", type=int, default=0, help="ordering-buffer depth (0: autotuned)")
+    ap.add_argument("--ft-order", choices=("morton", "input"), default="morton",
+                    help="storage order of the Gaussians for both runs (morton: along the Morton curve of the means)")
     ap.add_argument("--deterministic", action="store_true",
                     help="fixed-point gradient sums in the renders of training and fine-tuning (repeatable runs)")
     ap.add_argument("--skip-eval", action="store_true", help="no held-out evaluation after training")
@@ -389,6 +391,10 @@ def main():
         tgt = target_images(g, cams, args.ft_seed + 1, views_per_call=2)
         torch.cuda.synchronize()
         log(f"targets: {args.ft_views} views {args.ft_res[0]}x{args.ft_res[1]} in {time.perf_counter() - t:.1f} s")
+        if args.ft_order == "morton":
+            # scene preparation before both runs: neighbouring Gaussians (and so the faces
+            # of a binning workgroup) stored together; the targets above are unchanged
+            g = scenes.permuted(g, spatial_order(dict(mean=torch.from_numpy(g.mean).cuda())).cpu().numpy())
         # the same render options for both runs: fragment lists recomputed by the backward (the
         # workload's setting; --ft-list-rows > 0 stores them instead), the tile size and
         # ordering-buffer depth given or autotuned once on this scene and view set
@@ -406,6 +412,7 @@ def main():
         log(f"render options: tile {opts.tile_w}x{opts.tile_h}, ordering buffer {opts.kbuf}, "
             f"stored list rows {opts.list_rows} (0: recomputed), deterministic {det}")
         out = dict(n=args.ft_n, seed=args.ft_seed, views=args.ft_views, res=list(args.ft_res), steps=args.ft_steps,
+                   order=args.ft_order,
                    tile=[opts.tile_w, opts.tile_h], kbuf=opts.kbuf, list_rows=opts.list_rows, deterministic=det,
                    loss="0.6 L1 + 0.4 (1 - SSIM)", stop="image MSE of the render a step starts from")
         target = args.ft_target or None

@@ -120,6 +120,15 @@ def upstream_grad(n_views: int, height: int, width: int, seed: int, scale: float
     return _f32(rng.standard_normal(size=(n_views, 4, height, width)) * scale)
 
 
+def permuted(g: Gaussians, order) -> Gaussians:
+    """The same scene with its Gaussians stored in `order` (e.g. the Morton order
+    of their means), so that neighbouring Gaussians are near each other in
+    memory; images do not depend on the storage order."""
+    o = np.asarray(order, np.int64)
+    return Gaussians(mean=_f32(g.mean[:, o]), scale=_f32(g.scale[:, o]), quat=_f32(g.quat[:, o]),
+                     opacity=_f32(g.opacity[o]), rgb=_f32(g.rgb[:, o]), sh=None if g.sh is None else _f32(g.sh[:, o]))
+
+
 def perturbed(g: Gaussians, seed: int) -> Gaussians:
     """Seeded perturbation of a scene, used to make fine-tuning targets:
     m += N(0, (0.25 s_max)^2); log s += N(0, 0.1^2) (zero scales stay zero);
